@@ -1,0 +1,126 @@
+"""Oracle-side mapping from the dimensionless problem to lattice units.
+
+Test infrastructure only (see the package docstring).  Written from the
+paper's definitions:
+
+* lattice units dx = dt = c = 1, c_s^2 = 1/3 (Sec. IV parameter list);
+* dimensionless groups Ra, Pr, Da, J, lambda, sigma, H_v, Fo, St (Eq. 54);
+* rho_l = rho_s = 1, c_pl = c_ps = c_pm = 1, so the capacity ratio sigma
+  equals rho_m (Sec. IV parameter list);
+* viscosity <-> rate (Eq. 26 and the rate rule of Sec. III C);
+* thermal diffusivities <-> rates (Eq. A19 and the metal analogue after
+  Eq. 51), free rates of Sec. III C, Eq. (53) for zeta_e;
+* Forchheimer coefficient from the porosity, Eq. (4), unless given;
+* characteristic length L = nx - 1 (walls on the first and last node
+  columns; for the periodic-in-x channel, the distance between the two
+  horizontal walls, ny - 1), reference temperature T_0 = T_cold (Sec. IV B).
+"""
+from __future__ import annotations
+
+import math
+
+
+def char_length(p: dict) -> float:
+    """Distance between the two walls that carry the imposed temperature
+    difference (cavity) or the no-slip condition (periodic channel)."""
+    return float(p["ny"] - 1) if int(p["bc_x"]) == 1 else float(p["nx"] - 1)
+
+
+def stable_k_f(p: dict) -> float:
+    """Largest lattice PCM diffusivity keeping every thermal/viscous
+    relaxation time at or below 2 and the interstitial-exchange number
+    z = h_v dt (1/(phi rho_l c_pl) + 1/((1-phi) rho_m c_pm)) at or below 0.5.
+    """
+    phi = p["porosity"]
+    J = p["J"] if p["J"] > 0 else 1.0
+    c_fref = p["cf_ref"] if p["cf_ref"] > 0 else 0.2
+    c_mref = p["cm_ref"] if p["cm_ref"] > 0 else 1.0
+    rho_m = p["cap_ratio"]
+    lam = p["k_ratio"]
+    L = char_length(p)
+    dpL = p["dp_over_L"] if p["dp_over_L"] > 0 else 0.0135
+    d_p = dpL * L
+    limits = [0.5 / (J * p["Pr"]), 0.5 * c_fref, 0.5 * rho_m * c_mref / lam]
+    if p["Nu_i"] > 0:
+        limits.append(0.5 * d_p * d_p / (p["Nu_i"] * (1.0 / phi + 1.0 / ((1.0 - phi) * rho_m))))
+    return min(limits)
+
+
+def lattice_params(p: dict) -> dict:
+    """Map a problem description (see lbm_workloads.PARAM_FIELDS) to the
+    lattice constants the update uses.  Raises ValueError for parameter sets
+    the scheme cannot run."""
+    nx, ny = int(p["nx"]), int(p["ny"])
+    if nx < 4 or ny < 4:
+        raise ValueError("grid must be at least 4 x 4")
+    phi = float(p["porosity"])
+    if not 0.0 < phi < 1.0:
+        raise ValueError("porosity must lie in (0, 1)")
+    rho_l = 1.0
+    c_pl = c_ps = c_pm = 1.0
+    rho_m = float(p["cap_ratio"])
+    c_fref = p["cf_ref"] if p["cf_ref"] > 0 else 0.2 * c_pl
+    c_mref = p["cm_ref"] if p["cm_ref"] > 0 else 1.0 * c_pm
+    # Remark I: c_f,ref < 9/5 c_pf and c_m,ref < 9/5 c_pm.
+    if not c_fref < 1.8 * c_pl or not c_mref < 1.8 * c_pm:
+        raise ValueError("reference specific heats must stay below 9/5 of c_p (Remark I)")
+    J = p["J"] if p["J"] > 0 else 1.0
+    L = char_length(p)
+    dT = float(p["T_hot"]) - float(p["T_cold"])
+    if not dT > 0:
+        raise ValueError("T_hot must exceed T_cold")
+    k_f = p["k_f"] if p["k_f"] > 0 else stable_k_f(p)
+    alpha_f = k_f / (rho_l * c_pl)
+    nu_f = p["Pr"] * alpha_f
+    nu_e = J * nu_f
+    k_m = p["k_ratio"] * k_f
+    dpL = p["dp_over_L"] if p["dp_over_L"] > 0 else 0.0135
+    d_p = dpL * L
+    h_v = p["Nu_i"] * k_f / (d_p * d_p)
+    F_phi = p["F_phi"] if p["F_phi"] >= 0 else 1.75 / math.sqrt(150.0 * phi ** 3)
+    K = p["Da"] * L * L
+    if not K > 0:
+        raise ValueError("Da must be positive")
+    gbeta = p["Ra"] * nu_f * alpha_f / (dT * L ** 3)
+    if not p["Ste"] > 0:
+        raise ValueError("Ste must be positive")
+    L_a = c_pl * dT / p["Ste"]
+    T_fs, T_fl = float(p["T_solidus"]), float(p["T_liquidus"])
+    if not T_fl > T_fs:
+        raise ValueError("liquidus must lie above solidus")
+
+    # Eq. (26) / Sec. III C: s_v^-1 = 0.5 + nu_e / c_s^2.
+    s_v = 1.0 / (0.5 + 3.0 * nu_e)
+    # Eq. (A19): alpha_f,ref = k_f/(rho_l c_f,ref) = c_s^2 (1/zeta_alpha - 1/2).
+    alpha_fref = k_f / (rho_l * c_fref)
+    zeta_a = 1.0 / (0.5 + 3.0 * alpha_fref)
+    # After Eq. (51): alpha_m,ref = k_m/(rho_m c_m,ref) = c_s^2 (1/eta_alpha - 1/2).
+    alpha_mref = k_m / (rho_m * c_mref)
+    eta_a = 1.0 / (0.5 + 3.0 * alpha_mref)
+    # Sec. III C free rates; zeta_e = zeta_eps = 2 - zeta_alpha (Eq. 53);
+    # the conserved-moment rates zeta_0 and s_rho multiply zero and are 1.
+    s = [1.0, 1.1, 1.1, 1.0, 1.2, 1.0, 1.2, s_v, s_v]
+    zeta = [1.0, 2.0 - zeta_a, 2.0 - zeta_a, zeta_a, zeta_a, zeta_a, zeta_a, 1.2, 1.2]
+    eta = [1.0, 1.1, 1.1, eta_a, eta_a, eta_a, eta_a, 1.2, 1.2]
+    for name, r in (("s", s), ("zeta", zeta), ("eta", eta)):
+        if not all(0.0 < v < 2.0 for v in r):
+            raise ValueError(f"relaxation rates {name} must lie in (0, 2): {r}")
+    z = h_v * (1.0 / (phi * rho_l * c_pl) + 1.0 / ((1.0 - phi) * rho_m * c_pm))
+    if not z < 1.0:
+        raise ValueError(f"interstitial exchange number z = {z} >= 1 (explicit source unstable)")
+    return dict(
+        nx=nx, ny=ny, periodic_x=int(p["bc_x"]), gravity_axis=int(p["gravity_axis"]),
+        phi=phi, rho_l=rho_l, rho_m=rho_m, c_pl=c_pl, c_ps=c_ps, c_pm=c_pm,
+        c_fref=c_fref, c_mref=c_mref, nu_f=nu_f, nu_e=nu_e, K=K, F_phi=F_phi, gbeta=gbeta,
+        T0=float(p["T_cold"]), h_v=h_v, L_a=L_a, T_fs=T_fs, T_fl=T_fl,
+        H_fs=c_ps * T_fs, H_fl=c_pl * T_fl + L_a,
+        T_hot=float(p["T_hot"]), T_cold=float(p["T_cold"]),
+        k_f=k_f, k_m=k_m, L=L, alpha_f=alpha_f, d_p=d_p, z=z,
+        tau_v=1.0 / s_v, tau_g=1.0 / zeta_a, tau_h=1.0 / eta_a,
+        s=s, zeta=zeta, eta=eta,
+    )
+
+
+def steps_for_fourier(lp: dict, Fo: float) -> float:
+    """t = Fo L^2 / alpha_f (Eq. 54)."""
+    return Fo * lp["L"] ** 2 / lp["alpha_f"]
