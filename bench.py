@@ -1,0 +1,222 @@
+"""Throughput of the fused three-field MRT step on one MI355X.
+
+Prints one JSON line.  A step is one launch of the fused kernel over every
+node of the workload (default: the 8192 x 8192 cavity, Ra = 1e7, Da = 1e-5,
+phi = 0.9, Ste = 0.5, lambda = 1000, FP32 storage, 67.1 M nodes, 15 GB of
+double-buffered populations).  Inputs are resident in HBM before timing;
+the timed region is bracketed by HIP events on the stream the kernels run
+on.  MLUPS counts every node (walls included) advancing all 27 populations.
+
+Algorithmic HBM bytes per node and step: 27 populations read + 27 written
++ the previous-step source read + written: FP32 224 B, FP64 448 B, 16-bit
+offsets 116 B.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_NODE = {"f64": 448, "f32": 224, "f16": 116, "bf16": 116}
+PEAK_HBM_GBPS = 8000.0
+METRIC = "MLUPS (3 coupled MRT fields) + achieved HBM GB/s vs peak; FP16-store vs FP32"
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1701_00702_amd", "csrc", n)
+                  for n in ("lbm_kernels.hip", "lbm_internal.h")]
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str):
+    import lbm_workloads as W
+    if name == "c3":
+        p, _, seed, prec = W.case_c3()
+        return [p], seed, prec, "cavity 8192x8192 Ra=1e7 Da=1e-5 phi=0.9 Ste=0.5 lambda=1000 sigma=1 Nu_i=5"
+    if name == "c2":
+        p, _, seed, prec = W.case_c2()
+        return [p], seed, prec, "cavity 1024x1024 Ra=1e6 Da=1e-4 phi=0.95 Ste=1 lambda=100 Nu_i=10"
+    if name == "c4":
+        p, _, seed, prec = W.case_c4()
+        return [p], seed, prec, "cavity 4096x4096 Ra=1e6 Da=1e-4 phi=0.9 Ste=1 lambda=100 Nu_i=5"
+    if name == "c5":
+        ps, _, seed, prec = W.case_c5()
+        return ps, seed, prec, "256 cavities, sides log-U[64,512] (seed 7), 24198641 nodes"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_from_profile(sha: str, workload_name: str, precision: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if the summary
+    in profiles/ was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_kernel_{workload_name}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernel_sha:\s*(\w+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_b or m_sha.group(1) != sha:
+        return None
+    return float(m_b.group(1))
+
+
+def make_solver(lbm, torch, params, precision, stream):
+    nbytes = lbm.lbm_workspace_bytes(params, precision)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = (ws.data_ptr() + 255) // 256 * 256
+    s = lbm.Solver(params, precision, workspace=(base, nbytes), stream=stream.cuda_stream)
+    return s, ws
+
+
+def time_steps(lbm, torch, s, stream, steps, warmup, looped=False):
+    step = lbm.lbm_step_per_cavity if looped else lbm.lbm_step
+    step(s.h, warmup)
+    lbm.lbm_synchronize(s.h)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    step(s.h, steps)
+    e1.record(stream)
+    lbm.lbm_synchronize(s.h)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)  # ms
+
+
+def cpu_baseline(params, seed, budget_s=15.0):
+    """The FP64 checker on a 384 x 384 window of the same cavity (hot-wall
+    corner), OpenMP over rows on the host cores."""
+    import oracle
+    import lbm_workloads as W
+    p = params[0]
+    win = (0, 0, min(384, p["nx"]), min(384, p["ny"]))
+    d = W.perturbation(seed, win[3], win[2])
+    Tf = np.full((win[3], win[2]), p["T_init"])
+    Tf[1:, 1:] += d[1:, 1:]
+    Tm = np.full_like(Tf, p["T_init"])
+    o = oracle.Oracle(p, window=win)
+    o.set_initial(Tf, Tm)
+    t0 = time.perf_counter()
+    o.step(5)
+    t1 = time.perf_counter()
+    per = (t1 - t0) / 5
+    n = max(5, int(budget_s / max(per, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    nodes = win[2] * win[3]
+    return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{win[2]}x{win[3]} window at the hot-wall corner of the same cavity, "
+                      f"{n} steps, {dt:.1f} s, FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--precision", default=None, choices=[None, "f64", "f32", "f16", "bf16"])
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--npt", type=int, default=1)
+    ap.add_argument("--xcd", type=int, default=1)
+    ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--forms", action="store_true", help="also time the 16-bit and batched forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    from paper_1701_00702_amd import lbm
+    import lbm_workloads as W
+
+    params, seed, prec, desc = workload(args.workload)
+    prec = args.precision or prec
+    stream = torch.cuda.Stream()
+    s, ws = make_solver(lbm, torch, params, prec, stream)
+    for c, p in enumerate(params):
+        T_pcm, T_mf = W.initial_temperatures(p, seed + c if len(params) > 1 else seed)
+        s.set_initial(c, T_pcm, T_mf)
+    if args.autotune:
+        launch = lbm.lbm_autotune(s.h, 5, os.path.join(ROOT, "gpurun_out", "autotune_cache.txt"))
+    else:
+        lbm.lbm_set_launch(s.h, args.block, args.npt, args.xcd, args.persistent)
+        launch = lbm.lbm_get_launch(s.h)
+    nodes = sum(p["nx"] * p["ny"] for p in params)
+    ms = time_steps(lbm, torch, s, stream, args.steps, args.warmup)
+    d = s.diagnostics(0, allow_nonfinite=True)
+    ms_step = ms / args.steps
+    mlups = nodes / (ms_step * 1e-3) / 1e6
+    alg = BYTES_PER_NODE[prec] * nodes
+    achieved = alg / (ms_step * 1e-3) / 1e9
+    sha = kernel_sha()
+    traffic = traffic_from_profile(sha, args.workload, prec)
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": desc, "nodes": nodes, "storage": prec, "launch": launch,
+                   "seed": seed, "step_kernel": "lbm::step_kernel (fused pull-stream + NEE walls + 3 MRT collisions)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBPS,
+                     "traffic": None if traffic is None else traffic,
+                     "algorithmic_bytes_per_launch": alg, "kernel_sha": sha},
+        "check": {"nonfinite": d["nonfinite"], "liquid_fraction": d["liquid_fraction"],
+                  "energy_residual_rel": d["energy_residual"] / max(abs(d["E_int"]), 1e-300)},
+    }
+    s.close()
+    del ws
+    torch.cuda.empty_cache()
+
+    if args.forms:
+        forms = {}
+        for wl, pr in (("c4", "f16"), ("c4", "bf16"), ("c4", "f32")):
+            ps, sd, _, _ = workload(wl)
+            s2, ws2 = make_solver(lbm, torch, ps, pr, stream)
+            T_pcm, T_mf = W.initial_temperatures(ps[0], sd)
+            s2.set_initial(0, T_pcm, T_mf)
+            lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent)
+            n2 = ps[0]["nx"] * ps[0]["ny"]
+            t = time_steps(lbm, torch, s2, stream, 200, 10) / 200
+            forms[f"{wl}_{pr}"] = {"MLUPS": n2 / (t * 1e-3) / 1e6,
+                                   "alg_GBps": BYTES_PER_NODE[pr] * n2 / (t * 1e-3) / 1e9}
+            s2.close()
+            del ws2
+            torch.cuda.empty_cache()
+        ps, sd, _, _ = workload("c5")
+        s2, ws2 = make_solver(lbm, torch, ps, "f32", stream)
+        lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent)
+        n2 = sum(q["nx"] * q["ny"] for q in ps)
+        t1 = time_steps(lbm, torch, s2, stream, 200, 10) / 200
+        t2 = time_steps(lbm, torch, s2, stream, 50, 2, looped=True) / 50
+        forms["c5_batched_f32"] = {"MLUPS": n2 / (t1 * 1e-3) / 1e6,
+                                   "looped_single_cavity_MLUPS": n2 / (t2 * 1e-3) / 1e6}
+        s2.close()
+        del ws2
+        torch.cuda.empty_cache()
+        out["forms"] = forms
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(params, seed)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

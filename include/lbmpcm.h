@@ -1,0 +1,238 @@
+/*
+ * lbmpcm.h - C ABI of the MI355X (gfx950) library for the enthalpy-based
+ * multiple-relaxation-time lattice Boltzmann method for solid-liquid phase
+ * change in metal foams under local thermal non-equilibrium
+ * (Q. Liu, Y.-L. He, Q. Li, arXiv:1701.00702).
+ *
+ * One time step updates three coupled D2Q9 populations per node:
+ *   f  flow field with the Brinkman-Forchheimer (generalized non-Darcy) force
+ *      and the volumetric no-slip treatment of the solid phase (Sec. III A,
+ *      Eqs. 12-27);
+ *   g  PCM total enthalpy, with temperature and liquid fraction recovered
+ *      without iteration from the enthalpy (Sec. III B 1, Eqs. 28-40);
+ *   h  metal-foam internal energy (Sec. III B 2, Eqs. 41-49);
+ * coupled by the interstitial heat-exchange sources (Eqs. 36, 47) and closed
+ * by non-equilibrium extrapolation on the walls (Sec. III C, Eq. 52).
+ * The problem is the cavity of Sec. IV B: isothermal hot wall at x = 0, cold
+ * wall at x = nx-1, adiabatic horizontal walls, gravity along -y.
+ *
+ * Conventions shared by every entry point:
+ *  - Host field arrays are row-major double[ny][nx], x fastest, owned by the
+ *    caller.  Node (x, y) = (0, 0) is the bottom-left corner.
+ *  - All device memory is owned by the library, except after
+ *    lbm_create_ext, where the caller lends one device workspace.
+ *  - Work is queued on the handle's HIP stream.  lbm_step returns without
+ *    waiting; errors raised on the device surface at the next call that
+ *    synchronises (lbm_fields, lbm_diagnostics, lbm_synchronize, lbm_save).
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Every entry point returns an lbm_status; on failure a message is
+ *    available from lbm_last_error() (thread-local, valid until the next
+ *    failing call on the same thread).
+ */
+#ifndef LBMPCM_H
+#define LBMPCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_handle lbm_handle;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* bad argument or a parameter set the scheme cannot run */
+    LBM_ENOMEM = -2,     /* device or host allocation failed */
+    LBM_EDEVICE = -3,    /* a HIP call or kernel failed */
+    LBM_ENONFINITE = -4, /* the state holds NaN/Inf (reported by lbm_diagnostics) */
+    LBM_ESTATE = -5,     /* call not valid in the handle's current state */
+    LBM_EIO = -6         /* checkpoint file could not be written or read */
+} lbm_status;
+
+/* Storage of the 27 populations per node.  Arithmetic is FP64 for LBM_F64
+ * and FP32 otherwise.  The 16-bit forms store, per field, the offset of each
+ * population from the rest equilibrium at a fixed reference state (flow: the
+ * lattice weights times the reference density; enthalpy and metal fields:
+ * the equilibria at the middle of the mushy band), times a power-of-two scale. */
+typedef enum {
+    LBM_F64 = 0,
+    LBM_F32 = 1,
+    LBM_F16_OFFSET = 2,
+    LBM_BF16_OFFSET = 3
+} lbm_precision;
+
+/* Problem description in dimensionless groups (Eq. 54).  Lattice units:
+ * dx = dt = 1, c_s^2 = 1/3, rho_l = rho_s = 1, c_pl = c_ps = c_pm = 1
+ * (Sec. IV parameter list).  Optional fields use the stated sentinel. */
+typedef struct lbm_params {
+    int32_t nx, ny;       /* nodes including the wall nodes, each >= 4          */
+    int32_t bc_x;         /* 0: cavity (hot wall x=0, cold wall x=nx-1);
+                             1: periodic in x, walls only at y=0 and y=ny-1      */
+    int32_t gravity_axis; /* 1: gravity along -y; 0: along -x                    */
+    double porosity;      /* phi, in (0, 1)                                       */
+    double Ra, Pr, Da, Ste;
+    double k_ratio;       /* lambda = k_m / k_f                                   */
+    double cap_ratio;     /* sigma = (rho c_p)_m / (rho c_p)_f  (= rho_m here)    */
+    double Nu_i;          /* interstitial Nusselt number H_v = h_v d_p^2 / k_f    */
+    double F_phi;         /* Forchheimer coefficient; < 0: Eq. (4) from phi       */
+    double dp_over_L;     /* pore size d_p / L; <= 0: 0.0135                      */
+    double k_f;           /* lattice PCM diffusivity; <= 0: the largest value with
+                             every relaxation time <= 2 and the interstitial
+                             exchange number z <= 0.5                             */
+    double cf_ref;        /* c_f,ref; <= 0: 0.2 c_pl                              */
+    double cm_ref;        /* c_m,ref; <= 0: 1.0 c_pm                              */
+    double J;             /* viscosity ratio nu_e / nu_f; <= 0: 1                 */
+    double T_hot, T_cold; /* isothermal wall temperatures; T_0 = T_cold          */
+    double T_init;        /* initial temperature of both phases                   */
+    double T_solidus, T_liquidus;
+} lbm_params;
+
+/* Derived lattice constants of one cavity (read-only view). */
+typedef struct lbm_lattice {
+    double L;                        /* characteristic length nx-1 (channel: ny-1) */
+    double k_f, k_m, nu_f, nu_e, K, F_phi, gbeta, h_v, L_a, d_p, z;
+    double tau_v, tau_g, tau_h;
+    double s[9], zeta[9], eta[9];    /* relaxation rates in moment order of Eq. (13) */
+    double H_fs, H_fl, T_ref, H_ref;
+    double scale_exp[3];             /* storage scale exponents (f, g, h) */
+} lbm_lattice;
+
+/* Diagnostics of one cavity at the current step (all FP64).
+ * Walls are indexed 0 left (hot), 1 right (cold), 2 bottom, 3 top; corner
+ * nodes belong to the left/right walls.  Interior = non-wall nodes. */
+typedef struct lbm_diag {
+    double step, Fo;                  /* steps taken; Fo = t k_f / L^2          */
+    double liquid_fraction;           /* mean f_l over interior nodes           */
+    double Nu_hot;                    /* -(L/(k_e dT)) <phi k_f dT_f/dx + (1-phi) k_m dT_m/dx> at x=0 */
+    double Nu_hot_pcm;                /* -(L/dT) <dT_f/dx> at x=0               */
+    double Nu_cold;                   /* same at x = nx-1 (positive outflow)    */
+    double E_int, E_int0;             /* sum of phi rho_l H + (1-phi) rho_m c_pm T_m */
+    double flux_E[4];                 /* energy carried in through each wall since step 0 */
+    double energy_residual;           /* E_int - E_int0 - sum(flux_E)           */
+    double M_int, M_int0, flux_M[4], mass_residual; /* same for the density   */
+    double x_front_mid;               /* f_l = 0.5 crossing on row ny/2, / L    */
+    double max_dT_LTNE;               /* max |T_f - T_m| over interior nodes    */
+    double u_max;                     /* max |u| over interior nodes            */
+    double nonfinite;                 /* nodes holding a non-finite population  */
+} lbm_diag;
+
+/* Launch shape of the step kernel.  Every shape gives bit-identical results. */
+typedef struct lbm_launch_config {
+    int32_t block;            /* threads per workgroup: 64, 128, 256 or 512      */
+    int32_t nodes_per_thread; /* 1, 2 or 4 consecutive-by-block nodes per thread */
+    int32_t xcd_remap;        /* 1: consecutive tiles share an XCD (and its L2)  */
+    int32_t persistent;       /* 0: one tile per workgroup; >0: that many
+                                 workgroups per CU loop over all tiles           */
+} lbm_launch_config;
+
+/* Create a single-cavity solver.  Maps the groups to lattice units (Eq. 54,
+ * Eq. 26, Eq. A19, Sec. III C rates), validates them (rates in (0,2),
+ * interstitial exchange number < 1, Remark I bounds, phi in (0,1)), allocates
+ * the double-buffered state with hipMalloc and initialises every node at rest
+ * at T_init (isothermal walls at their temperature).  *out receives the
+ * handle, or NULL on failure. */
+lbm_status lbm_create(const lbm_params *p, lbm_precision prec, lbm_handle **out);
+
+/* Create a solver advancing n_cavities independent cavities (p[0..n-1]) in
+ * one launch per step over a packed node index. */
+lbm_status lbm_create_batch(const lbm_params *p, int32_t n_cavities, lbm_precision prec,
+                            lbm_handle **out);
+
+/* Device bytes lbm_create_ext needs for the same cavities and precision. */
+lbm_status lbm_workspace_bytes(const lbm_params *p, int32_t n_cavities, lbm_precision prec,
+                               uint64_t *bytes);
+
+/* As lbm_create_batch, but the caller lends a device workspace of at least
+ * lbm_workspace_bytes bytes (256-byte aligned) and a HIP stream
+ * (hipStream_t, may be NULL for the null stream).  The workspace must stay
+ * valid until lbm_destroy; the library never frees it. */
+lbm_status lbm_create_ext(const lbm_params *p, int32_t n_cavities, lbm_precision prec,
+                          void *workspace, uint64_t workspace_bytes, void *hip_stream,
+                          lbm_handle **out);
+
+/* Queue later work on another HIP stream (hipStream_t). */
+lbm_status lbm_set_stream(lbm_handle *h, void *hip_stream);
+
+/* Re-initialise one cavity (only before the first step): every node at rest
+ * with PCM temperature T_pcm0 and foam temperature T_mf0 (host double[ny][nx];
+ * either may be NULL for T_init); isothermal wall nodes take their wall
+ * temperature.  The previous-step interstitial source is set to the current
+ * one, so the time-derivative terms of Eqs. (36) and (47) start at zero. */
+lbm_status lbm_set_initial(lbm_handle *h, int32_t cavity, const double *T_pcm0,
+                           const double *T_mf0);
+
+/* Advance every cavity by n >= 0 steps (asynchronous).  Each step is one
+ * launch of the fused kernel: streaming, wall reconstruction (Eq. 52),
+ * enthalpy/temperature/liquid fraction (Eqs. 37-39, 48), volumetric blend
+ * (Eq. 20), velocity (Eqs. 23-25), the three moment-space collisions
+ * (Eqs. 14, 32, 43) and the wall energy/mass flux tallies. */
+lbm_status lbm_step(lbm_handle *h, int64_t n);
+
+/* Batched handles only: the same n steps as one launch per cavity per step
+ * (the reference point for the single-launch batched form). */
+lbm_status lbm_step_per_cavity(lbm_handle *h, int64_t n);
+
+/* Wait for all queued work on the handle's stream. */
+lbm_status lbm_synchronize(lbm_handle *h);
+
+/* Steps taken so far. */
+int64_t lbm_step_count(const lbm_handle *h);
+
+/* Macroscopic fields of one cavity at the current step, from the
+ * post-streaming populations: velocity u of Eq. (23), T_f and f_l of
+ * Eqs. (38)-(39), T_m of Eq. (48), density of Eq. (21).  Any pointer may be
+ * NULL.  Synchronises the stream. */
+lbm_status lbm_fields(lbm_handle *h, int32_t cavity, double *ux, double *uy, double *T_pcm,
+                      double *T_mf, double *f_l, double *rho);
+
+/* FP64 diagnostics of one cavity (deterministic reductions).  Returns
+ * LBM_ENONFINITE, with *out filled, when the state holds NaN/Inf. */
+lbm_status lbm_diagnostics(lbm_handle *h, int32_t cavity, lbm_diag *out);
+
+/* Derived lattice constants of one cavity. */
+lbm_status lbm_get_lattice(const lbm_handle *h, int32_t cavity, lbm_lattice *out);
+
+/* The same mapping and validation without a handle or a device (host only):
+ * what lbm_create would use for these parameters. */
+lbm_status lbm_lattice_of(const lbm_params *p, lbm_precision prec, lbm_lattice *out);
+
+/* Read or set the step kernel's launch shape. */
+lbm_status lbm_get_launch(const lbm_handle *h, lbm_launch_config *out);
+lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg);
+
+/* Time every supported launch shape for steps_per_trial steps on the live
+ * state (reads the current buffer, writes only scratch), keep the fastest,
+ * and report it in *chosen (may be NULL).  With a non-NULL cache_path the
+ * choice is looked up in / appended to that text file, keyed by device,
+ * precision and cavity sizes.  Synchronises the stream. */
+lbm_status lbm_autotune(lbm_handle *h, int32_t steps_per_trial, const char *cache_path,
+                        lbm_launch_config *chosen);
+
+/* Write / read the complete state (populations, previous-step sources,
+ * wall tallies, step count) to a file; resuming is bit-exact.  lbm_load
+ * requires a handle created with the same cavities and precision. */
+lbm_status lbm_save(lbm_handle *h, const char *path);
+lbm_status lbm_load(lbm_handle *h, const char *path);
+
+/* Copy the raw stored populations of one cavity to host memory, for
+ * bit-level comparisons: f, g, h each [9][ny][nx] in the storage type
+ * (8, 4 or 2 bytes per value), i.e. 27 * nx * ny * bytes in total. */
+lbm_status lbm_copy_state(lbm_handle *h, int32_t cavity, void *host, uint64_t bytes);
+
+/* Overwrite one stored population of the current state (test hook for the
+ * failure-detection path).  field: 0 f, 1 g, 2 h; dir: 0..8. */
+lbm_status lbm_debug_poke(lbm_handle *h, int32_t cavity, int32_t x, int32_t y, int32_t field,
+                          int32_t dir, double value);
+
+/* Release the handle and everything the library allocated for it. */
+lbm_status lbm_destroy(lbm_handle *h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMPCM_H */

@@ -1,0 +1,1018 @@
+// Host side of the C ABI declared in include/lbmpcm.h: mapping of the
+// dimensionless problem to lattice units, device buffers, launch shapes,
+// hipGraph replay of the step loop, autotuning, checkpoints and diagnostics.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmpcm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+
+static lbm_status fail(lbm_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(LBM_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),  \
+                        __FILE__, __LINE__);                                                 \
+    } while (0)
+
+extern "C" const char *lbm_last_error(void) { return g_err; }
+
+// ---------------------------------------------------------------------------
+// Parameter mapping (lattice units dx = dt = 1, c_s^2 = 1/3).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Lattice {
+    int nx, ny, periodic, gaxis;
+    double phi, rho_l, rho_m, c_pl, c_ps, c_pm, c_fref, c_mref;
+    double L, k_f, k_m, nu_f, nu_e, K, F_phi, gbeta, T0, h_v, L_a, d_p, z;
+    double T_fs, T_fl, H_fs, H_fl, T_ref, H_ref;
+    double T_hot, T_cold, T_init;
+    double s[9], zeta[9], eta[9];
+    int scale_exp[3];
+};
+
+double enthalpy_of(const Lattice &l, double T) {
+    // inverse of Eq. (38); a tie at the solidus is solid
+    if (T <= l.T_fs) return l.c_ps * T;
+    if (T >= l.T_fl) return l.c_pl * (T - l.T_fl) + l.H_fl;
+    return l.H_fs + (T - l.T_fs) / (l.T_fl - l.T_fs) * (l.H_fl - l.H_fs);
+}
+
+// Characteristic length: distance between the walls that carry the imposed
+// temperature difference; for the periodic channel, between the no-slip walls.
+double char_length(const lbm_params &p) { return p.bc_x == 1 ? p.ny - 1.0 : p.nx - 1.0; }
+
+lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
+    if (p.nx < 4 || p.ny < 4) return fail(LBM_EINVAL, "grid %dx%d: each side needs >= 4 nodes", p.nx, p.ny);
+    if ((int64_t)p.nx * p.ny > (int64_t)1 << 31)
+        return fail(LBM_EINVAL, "cavity of %dx%d nodes exceeds 2^31 nodes", p.nx, p.ny);
+    if (p.bc_x != 0 && p.bc_x != 1) return fail(LBM_EINVAL, "bc_x must be 0 or 1");
+    if (p.gravity_axis != 0 && p.gravity_axis != 1) return fail(LBM_EINVAL, "gravity_axis must be 0 or 1");
+    if (!(p.porosity > 0.0 && p.porosity < 1.0)) return fail(LBM_EINVAL, "porosity %g not in (0,1)", p.porosity);
+    if (!(p.cap_ratio > 0.0)) return fail(LBM_EINVAL, "cap_ratio must be positive");
+    if (!(p.k_ratio >= 0.0)) return fail(LBM_EINVAL, "k_ratio must be non-negative");
+    if (!(p.Pr > 0.0)) return fail(LBM_EINVAL, "Pr must be positive");
+    if (!(p.Ra >= 0.0)) return fail(LBM_EINVAL, "Ra must be non-negative");
+    if (!(p.Da > 0.0)) return fail(LBM_EINVAL, "Da must be positive");
+    if (!(p.Ste > 0.0)) return fail(LBM_EINVAL, "Ste must be positive");
+    if (!(p.Nu_i >= 0.0)) return fail(LBM_EINVAL, "Nu_i must be non-negative");
+    if (!(p.T_hot > p.T_cold)) return fail(LBM_EINVAL, "T_hot must exceed T_cold");
+    if (!(p.T_liquidus > p.T_solidus)) return fail(LBM_EINVAL, "T_liquidus must exceed T_solidus");
+    l.nx = p.nx;
+    l.ny = p.ny;
+    l.periodic = p.bc_x;
+    l.gaxis = p.gravity_axis;
+    l.phi = p.porosity;
+    l.rho_l = 1.0;
+    l.c_pl = l.c_ps = l.c_pm = 1.0;
+    l.rho_m = p.cap_ratio;  // (rho c_p)_m / (rho c_p)_f with unit c_p and rho_l
+    l.c_fref = p.cf_ref > 0 ? p.cf_ref : 0.2 * l.c_pl;
+    l.c_mref = p.cm_ref > 0 ? p.cm_ref : 1.0 * l.c_pm;
+    if (!(l.c_fref < 1.8 * l.c_pl) || !(l.c_mref < 1.8 * l.c_pm))
+        return fail(LBM_EINVAL, "reference specific heats must stay below 9/5 c_p (Remark I)");
+    const double J = p.J > 0 ? p.J : 1.0;
+    l.L = char_length(p);
+    const double dpL = p.dp_over_L > 0 ? p.dp_over_L : 0.0135;
+    l.d_p = dpL * l.L;
+    double kf = p.k_f;
+    if (!(kf > 0)) {
+        // largest k_f with tau_v, tau_g, tau_h <= 2 and z <= 0.5
+        kf = 0.5 / (J * p.Pr);
+        kf = std::min(kf, 0.5 * l.rho_l * l.c_fref);
+        if (p.k_ratio > 0) kf = std::min(kf, 0.5 * l.rho_m * l.c_mref / p.k_ratio);
+        if (p.Nu_i > 0)
+            kf = std::min(kf, 0.5 * l.d_p * l.d_p /
+                                  (p.Nu_i * (1.0 / (l.phi * l.rho_l * l.c_pl) +
+                                             1.0 / ((1.0 - l.phi) * l.rho_m * l.c_pm))));
+    }
+    l.k_f = kf;
+    const double alpha_f = kf / (l.rho_l * l.c_pl);
+    l.nu_f = p.Pr * alpha_f;
+    l.nu_e = J * l.nu_f;
+    l.k_m = p.k_ratio * kf;
+    l.h_v = p.Nu_i * kf / (l.d_p * l.d_p);
+    l.F_phi = p.F_phi >= 0 ? p.F_phi : 1.75 / std::sqrt(150.0 * l.phi * l.phi * l.phi);
+    l.K = p.Da * l.L * l.L;
+    const double dT = p.T_hot - p.T_cold;
+    l.gbeta = p.Ra * l.nu_f * alpha_f / (dT * l.L * l.L * l.L);
+    l.T0 = p.T_cold;
+    l.L_a = l.c_pl * dT / p.Ste;
+    l.T_fs = p.T_solidus;
+    l.T_fl = p.T_liquidus;
+    l.H_fs = l.c_ps * l.T_fs;
+    l.H_fl = l.c_pl * l.T_fl + l.L_a;
+    l.T_ref = 0.5 * (l.T_fs + l.T_fl);
+    l.H_ref = 0.5 * (l.H_fs + l.H_fl);
+    l.T_hot = p.T_hot;
+    l.T_cold = p.T_cold;
+    l.T_init = p.T_init;
+    // relaxation rates: s_v from nu_e (Eq. 26); zeta_alpha, eta_alpha from the
+    // reference diffusivities (Eq. A19 and after Eq. 51); free rates and
+    // zeta_e = zeta_eps = 2 - zeta_alpha (Sec. III C, Eq. 53)
+    const double s_v = 1.0 / (0.5 + 3.0 * l.nu_e);
+    const double za = 1.0 / (0.5 + 3.0 * kf / (l.rho_l * l.c_fref));
+    const double ea = 1.0 / (0.5 + 3.0 * l.k_m / (l.rho_m * l.c_mref));
+    const double s[9] = {1.0, 1.1, 1.1, 1.0, 1.2, 1.0, 1.2, s_v, s_v};
+    const double zt[9] = {1.0, 2.0 - za, 2.0 - za, za, za, za, za, 1.2, 1.2};
+    const double et[9] = {1.0, 1.1, 1.1, ea, ea, ea, ea, 1.2, 1.2};
+    for (int k = 0; k < 9; ++k) {
+        l.s[k] = s[k];
+        l.zeta[k] = zt[k];
+        l.eta[k] = et[k];
+        if (!(s[k] > 0 && s[k] < 2) || !(zt[k] > 0 && zt[k] < 2) || !(et[k] > 0 && et[k] < 2))
+            return fail(LBM_EINVAL, "relaxation rate outside (0,2): s_v=%g zeta_a=%g eta_a=%g", s_v, za, ea);
+    }
+    l.z = l.h_v * (1.0 / (l.phi * l.rho_l * l.c_pl) + 1.0 / ((1.0 - l.phi) * l.rho_m * l.c_pm));
+    if (!(l.z < 1.0))
+        return fail(LBM_EINVAL, "interstitial exchange number z = %g >= 1: explicit source unstable", l.z);
+    // storage scales (16-bit forms): keep the largest expected offset near 2^14
+    l.scale_exp[0] = l.scale_exp[1] = l.scale_exp[2] = 0;
+    if (prec == LBM_F16_OFFSET) {
+        double span_g = 1.0, span_h = 1.0;
+        const double Ts[3] = {p.T_hot, p.T_cold, p.T_init};
+        for (double T : Ts) {
+            span_g = std::max(span_g, std::fabs(enthalpy_of(l, T) - l.H_ref) + std::fabs(T - l.T_ref));
+            span_h = std::max(span_h, std::fabs(T - l.T_ref) * l.c_pm);
+        }
+        l.scale_exp[0] = 16;
+        l.scale_exp[1] = std::max(0, std::min(14, (int)std::floor(std::log2(16384.0 / span_g))));
+        l.scale_exp[2] = std::max(0, std::min(14, (int)std::floor(std::log2(16384.0 / span_h))));
+    }
+    return LBM_OK;
+}
+
+template <typename R>
+CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
+    CavityConst<R> c;
+    std::memset(&c, 0, sizeof(c));
+    c.nx = l.nx;
+    c.ny = l.ny;
+    c.periodic = l.periodic;
+    c.gaxis = l.gaxis;
+    c.node0 = node0;
+    c.acc0 = acc0;
+    c.phi = (R)l.phi;
+    c.inv_phi = (R)(1.0 / l.phi);
+    c.inv_cpm = (R)(1.0 / l.c_pm);
+    c.inv_cps = (R)(1.0 / l.c_ps);
+    c.inv_cpl = (R)(1.0 / l.c_pl);
+    c.c_pl = (R)l.c_pl;
+    c.c_pm = (R)l.c_pm;
+    c.c_fref = (R)l.c_fref;
+    c.c_mref = (R)l.c_mref;
+    for (int k = 0; k < 9; ++k) {
+        c.s[k] = (R)l.s[k];
+        c.s_half[k] = (R)(1.0 - 0.5 * l.s[k]);
+        c.zeta[k] = (R)l.zeta[k];
+        c.eta[k] = (R)l.eta[k];
+    }
+    c.gbeta = (R)l.gbeta;
+    c.T0 = (R)l.T0;
+    const double dl = l.phi * l.nu_f / l.K;             // phi nu_f / K
+    const double dq = l.phi * l.F_phi / std::sqrt(l.K);  // phi F_phi / sqrt(K)
+    c.drag_lin = (R)dl;
+    c.drag_quad = (R)dq;
+    const double l0 = 0.5 * (1.0 + 0.5 * dl);          // Eq. (25)
+    c.l0 = (R)l0;
+    c.l0sq = (R)(l0 * l0);
+    c.l1 = (R)(0.5 * dq);
+    const double hvf = l.h_v / (l.phi * l.rho_l), hvm = l.h_v / ((1.0 - l.phi) * l.rho_m);
+    c.hv_f = (R)hvf;
+    c.hv_m = (R)hvm;
+    c.sr_ratio = (R)((l.phi * l.rho_l) / ((1.0 - l.phi) * l.rho_m));
+    c.H_fs = (R)l.H_fs;
+    c.H_fl = (R)l.H_fl;
+    c.T_fs = (R)l.T_fs;
+    c.T_fl = (R)l.T_fl;
+    c.inv_dH = (R)(1.0 / (l.H_fl - l.H_fs));
+    c.dT_band = (R)(l.T_fl - l.T_fs);
+    c.T_ref = (R)l.T_ref;
+    c.H_ref = (R)l.H_ref;
+    c.T_hot = (R)l.T_hot;
+    c.T_cold = (R)l.T_cold;
+    c.H_hot = (R)enthalpy_of(l, l.T_hot);
+    c.H_cold = (R)enthalpy_of(l, l.T_cold);
+    for (int f = 0; f < 3; ++f) {
+        c.scale[f] = (R)std::ldexp(1.0, l.scale_exp[f]);
+        c.inv_scale[f] = (R)std::ldexp(1.0, -l.scale_exp[f]);
+    }
+    c.we = l.phi * l.rho_l;
+    c.wm = (1.0 - l.phi) * l.rho_m;
+    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    for (int i = 0; i < 9; ++i) {
+        c.g_ref[i] = i == 0 ? l.H_ref - 5.0 / 9.0 * l.c_fref * l.T_ref : w[i] * l.c_fref * l.T_ref;
+        c.h_ref[i] = i == 0 ? (l.c_pm - 5.0 / 9.0 * l.c_mref) * l.T_ref : w[i] * l.c_mref * l.T_ref;
+    }
+    c.T_init = l.T_init;
+    return c;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int storage_of(lbm_precision p) {
+    switch (p) {
+        case LBM_F64: return ST_F64;
+        case LBM_F32: return ST_F32;
+        case LBM_F16_OFFSET: return ST_F16;
+        case LBM_BF16_OFFSET: return ST_BF16;
+    }
+    return -1;
+}
+
+size_t elem_size(int st) { return st == ST_F64 ? 8 : (st == ST_F32 ? 4 : 2); }
+size_t real_size(int st) { return st == ST_F64 ? 8 : 4; }
+
+// Memory plan shared by lbm_workspace_bytes and the create calls.
+struct Plan {
+    std::vector<Lattice> lat;
+    std::vector<int64_t> node0, acc0;
+    int64_t nodes = 0, stride = 0, slots = 0, max_nodes = 0;
+    int max_tiles = 0;
+    size_t off_pop[2], off_sr[2], off_acc, off_accs, off_cav, off_tiles, off_fields, off_part,
+        off_out, total;
+};
+
+lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (n < 1) return fail(LBM_EINVAL, "need at least one cavity");
+    if (storage_of(prec) < 0) return fail(LBM_EINVAL, "unknown precision %d", (int)prec);
+    const int st = storage_of(prec);
+    pl.lat.resize(n);
+    int64_t tiles = 0;
+    for (int c = 0; c < n; ++c) {
+        lbm_status s = map_params(p[c], prec, pl.lat[c]);
+        if (s != LBM_OK) {
+            char buf[512];
+            snprintf(buf, sizeof(buf), "cavity %d: %s", c, g_err);
+            return fail(s, "%s", buf);
+        }
+        pl.node0.push_back(pl.nodes);
+        pl.acc0.push_back(pl.slots);
+        const int64_t nn = (int64_t)p[c].nx * p[c].ny;
+        pl.nodes += nn;
+        pl.slots += 2 * ((int64_t)p[c].nx + p[c].ny);
+        pl.max_nodes = std::max(pl.max_nodes, nn);
+        tiles += (int64_t)p[c].ny * ((p[c].nx + 63) / 64);
+    }
+    if (pl.nodes >= ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "more than 2^31 nodes in total");
+    if (tiles >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
+    pl.max_tiles = (int)tiles;
+    pl.stride = (pl.nodes + 127) & ~(int64_t)127;
+    size_t off = 0;
+    for (int b = 0; b < 2; ++b) {
+        pl.off_pop[b] = off;
+        off = align256(off + (size_t)27 * pl.stride * elem_size(st));
+    }
+    for (int b = 0; b < 2; ++b) {
+        pl.off_sr[b] = off;
+        off = align256(off + (size_t)pl.stride * real_size(st));
+    }
+    pl.off_acc = off;
+    off = align256(off + (size_t)pl.slots * 2 * sizeof(double));
+    pl.off_accs = off;
+    off = align256(off + (size_t)pl.slots * 2 * sizeof(double));
+    pl.off_cav = off;
+    off = align256(off + (size_t)n * std::max(sizeof(CavityConst<double>), sizeof(CavityConst<float>)));
+    pl.off_tiles = off;
+    off = align256(off + (size_t)pl.max_tiles * sizeof(Tile));
+    pl.off_fields = off;
+    off = align256(off + (size_t)6 * pl.max_nodes * sizeof(double));
+    pl.off_part = off;
+    off = align256(off + (size_t)macro_blocks((int)std::min<int64_t>(pl.max_nodes, INT32_MAX), 1) * NPART * sizeof(double) +
+                   (size_t)NPART * sizeof(double) * 64);
+    pl.off_out = off;
+    off = align256(off + 64 * sizeof(double));
+    pl.total = off;
+    return LBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct lbm_handle {
+    Plan pl;
+    lbm_precision prec;
+    int st;
+    int n;
+    std::vector<lbm_params> params;
+    char *ws = nullptr;
+    bool owns_ws = false;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    hipStream_t cap = nullptr;
+    int device = 0;
+    int n_cu = 256;
+    int cur = 0;
+    int64_t step = 0;
+    std::vector<double> E0, M0;
+    lbm_launch_config lc{256, 1, 1, 0};
+    std::vector<Tile> tiles;             // host copy, sorted by cavity, row, x
+    std::vector<int> cav_tile0, cav_ntiles;
+    int graph_chunk = 32;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraph_t gsrc[2] = {nullptr, nullptr};
+
+    void *pop(int b) { return ws + pl.off_pop[b]; }
+    void *sr(int b) { return ws + pl.off_sr[b]; }
+    double *acc() { return (double *)(ws + pl.off_acc); }
+    double *acc_scratch() { return (double *)(ws + pl.off_accs); }
+    void *cav() { return ws + pl.off_cav; }
+    Tile *dtiles() { return (Tile *)(ws + pl.off_tiles); }
+    double *fields() { return (double *)(ws + pl.off_fields); }
+    double *partials() { return (double *)(ws + pl.off_part); }
+    double *dout() { return (double *)(ws + pl.off_out); }
+};
+
+namespace {
+
+void drop_graphs(lbm_handle *h) {
+    for (int b = 0; b < 2; ++b) {
+        if (h->graph[b]) (void)hipGraphExecDestroy(h->graph[b]);
+        if (h->gsrc[b]) (void)hipGraphDestroy(h->gsrc[b]);
+        h->graph[b] = nullptr;
+        h->gsrc[b] = nullptr;
+    }
+}
+
+lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
+    const int tw = lc.block * lc.nodes_per_thread;
+    h->tiles.clear();
+    h->cav_tile0.assign(h->n, 0);
+    h->cav_ntiles.assign(h->n, 0);
+    for (int c = 0; c < h->n; ++c) {
+        h->cav_tile0[c] = (int)h->tiles.size();
+        const int nx = h->params[c].nx, ny = h->params[c].ny;
+        for (int y = 0; y < ny; ++y)
+            for (int x0 = 0; x0 < nx; x0 += tw) h->tiles.push_back(Tile{c, y, x0, std::min(nx, x0 + tw)});
+        h->cav_ntiles[c] = (int)h->tiles.size() - h->cav_tile0[c];
+    }
+    if ((int)h->tiles.size() > h->pl.max_tiles) return fail(LBM_EINVAL, "tile table overflow");
+    HIP_TRY(hipMemcpyAsync(h->dtiles(), h->tiles.data(), h->tiles.size() * sizeof(Tile),
+                           hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+bool valid_launch(const lbm_launch_config &lc) {
+    const bool b = lc.block == 64 || lc.block == 128 || lc.block == 256 || lc.block == 512;
+    const bool n = lc.nodes_per_thread == 1 || lc.nodes_per_thread == 2 || lc.nodes_per_thread == 4;
+    return b && n && (lc.xcd_remap == 0 || lc.xcd_remap == 1) && lc.persistent >= 0 && lc.persistent <= 64;
+}
+
+StepLaunch step_args(lbm_handle *h, int pull, int src_buf, double *acc, int tile0, int ntiles,
+                     const lbm_launch_config &lc) {
+    StepLaunch L;
+    L.storage = h->st;
+    L.block = lc.block;
+    L.npt = lc.nodes_per_thread;
+    L.xcd_remap = lc.xcd_remap;
+    L.grid = lc.persistent > 0 ? std::min(ntiles, h->n_cu * lc.persistent) : ntiles;
+    L.pull = pull;
+    L.src = h->pop(src_buf);
+    L.dst = h->pop(1 - src_buf);
+    L.plane_stride = h->pl.stride;
+    L.sr_src = h->sr(src_buf);
+    L.sr_dst = h->sr(1 - src_buf);
+    L.acc = acc;
+    L.cav = h->cav();
+    L.tiles = h->dtiles() + tile0;
+    L.ntiles = ntiles;
+    return L;
+}
+
+lbm_status launch_one(lbm_handle *h, hipStream_t s, int pull, int src_buf) {
+    StepLaunch L = step_args(h, pull, src_buf, h->acc(), 0, (int)h->tiles.size(), h->lc);
+    HIP_TRY(launch_step(L, s));
+    return LBM_OK;
+}
+
+lbm_status build_graph(lbm_handle *h, int parity) {
+    if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    int b = parity;
+    for (int k = 0; k < h->graph_chunk; ++k) {
+        StepLaunch L = step_args(h, 1, b, h->acc(), 0, (int)h->tiles.size(), h->lc);
+        hipError_t e = launch_step(L, h->cap);
+        if (e != hipSuccess) {
+            hipGraph_t g;
+            (void)hipStreamEndCapture(h->cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            return fail(LBM_EDEVICE, "kernel launch during capture failed: %s", hipGetErrorString(e));
+        }
+        b ^= 1;
+    }
+    HIP_TRY(hipStreamEndCapture(h->cap, &h->gsrc[parity]));
+    HIP_TRY(hipGraphInstantiate(&h->graph[parity], h->gsrc[parity], nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+// Run the diagnostics kernels for cavity c; results land in h->dout() and
+// the six field planes in h->fields().
+lbm_status run_macro(lbm_handle *h, int c, bool with_diag) {
+    const lbm_params &p = h->params[c];
+    MacroLaunch M;
+    M.storage = h->st;
+    M.raw = h->step == 0 ? 1 : 0;
+    M.cav_index = c;
+    M.src = h->pop(h->cur);
+    M.plane_stride = h->pl.stride;
+    M.cav = h->cav();
+    M.fields = h->fields();
+    M.partials = h->partials();
+    M.nblocks = macro_blocks(p.nx, p.ny);
+    HIP_TRY(launch_macro(M, p.nx, p.ny, h->stream));
+    if (with_diag) {
+        const Lattice &l = h->pl.lat[c];
+        DiagLaunch D;
+        D.nx = p.nx;
+        D.ny = p.ny;
+        D.periodic = p.bc_x;
+        D.acc0 = h->pl.acc0[c];
+        D.fields = h->fields();
+        D.partials = h->partials();
+        D.nblocks = M.nblocks;
+        D.acc = h->acc();
+        D.out = h->dout();
+        D.L = l.L;
+        D.kf = l.phi * l.k_f;
+        D.km = (1.0 - l.phi) * l.k_m;
+        D.ke = D.kf + D.km;
+        D.dT = l.T_hot - l.T_cold;
+        HIP_TRY(launch_diag(D, p.nx, p.ny, h->stream));
+    }
+    return LBM_OK;
+}
+
+lbm_status read_diag(lbm_handle *h, int c, double out[NDIAG]) {
+    lbm_status s = run_macro(h, c, true);
+    if (s != LBM_OK) return s;
+    HIP_TRY(hipMemcpyAsync(out, h->dout(), NDIAG * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+lbm_status init_cavity(lbm_handle *h, int c, const double *T_pcm, const double *T_mf) {
+    const lbm_params &p = h->params[c];
+    const int64_t nn = (int64_t)p.nx * p.ny;
+    double *dT = h->fields();  // staging for the temperature arrays
+    if (T_pcm) HIP_TRY(hipMemcpyAsync(dT, T_pcm, nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    if (T_mf) HIP_TRY(hipMemcpyAsync(dT + nn, T_mf, nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    InitLaunch I;
+    I.storage = h->st;
+    I.cav_index = c;
+    I.cav = h->cav();
+    I.dst = h->pop(h->cur);
+    I.plane_stride = h->pl.stride;
+    I.sr = h->sr(h->cur);
+    I.T_pcm = T_pcm ? dT : nullptr;
+    I.T_mf = T_mf ? dT + nn : nullptr;
+    HIP_TRY(launch_init(I, p.nx, p.ny, h->stream));
+    const int64_t a0 = h->pl.acc0[c], ns = 2 * ((int64_t)p.nx + p.ny);
+    HIP_TRY(hipMemsetAsync(h->acc() + 2 * a0, 0, ns * 2 * sizeof(double), h->stream));
+    double d[NDIAG];
+    lbm_status s = read_diag(h, c, d);
+    if (s != LBM_OK) return s;
+    h->E0[c] = d[D_E];
+    h->M0[c] = d[D_M];
+    return LBM_OK;
+}
+
+lbm_status setup(lbm_handle *h) {
+    HIP_TRY(hipGetDevice(&h->device));
+    int ncu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+    h->n_cu = ncu > 0 ? ncu : 256;
+    HIP_TRY(hipMemsetAsync(h->ws, 0, h->pl.total, h->stream));
+    // cavity table
+    std::vector<char> tab;
+    if (h->st == ST_F64) {
+        std::vector<CavityConst<double>> t;
+        for (int c = 0; c < h->n; ++c) t.push_back(make_const<double>(h->pl.lat[c], h->pl.node0[c], h->pl.acc0[c]));
+        HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<CavityConst<float>> t;
+        for (int c = 0; c < h->n; ++c) t.push_back(make_const<float>(h->pl.lat[c], h->pl.node0[c], h->pl.acc0[c]));
+        HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    lbm_status s = build_tiles(h, h->lc);
+    if (s != LBM_OK) return s;
+    h->E0.assign(h->n, 0.0);
+    h->M0.assign(h->n, 0.0);
+    for (int c = 0; c < h->n; ++c) {
+        s = init_cavity(h, c, nullptr, nullptr);
+        if (s != LBM_OK) return s;
+    }
+    return LBM_OK;
+}
+
+lbm_status create_common(const lbm_params *p, int n, lbm_precision prec, void *ws, uint64_t ws_bytes,
+                         void *stream, bool ext, lbm_handle **out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    lbm_handle *h = new lbm_handle();
+    lbm_status s = make_plan(p, n, prec, h->pl);
+    if (s != LBM_OK) {
+        delete h;
+        return s;
+    }
+    h->prec = prec;
+    h->st = storage_of(prec);
+    h->n = n;
+    h->params.assign(p, p + n);
+    h->stream = (hipStream_t)stream;
+    if (ext) {
+        if (!ws) {
+            delete h;
+            return fail(LBM_EINVAL, "workspace is NULL");
+        }
+        if (ws_bytes < h->pl.total) {
+            delete h;
+            return fail(LBM_EINVAL, "workspace of %llu bytes is smaller than the %llu needed",
+                        (unsigned long long)ws_bytes, (unsigned long long)h->pl.total);
+        }
+        if (((uintptr_t)ws) & 255) {
+            delete h;
+            return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+        }
+        h->ws = (char *)ws;
+    } else {
+        hipError_t e = hipMalloc((void **)&h->ws, h->pl.total);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(LBM_ENOMEM, "hipMalloc of %llu bytes failed: %s", (unsigned long long)h->pl.total,
+                        hipGetErrorString(e));
+        }
+        h->owns_ws = true;
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            (void)hipFree(h->ws);
+            delete h;
+            return fail(LBM_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+        }
+        h->owns_stream = true;
+    }
+    s = setup(h);
+    if (s != LBM_OK) {
+        std::string msg = g_err;
+        lbm_destroy(h);
+        return fail(s, "%s", msg.c_str());
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" lbm_status lbm_workspace_bytes(const lbm_params *p, int32_t n, lbm_precision prec,
+                                          uint64_t *bytes) {
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    Plan pl;
+    lbm_status s = make_plan(p, n, prec, pl);
+    if (s != LBM_OK) return s;
+    *bytes = pl.total;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_create(const lbm_params *p, lbm_precision prec, lbm_handle **out) {
+    return create_common(p, 1, prec, nullptr, 0, nullptr, false, out);
+}
+
+extern "C" lbm_status lbm_create_batch(const lbm_params *p, int32_t n, lbm_precision prec,
+                                       lbm_handle **out) {
+    return create_common(p, n, prec, nullptr, 0, nullptr, false, out);
+}
+
+extern "C" lbm_status lbm_create_ext(const lbm_params *p, int32_t n, lbm_precision prec, void *ws,
+                                     uint64_t ws_bytes, void *stream, lbm_handle **out) {
+    return create_common(p, n, prec, ws, ws_bytes, stream, true, out);
+}
+
+extern "C" lbm_status lbm_destroy(lbm_handle *h) {
+    if (!h) return LBM_OK;
+    (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    if (h->owns_ws && h->ws) (void)hipFree(h->ws);
+    delete h;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_stream(lbm_handle *h, void *stream) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->owns_stream && h->stream) HIP_TRY(hipStreamDestroy(h->stream));
+    h->owns_stream = false;  // the caller's stream is never destroyed here
+    h->stream = (hipStream_t)stream;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_initial(lbm_handle *h, int32_t c, const double *T_pcm, const double *T_mf) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    if (h->step != 0) return fail(LBM_ESTATE, "initial state can only be set before the first step");
+    return init_cavity(h, c, T_pcm, T_mf);
+}
+
+extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "negative step count");
+    if (n == 0) return LBM_OK;
+    if (h->step == 0) {
+        lbm_status s = launch_one(h, h->stream, 0, h->cur);
+        if (s != LBM_OK) return s;
+        h->cur ^= 1;
+        h->step += 1;
+        n -= 1;
+    }
+    while (n >= h->graph_chunk && h->graph_chunk > 0) {
+        if (!h->graph[h->cur]) {
+            lbm_status s = build_graph(h, h->cur);
+            if (s != LBM_OK) return s;
+        }
+        HIP_TRY(hipGraphLaunch(h->graph[h->cur], h->stream));
+        h->step += h->graph_chunk;
+        n -= h->graph_chunk;
+    }
+    for (; n > 0; --n) {
+        lbm_status s = launch_one(h, h->stream, 1, h->cur);
+        if (s != LBM_OK) return s;
+        h->cur ^= 1;
+        h->step += 1;
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step_per_cavity(lbm_handle *h, int64_t n) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "negative step count");
+    for (int64_t k = 0; k < n; ++k) {
+        const int pull = h->step == 0 ? 0 : 1;
+        for (int c = 0; c < h->n; ++c) {
+            StepLaunch L = step_args(h, pull, h->cur, h->acc(), h->cav_tile0[c], h->cav_ntiles[c], h->lc);
+            HIP_TRY(launch_step(L, h->stream));
+        }
+        h->cur ^= 1;
+        h->step += 1;
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_synchronize(lbm_handle *h) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int64_t lbm_step_count(const lbm_handle *h) { return h ? h->step : -1; }
+
+extern "C" lbm_status lbm_fields(lbm_handle *h, int32_t c, double *ux, double *uy, double *T_pcm,
+                                 double *T_mf, double *f_l, double *rho) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    lbm_status s = run_macro(h, c, false);
+    if (s != LBM_OK) return s;
+    const int64_t nn = (int64_t)h->params[c].nx * h->params[c].ny;
+    double *outs[6] = {ux, uy, T_pcm, T_mf, f_l, rho};
+    for (int k = 0; k < 6; ++k)
+        if (outs[k])
+            HIP_TRY(hipMemcpyAsync(outs[k], h->fields() + k * nn, nn * sizeof(double), hipMemcpyDeviceToHost,
+                                   h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_diagnostics(lbm_handle *h, int32_t c, lbm_diag *out) {
+    if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    double d[NDIAG];
+    lbm_status s = read_diag(h, c, d);
+    if (s != LBM_OK) return s;
+    const Lattice &l = h->pl.lat[c];
+    std::memset(out, 0, sizeof(*out));
+    out->step = (double)h->step;
+    out->Fo = (double)h->step * (l.k_f / (l.rho_l * l.c_pl)) / (l.L * l.L);
+    out->liquid_fraction = d[D_FL];
+    out->Nu_hot = d[D_NUH];
+    out->Nu_hot_pcm = d[D_NUHP];
+    out->Nu_cold = d[D_NUC];
+    out->E_int = d[D_E];
+    out->E_int0 = h->E0[c];
+    out->M_int = d[D_M];
+    out->M_int0 = h->M0[c];
+    double sE = 0, sM = 0;
+    for (int w = 0; w < 4; ++w) {
+        out->flux_E[w] = d[D_FLUXE + w];
+        out->flux_M[w] = d[D_FLUXM + w];
+        sE += d[D_FLUXE + w];
+        sM += d[D_FLUXM + w];
+    }
+    out->energy_residual = out->E_int - out->E_int0 - sE;
+    out->mass_residual = out->M_int - out->M_int0 - sM;
+    out->x_front_mid = d[D_FRONT];
+    out->max_dT_LTNE = d[D_DT];
+    out->u_max = d[D_U];
+    out->nonfinite = d[D_NF];
+    if (d[D_NF] > 0) return fail(LBM_ENONFINITE, "cavity %d holds %g nodes with non-finite populations", c, d[D_NF]);
+    return LBM_OK;
+}
+
+namespace {
+void fill_lattice(const Lattice &l, lbm_lattice *out) {
+    std::memset(out, 0, sizeof(*out));
+    out->L = l.L;
+    out->k_f = l.k_f;
+    out->k_m = l.k_m;
+    out->nu_f = l.nu_f;
+    out->nu_e = l.nu_e;
+    out->K = l.K;
+    out->F_phi = l.F_phi;
+    out->gbeta = l.gbeta;
+    out->h_v = l.h_v;
+    out->L_a = l.L_a;
+    out->d_p = l.d_p;
+    out->z = l.z;
+    out->tau_v = 1.0 / l.s[7];
+    out->tau_g = 1.0 / l.zeta[3];
+    out->tau_h = 1.0 / l.eta[3];
+    for (int k = 0; k < 9; ++k) {
+        out->s[k] = l.s[k];
+        out->zeta[k] = l.zeta[k];
+        out->eta[k] = l.eta[k];
+    }
+    out->H_fs = l.H_fs;
+    out->H_fl = l.H_fl;
+    out->T_ref = l.T_ref;
+    out->H_ref = l.H_ref;
+    for (int f = 0; f < 3; ++f) out->scale_exp[f] = l.scale_exp[f];
+}
+}  // namespace
+
+extern "C" lbm_status lbm_get_lattice(const lbm_handle *h, int32_t c, lbm_lattice *out) {
+    if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    fill_lattice(h->pl.lat[c], out);
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_lattice_of(const lbm_params *p, lbm_precision prec, lbm_lattice *out) {
+    if (!p || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (storage_of(prec) < 0) return fail(LBM_EINVAL, "unknown precision %d", (int)prec);
+    Lattice l;
+    lbm_status s = map_params(*p, prec, l);
+    if (s != LBM_OK) return s;
+    fill_lattice(l, out);
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_get_launch(const lbm_handle *h, lbm_launch_config *out) {
+    if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+    *out = h->lc;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg) {
+    if (!h || !cfg) return fail(LBM_EINVAL, "NULL argument");
+    if (!valid_launch(*cfg))
+        return fail(LBM_EINVAL, "unsupported launch shape block=%d npt=%d xcd=%d persistent=%d", cfg->block,
+                    cfg->nodes_per_thread, cfg->xcd_remap, cfg->persistent);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    lbm_status s = build_tiles(h, *cfg);
+    if (s != LBM_OK) return s;
+    h->lc = *cfg;
+    drop_graphs(h);
+    return LBM_OK;
+}
+
+namespace {
+std::string tune_key(lbm_handle *h) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s:prec%d:n%d:nodes%lld:nx%d:ny%d", arch.c_str(), (int)h->prec, h->n,
+             (long long)h->pl.nodes, h->params[0].nx, h->params[0].ny);
+    return buf;
+}
+}  // namespace
+
+extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cache_path,
+                                   lbm_launch_config *chosen) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (steps < 1) return fail(LBM_EINVAL, "steps_per_trial must be >= 1");
+    const std::string key = tune_key(h);
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char k[256];
+            lbm_launch_config lc;
+            while (fscanf(f, "%255s %d %d %d %d", k, &lc.block, &lc.nodes_per_thread, &lc.xcd_remap,
+                          &lc.persistent) == 5) {
+                if (key == k && valid_launch(lc)) {
+                    fclose(f);
+                    lbm_status s = lbm_set_launch(h, &lc);
+                    if (s == LBM_OK && chosen) *chosen = lc;
+                    return s;
+                }
+            }
+            fclose(f);
+        }
+    }
+    const int blocks[] = {128, 256, 512};
+    const int npts[] = {1, 2};
+    const int xcds[] = {0, 1};
+    const int pers[] = {0, 4};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    lbm_launch_config best = h->lc;
+    float best_ms = 1e30f;
+    const lbm_launch_config saved = h->lc;
+    for (int b : blocks)
+        for (int np : npts)
+            for (int xr : xcds)
+                for (int pp : pers) {
+                    lbm_launch_config lc{b, np, xr, pp};
+                    lbm_status s = build_tiles(h, lc);
+                    if (s != LBM_OK) return s;
+                    // reads the live buffer, writes only the other buffer and scratch tallies
+                    StepLaunch L = step_args(h, 1, h->cur, h->acc_scratch(), 0, (int)h->tiles.size(), lc);
+                    HIP_TRY(launch_step(L, h->stream));
+                    HIP_TRY(hipEventRecord(e0, h->stream));
+                    for (int k = 0; k < steps; ++k) HIP_TRY(launch_step(L, h->stream));
+                    HIP_TRY(hipEventRecord(e1, h->stream));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = lc;
+                    }
+                }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)saved;
+    // The trials wrote the inactive buffer; when the live state is the raw
+    // initial state the inactive buffer is not part of the state either.
+    lbm_status s = lbm_set_launch(h, &best);
+    if (s != LBM_OK) return s;
+    if (chosen) *chosen = best;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %d %d\n", key.c_str(), best.block, best.nodes_per_thread, best.xcd_remap,
+                    best.persistent);
+            fclose(f);
+        }
+    }
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Checkpoints
+// ---------------------------------------------------------------------------
+namespace {
+const char kMagic[8] = {'L', 'B', 'M', 'P', 'C', 'M', '0', '1'};
+
+struct CkptHeader {
+    char magic[8];
+    int32_t prec, n, cur_is_raw, pad;
+    int64_t step, nodes, slots;
+};
+}  // namespace
+
+extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
+    if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const size_t es = elem_size(h->st), rs = real_size(h->st);
+    std::vector<char> buf((size_t)27 * h->pl.stride * es);
+    HIP_TRY(hipMemcpy(buf.data(), h->pop(h->cur), buf.size(), hipMemcpyDeviceToHost));
+    std::vector<char> sr((size_t)h->pl.stride * rs);
+    HIP_TRY(hipMemcpy(sr.data(), h->sr(h->cur), sr.size(), hipMemcpyDeviceToHost));
+    std::vector<double> acc((size_t)h->pl.slots * 2);
+    HIP_TRY(hipMemcpy(acc.data(), h->acc(), acc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(LBM_EIO, "cannot open %s for writing", path);
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    std::memcpy(hd.magic, kMagic, 8);
+    hd.prec = (int32_t)h->prec;
+    hd.n = h->n;
+    hd.cur_is_raw = h->step == 0;
+    hd.step = h->step;
+    hd.nodes = h->pl.nodes;
+    hd.slots = h->pl.slots;
+    bool ok = fwrite(&hd, sizeof(hd), 1, f) == 1;
+    ok = ok && fwrite(h->params.data(), sizeof(lbm_params), h->n, f) == (size_t)h->n;
+    ok = ok && fwrite(h->E0.data(), sizeof(double), h->n, f) == (size_t)h->n;
+    ok = ok && fwrite(h->M0.data(), sizeof(double), h->n, f) == (size_t)h->n;
+    ok = ok && fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+    ok = ok && fwrite(sr.data(), 1, sr.size(), f) == sr.size();
+    ok = ok && fwrite(acc.data(), sizeof(double), acc.size(), f) == acc.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(LBM_EIO, "short write to %s", path);
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
+    if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(LBM_EIO, "cannot open %s", path);
+    CkptHeader hd;
+    if (fread(&hd, sizeof(hd), 1, f) != 1 || std::memcmp(hd.magic, kMagic, 8) != 0) {
+        fclose(f);
+        return fail(LBM_EIO, "%s is not a checkpoint of this library", path);
+    }
+    if (hd.prec != (int32_t)h->prec || hd.n != h->n || hd.nodes != h->pl.nodes || hd.slots != h->pl.slots) {
+        fclose(f);
+        return fail(LBM_EINVAL, "checkpoint %s was written for other cavities or precision", path);
+    }
+    std::vector<lbm_params> ps(h->n);
+    std::vector<double> E0(h->n), M0(h->n);
+    const size_t es = elem_size(h->st), rs = real_size(h->st);
+    std::vector<char> buf((size_t)27 * h->pl.stride * es), sr((size_t)h->pl.stride * rs);
+    std::vector<double> acc((size_t)h->pl.slots * 2);
+    bool ok = fread(ps.data(), sizeof(lbm_params), h->n, f) == (size_t)h->n;
+    ok = ok && fread(E0.data(), sizeof(double), h->n, f) == (size_t)h->n;
+    ok = ok && fread(M0.data(), sizeof(double), h->n, f) == (size_t)h->n;
+    ok = ok && fread(buf.data(), 1, buf.size(), f) == buf.size();
+    ok = ok && fread(sr.data(), 1, sr.size(), f) == sr.size();
+    ok = ok && fread(acc.data(), sizeof(double), acc.size(), f) == acc.size();
+    fclose(f);
+    if (!ok) return fail(LBM_EIO, "short read from %s", path);
+    for (int c = 0; c < h->n; ++c)
+        if (std::memcmp(&ps[c], &h->params[c], sizeof(lbm_params)) != 0)
+            return fail(LBM_EINVAL, "checkpoint %s: parameters of cavity %d differ", path, c);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->cur = 0;
+    HIP_TRY(hipMemcpy(h->pop(0), buf.data(), buf.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->sr(0), sr.data(), sr.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->acc(), acc.data(), acc.size() * sizeof(double), hipMemcpyHostToDevice));
+    h->step = hd.step;
+    h->E0 = E0;
+    h->M0 = M0;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_copy_state(lbm_handle *h, int32_t c, void *host, uint64_t bytes) {
+    if (!h || !host) return fail(LBM_EINVAL, "NULL argument");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    const size_t es = elem_size(h->st);
+    const int64_t nn = (int64_t)h->params[c].nx * h->params[c].ny;
+    if (bytes < (uint64_t)27 * nn * es) return fail(LBM_EINVAL, "host buffer too small");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int q = 0; q < 27; ++q) {
+        const char *src = (const char *)h->pop(h->cur) + ((size_t)q * h->pl.stride + h->pl.node0[c]) * es;
+        HIP_TRY(hipMemcpy((char *)host + (size_t)q * nn * es, src, nn * es, hipMemcpyDeviceToHost));
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_debug_poke(lbm_handle *h, int32_t c, int32_t x, int32_t y, int32_t field,
+                                     int32_t dir, double value) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    const lbm_params &p = h->params[c];
+    if (x < 0 || x >= p.nx || y < 0 || y >= p.ny || field < 0 || field > 2 || dir < 0 || dir > 8)
+        return fail(LBM_EINVAL, "poke index out of range");
+    const size_t es = elem_size(h->st);
+    const int64_t node = h->pl.node0[c] + (int64_t)y * p.nx + x;
+    char *ptr = (char *)h->pop(h->cur) + ((size_t)(field * 9 + dir) * h->pl.stride + node) * es;
+    HIP_TRY(launch_poke(h->st, ptr, value, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}

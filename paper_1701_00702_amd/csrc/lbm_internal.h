@@ -1,0 +1,119 @@
+// Internal declarations shared by the kernels (lbm_kernels.hip) and the host
+// library (lbm_api.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+enum Wall { W_LEFT = 0, W_RIGHT = 1, W_BOTTOM = 2, W_TOP = 3 };
+
+// Per-cavity constants in the arithmetic type R of the kernels.  One table
+// entry per cavity lives in device memory; a workgroup reads the entry of
+// its tile through scalar loads.
+template <typename R>
+struct CavityConst {
+    // geometry of the cavity inside the packed node index
+    int32_t nx, ny, periodic, gaxis;
+    int64_t node0;  // first packed node of this cavity
+    int64_t acc0;   // first wall-tally slot of this cavity (2*(nx+ny) slots)
+    // materials
+    R phi, inv_phi;
+    R inv_cpm, inv_cps, inv_cpl, c_pl, c_pm, c_fref, c_mref;
+    // relaxation rates in moment order and the forcing factors 1 - s/2
+    R s[9], s_half[9], zeta[9], eta[9];
+    // flow: buoyancy, porous drag, explicit velocity (Eqs. 3, 7, 23-25)
+    R gbeta, T0, drag_lin, drag_quad, l0, l0sq, l1;
+    // interstitial exchange (Eqs. 36, 47): Sr_f = hv_f (T_m - T_f), Sr_m = hv_m (T_f - T_m)
+    R hv_f, hv_m, sr_ratio;  // sr_ratio = hv_m / hv_f
+    // enthalpy -> temperature, liquid fraction (Eqs. 38-39)
+    R H_fs, H_fl, T_fs, T_fl, inv_dH, dT_band;
+    // reference state the populations are stored relative to
+    R T_ref, H_ref;
+    // isothermal walls
+    R T_hot, T_cold, H_hot, H_cold;
+    // storage scale per field (populations are stored as (X - X_ref) * scale)
+    R scale[3], inv_scale[3];
+    // FP64 copies for the energy/mass tallies
+    double we, wm;  // phi rho_l and (1 - phi) rho_m
+    double g_ref[9], h_ref[9];
+    double T_init;
+};
+
+// A tile is a run of nodes [x0, x1) on row y of one cavity.
+struct Tile {
+    int32_t cav, y, x0, x1;
+};
+
+struct StepLaunch {
+    int storage;
+    int block, npt, xcd_remap, grid;  // grid: number of workgroups (>= 1)
+    int pull;                         // 0: first step, populations are post-streaming already
+    const void *src;                  // 27 planes of plane_stride elements
+    void *dst;
+    int64_t plane_stride;
+    const void *sr_src;
+    void *sr_dst;
+    double *acc;                      // wall tallies: [slot][2] (energy, mass)
+    const void *cav;                  // CavityConst<R>[]
+    const Tile *tiles;
+    int ntiles;
+};
+
+struct MacroLaunch {
+    int storage;
+    int raw;  // 1: populations are post-streaming already (step 0)
+    int cav_index;
+    const void *src;
+    int64_t plane_stride;
+    const void *cav;     // CavityConst<R>[]
+    double *fields;      // 6 planes of nx*ny doubles: ux, uy, T_f, T_m, f_l, rho
+    double *partials;    // [nblocks][NPART]
+    int nblocks;
+};
+
+// Per-block partial sums of the diagnostics kernel.
+enum {
+    P_FL = 0, P_E, P_M, P_DT, P_U, P_NF,
+    P_INE0, P_INE1, P_INE2, P_INE3, P_INM0, P_INM1, P_INM2, P_INM3,
+    NPART = 16
+};
+// Layout of the device-side diagnostics result (doubles).
+enum {
+    D_FL = 0, D_E, D_M, D_DT, D_U, D_NF, D_NUH, D_NUHP, D_NUC, D_FRONT,
+    D_FLUXE = 10, D_FLUXM = 14, NDIAG = 18
+};
+
+struct DiagLaunch {
+    int nx, ny, periodic;
+    int64_t acc0;
+    const double *fields;
+    const double *partials;
+    int nblocks;
+    const double *acc;
+    double *out;      // NDIAG doubles
+    double L, ke, kf, km, dT;  // kf = phi k_f, km = (1-phi) k_m, ke = kf + km
+};
+
+struct InitLaunch {
+    int storage;
+    int cav_index;
+    const void *cav;
+    void *dst;
+    int64_t plane_stride;
+    void *sr;
+    const double *T_pcm;  // device, may be null
+    const double *T_mf;   // device, may be null
+};
+
+hipError_t launch_step(const StepLaunch &L, hipStream_t s);
+hipError_t launch_macro(const MacroLaunch &L, int nx, int ny, hipStream_t s);
+hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s);
+hipError_t launch_init(const InitLaunch &L, int nx, int ny, hipStream_t s);
+hipError_t launch_poke(int storage, void *ptr, double value, hipStream_t s);
+int macro_blocks(int nx, int ny);
+
+}  // namespace lbm

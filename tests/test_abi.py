@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point the header declares, and its host-only parameter mapping
+and validation agree with the paper's printed numbers and with the CPU
+checker's mapping."""
+import os
+import re
+
+import pytest
+
+import lbm_workloads as W
+from oracle.mapping import lattice_params
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbmpcm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const char \*|lbm_status|int64_t)\s*(lbm_\w+)\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1701_00702_amd import lbm
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lbm._lib, n), n
+        assert n in lbm.EXPORTED, f"binding lacks {n}"
+        assert callable(getattr(lbm, n)), f"binding wrapper {n} missing"
+
+
+def test_host_mapping_matches_paper_and_checker():
+    from paper_1701_00702_amd import lbm
+    p, _, _, _ = W.case_p1()
+    l = lbm.lbm_lattice_of(p, "f64")
+    assert round(l["zeta"][1], 4) == 0.0296          # Sec. V D
+    lo = lattice_params(p)
+    for k in ("L", "k_f", "k_m", "nu_f", "nu_e", "K", "F_phi", "gbeta", "h_v", "L_a", "d_p", "z",
+              "H_fs", "H_fl"):
+        assert l[k] == pytest.approx(lo[k], rel=1e-14, abs=1e-300), k
+    for k in ("s", "zeta", "eta"):
+        assert l[k] == pytest.approx(lo[k], rel=1e-14), k
+    # every BASELINE-shaped case maps, and the rule for k_f gives the
+    # paper's value (tau_h = 2) at lambda = 1000
+    for case in (W.case_c1, W.case_c2, W.case_c3, W.case_c4):
+        q = case()[0]
+        a, b = lbm.lbm_lattice_of(q, "f32"), lattice_params(q)
+        assert a["k_f"] == pytest.approx(b["k_f"], rel=1e-14)
+        assert a["tau_h"] <= 2.0 + 1e-12 and a["z"] <= 0.5 + 1e-12
+    c5, _, _, _ = W.case_c5()
+    for q in c5:
+        a, b = lbm.lbm_lattice_of(q, "f32"), lattice_params(q)
+        assert a["k_f"] == pytest.approx(b["k_f"], rel=1e-14)
+        assert a["gbeta"] == pytest.approx(b["gbeta"], rel=1e-14)
+
+
+def test_host_validation_rejects_bad_sets():
+    from paper_1701_00702_amd import lbm
+    base = W.case_c1()[0]
+    bad = [dict(base, porosity=1.0), dict(base, nx=3), dict(base, cf_ref=1.9), dict(base, Ste=0.0),
+           dict(base, k_f=5e-3, Nu_i=60.0), dict(base, T_hot=0.0), dict(base, T_liquidus=-1.0),
+           dict(base, bc_x=2)]
+    for q in bad:
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_lattice_of(q, "f32")
+        assert e.value.status == lbm.LBM_EINVAL
+        assert lbm.lbm_last_error()
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_workspace_bytes([base], 7)
+
+
+def test_workspace_plan_sizes():
+    from paper_1701_00702_amd import lbm
+    p3 = W.case_c3()[0]
+    b32 = lbm.lbm_workspace_bytes(p3, "f32")
+    b16 = lbm.lbm_workspace_bytes(p3, "f16")
+    n = p3["nx"] * p3["ny"]
+    assert b32 >= 2 * 27 * 4 * n and b16 >= 2 * 27 * 2 * n
+    assert b32 - b16 >= 2 * 27 * 2 * n * 0.99
+    c5 = W.case_c5()[0]
+    nodes = sum(q["nx"] * q["ny"] for q in c5)
+    assert nodes == 24198641
+    assert lbm.lbm_workspace_bytes(c5, "f32") >= 2 * 27 * 4 * nodes
