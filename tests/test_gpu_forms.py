@@ -1,0 +1,160 @@
+"""GPU checks of the full-size, full-length, 16-bit and batched forms.
+
+* Full-size cavity (8192^2, FP32) in the benchmark's launch shape: after a
+  few steps every node depends only on a small neighbourhood of the seeded
+  initial state, so the CPU checker run on small windows (with its own
+  light-cone bookkeeping) gives exact expected values for sampled nodes at
+  the corners, on the walls and in the interior.
+* Full-length runs of the 64^2 FP64 case and the 256^2 FP32 case.
+* 16-bit offset storage: errors against the FP64 checker are measured and
+  bounded; the bounds are what the storage rounding allows,
+  not parity.
+* Batched cavities: each cavity inside the packed launch is bit-identical to
+  the same cavity run alone, and to the one-launch-per-cavity schedule.
+"""
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+import oracle
+from test_gpu_parity import diag_errors, field_errors, run_pair
+
+pytestmark = pytest.mark.gpu
+
+BENCH_LAUNCH = dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0)
+
+
+@pytest.fixture(scope="module")
+def lbm(require_gpu):
+    import torch
+    torch.cuda.set_device(0)
+    from paper_1701_00702_amd import lbm as mod
+    return mod
+
+
+def test_fullsize_c3_sampled_windows(lbm):
+    p, _, seed, _ = W.case_c3()
+    nx, ny = p["nx"], p["ny"]
+    T_pcm, T_mf = W.initial_temperatures(p, seed)
+    s = lbm.Solver(p, "f32")
+    lbm.lbm_set_launch(s.h, **BENCH_LAUNCH)
+    s.set_initial(0, T_pcm, T_mf)
+    steps = 8
+    s.step(steps)
+    g = s.fields()
+    s.close()
+    w = 48
+    windows = [(0, 0), (nx - w, ny - w), (0, ny // 2), (nx // 2, 0), (nx // 3, ny // 3),
+               (nx - w, 0), (0, ny - w)]
+    checked = 0
+    for (x0, y0) in windows:
+        o = oracle.Oracle(p, window=(x0, y0, w, w))
+        o.set_initial(T_pcm[y0:y0 + w, x0:x0 + w], T_mf[y0:y0 + w, x0:x0 + w])
+        o.step(steps)
+        r = o.fields()
+        mask = r["valid"]
+        assert mask.sum() > 100, (x0, y0)
+        sub = {k: v[y0:y0 + w, x0:x0 + w] for k, v in g.items()}
+        e = field_errors(sub, r, p, mask)
+        assert max(e.values()) < 1e-4, ((x0, y0), e)
+        checked += int(mask.sum())
+    assert checked > 4000
+
+
+def test_fp64_c1_full_length(lbm):
+    p, steps, seed, _ = W.case_c1()
+    g, gd, r, rd = run_pair(lbm, p, steps, seed)
+    e = field_errors(g, r, p)
+    de = diag_errors(gd, rd)
+    print("C1 FP64 20000 steps", e, de)
+    assert max(e.values()) < 1e-10, e
+    assert max(de.values()) < 1e-10, de
+    assert rd["liquid_fraction"] > 0.6        # well into the melting run
+    assert abs(gd["energy_residual"]) < 1e-12 * gd["E_int"]
+
+
+def test_fp32_c2_ab_full_length(lbm):
+    p, steps, seed, _ = W.case_c2(256)
+    assert steps == 12500
+    g, gd, r, rd = run_pair(lbm, p, steps, seed, precision="f32")
+    e = field_errors(g, r, p)
+    print("C2 A/B 256^2 FP32 12500 steps", e, gd["liquid_fraction"], rd["liquid_fraction"])
+    assert max(e.values()) < 1e-4, e
+    assert abs(gd["liquid_fraction"] - rd["liquid_fraction"]) < 1e-4
+    for k in ("Nu_hot", "Nu_hot_pcm"):
+        assert abs(gd[k] - rd[k]) < 1e-4 * abs(rd[k]), k
+    assert abs(gd["x_front_mid"] - rd["x_front_mid"]) < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["f16", "bf16"])
+def test_16bit_offsets_error_vs_fp64(lbm, precision):
+    p = W.scaled_cavity(W.case_c4()[0], 256)
+    steps = 3000
+    g, gd, r, rd = run_pair(lbm, p, steps, 0, precision=precision)
+    e = field_errors(g, r, p)
+    err = {"liquid_fraction": abs(gd["liquid_fraction"] - rd["liquid_fraction"]),
+           "x_front_mid": abs(gd["x_front_mid"] - rd["x_front_mid"]),
+           "Nu_hot": abs(gd["Nu_hot"] - rd["Nu_hot"]) / abs(rd["Nu_hot"])}
+    print(precision, "fields", e, "diag", err, "fl", gd["liquid_fraction"], rd["liquid_fraction"])
+    assert gd["nonfinite"] == 0
+    # coarse bounds: the run must stay physical and close to the FP64 answer
+    assert err["liquid_fraction"] < 0.25 * rd["liquid_fraction"] + 1e-3
+    assert e["T_pcm"] < 0.1 and e["T_mf"] < 0.1
+
+
+def test_batched_cavities_bitwise(lbm):
+    ps, _, _, _ = W.case_c5()
+    pick = sorted(range(len(ps)), key=lambda c: ps[c]["nx"] * ps[c]["ny"])[:5] + [0]
+    batch = [ps[c] for c in pick]
+    temps = [W.initial_temperatures(q, 100 + i) for i, q in enumerate(batch)]
+    steps = 120
+    b = lbm.Solver(batch, "f32")
+    lbm.lbm_set_launch(b.h, block=256, nodes_per_thread=1, xcd_remap=1, persistent=4)
+    for c, (tp, tm) in enumerate(temps):
+        b.set_initial(c, tp, tm)
+    b.step(steps)
+    lp = lbm.Solver(batch, "f32")
+    for c, (tp, tm) in enumerate(temps):
+        lp.set_initial(c, tp, tm)
+    lbm.lbm_step_per_cavity(lp.h, steps)
+    for c, q in enumerate(batch):
+        single = lbm.Solver(q, "f32")
+        single.set_initial(0, *temps[c])
+        single.step(steps)
+        a = b.state(c).view(np.uint32)
+        assert np.array_equal(a, single.state().view(np.uint32)), c
+        assert np.array_equal(a, lp.state(c).view(np.uint32)), c
+        db, ds = b.diagnostics(c), single.diagnostics()
+        assert db["flux_E"] == ds["flux_E"] and db["E_int"] == ds["E_int"]
+        single.close()
+    # and the smallest cavity against the FP64 checker
+    q = batch[0]
+    o = oracle.Oracle(q)
+    o.set_initial(*temps[0])
+    o.step(steps)
+    e = field_errors(b.fields(0), o.fields(), q)
+    assert max(e.values()) < 1e-4, e
+    b.close()
+    lp.close()
+
+
+def test_autotune_keeps_state(lbm, tmp_path):
+    p = W.scaled_cavity(W.case_c2()[0], 512)
+    T_pcm, T_mf = W.initial_temperatures(p, 1)
+    a = lbm.Solver(p, "f32")
+    a.set_initial(0, T_pcm, T_mf)
+    a.step(40)
+    before = a.state().copy()
+    cache = str(tmp_path / "tune.txt")
+    cfg = lbm.lbm_autotune(a.h, 3, cache)
+    assert cfg["block"] in (128, 256, 512)
+    assert np.array_equal(a.state().view(np.uint32), before.view(np.uint32))
+    a.step(10)
+    b = lbm.Solver(p, "f32")
+    b.set_initial(0, T_pcm, T_mf)
+    b.step(50)
+    assert np.array_equal(a.state().view(np.uint32), b.state().view(np.uint32))
+    # a second handle reads the choice from the cache
+    assert lbm.lbm_autotune(b.h, 3, cache) == cfg
+    a.close()
+    b.close()
