@@ -7,9 +7,10 @@ double-buffered populations).  Inputs are resident in HBM before timing;
 the timed region is bracketed by HIP events on the stream the kernels run
 on.  MLUPS counts every node (walls included) advancing all 27 populations.
 
-Algorithmic HBM bytes per node and step: 27 populations read + 27 written
-+ the previous-step source read + written: FP32 224 B, FP64 448 B, 16-bit
-offsets 116 B.
+Algorithmic HBM bytes per node and step: the stored populations read once
+and written once, plus the previous-step source read and written: FP64
+448 B, FP32 224 B, FP32 with the FP64 rest enthalpy population 232 B,
+split 16-bit 152 B, 16-bit offsets 116 B.
 """
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BYTES_PER_NODE = {"f64": 448, "f32": 224, "f16": 116, "bf16": 116}
+BYTES_PER_NODE = {"f64": 448, "f32": 224, "f32h64": 232, "f16split": 152, "f16": 116, "bf16": 116}
 PEAK_HBM_GBPS = 8000.0
 METRIC = "MLUPS (3 coupled MRT fields) + achieved HBM GB/s vs peak; FP16-store vs FP32"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1701_00702_amd", "csrc", n)
@@ -129,7 +130,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
-    ap.add_argument("--precision", default=None, choices=[None, "f64", "f32", "f16", "bf16"])
+    ap.add_argument("--precision", default=None, choices=[None] + list(BYTES_PER_NODE))
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--npt", type=int, default=1)
     ap.add_argument("--xcd", type=int, default=1)
@@ -199,26 +200,29 @@ def main():
 
     if args.forms:
         forms = {}
-        for wl, pr in (("c4", "f16"), ("c4", "bf16"), ("c4", "f32")):
+        for wl, pr in (("c3", "f32h64"), ("c3", "f16split"), ("c3", "f16"), ("c3", "bf16"),
+                       ("c4", "f32"), ("c4", "f16split")):
             ps, sd, _, _ = workload(wl)
             s2, ws2 = make_solver(lbm, torch, ps, pr, stream)
             T_pcm, T_mf = W.initial_temperatures(ps[0], sd)
             s2.set_initial(0, T_pcm, T_mf)
             lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent)
             n2 = ps[0]["nx"] * ps[0]["ny"]
-            t = time_steps(lbm, torch, s2, stream, 200, 10) / 200
-            forms[f"{wl}_{pr}"] = {"MLUPS": n2 / (t * 1e-3) / 1e6,
+            t = time_steps(lbm, torch, s2, stream, 100, 10) / 100
+            forms[f"{wl}_{pr}"] = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t,
                                    "alg_GBps": BYTES_PER_NODE[pr] * n2 / (t * 1e-3) / 1e9}
             s2.close()
             del ws2
             torch.cuda.empty_cache()
         ps, sd, _, _ = workload("c5")
         s2, ws2 = make_solver(lbm, torch, ps, "f32", stream)
+        for c, q in enumerate(ps):
+            s2.set_initial(c, *W.initial_temperatures(q, sd + c))
         lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent)
         n2 = sum(q["nx"] * q["ny"] for q in ps)
         t1 = time_steps(lbm, torch, s2, stream, 200, 10) / 200
-        t2 = time_steps(lbm, torch, s2, stream, 50, 2, looped=True) / 50
-        forms["c5_batched_f32"] = {"MLUPS": n2 / (t1 * 1e-3) / 1e6,
+        t2 = time_steps(lbm, torch, s2, stream, 20, 2, looped=True) / 20
+        forms["c5_batched_f32"] = {"MLUPS": n2 / (t1 * 1e-3) / 1e6, "ms_per_step": t1,
                                    "looped_single_cavity_MLUPS": n2 / (t2 * 1e-3) / 1e6}
         s2.close()
         del ws2

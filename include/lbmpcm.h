@@ -51,15 +51,28 @@ typedef enum {
 } lbm_status;
 
 /* Storage of the 27 populations per node.  Arithmetic is FP64 for LBM_F64
- * and FP32 otherwise.  The 16-bit forms store, per field, the offset of each
+ * and FP32 otherwise.  Every form stores, per field, the offset of each
  * population from the rest equilibrium at a fixed reference state (flow: the
  * lattice weights times the reference density; enthalpy and metal fields:
- * the equilibria at the middle of the mushy band), times a power-of-two scale. */
+ * the equilibria at rest at the middle of the mushy band).
+ *   LBM_F64, LBM_F32   the offsets in FP64 / FP32 (216 / 108 bytes per node)
+ *   LBM_F16_OFFSET     the offsets in binary16 times a power-of-two scale (54)
+ *   LBM_BF16_OFFSET    the offsets in bfloat16 (54)
+ *   LBM_F16_SPLIT      per field the rest population and one base value
+ *                      (flow: density offset; enthalpy: c_f,ref (T_f - T_ref);
+ *                      metal: c_m,ref (T_m - T_ref)) in FP32, and the eight
+ *                      moving populations as binary16 remainders from the rest
+ *                      equilibrium of that base (72 bytes per node)
+ *   LBM_F32_H64        as LBM_F32, except the rest population of the enthalpy
+ *                      field, which carries H itself, in FP64, and the
+ *                      enthalpy-field arithmetic in FP64 (112 bytes per node). */
 typedef enum {
     LBM_F64 = 0,
     LBM_F32 = 1,
     LBM_F16_OFFSET = 2,
-    LBM_BF16_OFFSET = 3
+    LBM_BF16_OFFSET = 3,
+    LBM_F16_SPLIT = 4,
+    LBM_F32_H64 = 5
 } lbm_precision;
 
 /* Problem description in dimensionless groups (Eq. 54).  Lattice units:
@@ -216,11 +229,13 @@ lbm_status lbm_save(lbm_handle *h, const char *path);
 lbm_status lbm_load(lbm_handle *h, const char *path);
 
 /* Copy the raw stored populations of one cavity to host memory, for
- * bit-level comparisons: f, g, h each [9][ny][nx] in the storage type
- * (8, 4 or 2 bytes per value), i.e. 27 * nx * ny * bytes in total. */
+ * bit-level comparisons: every stored plane of the cavity in storage order
+ * ([plane][ny][nx], planes as listed for lbm_precision), i.e. (bytes per
+ * node) * nx * ny bytes: 216, 108, 54, 54, 72 or 112 per node. */
 lbm_status lbm_copy_state(lbm_handle *h, int32_t cavity, void *host, uint64_t bytes);
 
-/* Overwrite one stored population of the current state (test hook for the
+/* Overwrite one stored population of the current state with value,
+ * converted to the element type it is stored in (test hook for the
  * failure-detection path).  field: 0 f, 1 g, 2 h; dir: 0..8. */
 lbm_status lbm_debug_poke(lbm_handle *h, int32_t cavity, int32_t x, int32_t y, int32_t field,
                           int32_t dir, double value);

@@ -151,6 +151,12 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
         return fail(LBM_EINVAL, "interstitial exchange number z = %g >= 1: explicit source unstable", l.z);
     // storage scales (16-bit forms): keep the largest expected offset near 2^14
     l.scale_exp[0] = l.scale_exp[1] = l.scale_exp[2] = 0;
+    if (prec == LBM_F16_SPLIT) {
+        // remainders from the rest equilibrium of the base values (small)
+        l.scale_exp[0] = 16;
+        l.scale_exp[1] = 12;
+        l.scale_exp[2] = 12;
+    }
     if (prec == LBM_F16_OFFSET) {
         double span_g = 1.0, span_h = 1.0;
         const double Ts[3] = {p.T_hot, p.T_cold, p.T_init};
@@ -163,6 +169,31 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
         l.scale_exp[2] = std::max(0, std::min(14, (int)std::floor(std::log2(16384.0 / span_h))));
     }
     return LBM_OK;
+}
+
+template <typename T>
+ThermalConst<T> make_thermal(const Lattice &l) {
+    ThermalConst<T> t;
+    std::memset(&t, 0, sizeof(t));
+    t.H_fs = (T)l.H_fs;
+    t.H_fl = (T)l.H_fl;
+    t.T_fs = (T)l.T_fs;
+    t.T_fl = (T)l.T_fl;
+    t.inv_dH = (T)(1.0 / (l.H_fl - l.H_fs));
+    t.dT_band = (T)(l.T_fl - l.T_fs);
+    t.inv_cps = (T)(1.0 / l.c_ps);
+    t.inv_cpl = (T)(1.0 / l.c_pl);
+    t.c_pl = (T)l.c_pl;
+    t.c_fref = (T)l.c_fref;
+    t.inv_phi = (T)(1.0 / l.phi);
+    for (int k = 0; k < 9; ++k) t.zeta[k] = (T)l.zeta[k];
+    t.T_ref = (T)l.T_ref;
+    t.H_ref = (T)l.H_ref;
+    t.T_hot = (T)l.T_hot;
+    t.T_cold = (T)l.T_cold;
+    t.H_hot = (T)enthalpy_of(l, l.T_hot);
+    t.H_cold = (T)enthalpy_of(l, l.T_cold);
+    return t;
 }
 
 template <typename R>
@@ -178,16 +209,11 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
     c.phi = (R)l.phi;
     c.inv_phi = (R)(1.0 / l.phi);
     c.inv_cpm = (R)(1.0 / l.c_pm);
-    c.inv_cps = (R)(1.0 / l.c_ps);
-    c.inv_cpl = (R)(1.0 / l.c_pl);
-    c.c_pl = (R)l.c_pl;
     c.c_pm = (R)l.c_pm;
-    c.c_fref = (R)l.c_fref;
     c.c_mref = (R)l.c_mref;
     for (int k = 0; k < 9; ++k) {
         c.s[k] = (R)l.s[k];
         c.s_half[k] = (R)(1.0 - 0.5 * l.s[k]);
-        c.zeta[k] = (R)l.zeta[k];
         c.eta[k] = (R)l.eta[k];
     }
     c.gbeta = (R)l.gbeta;
@@ -204,22 +230,15 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
     c.hv_f = (R)hvf;
     c.hv_m = (R)hvm;
     c.sr_ratio = (R)((l.phi * l.rho_l) / ((1.0 - l.phi) * l.rho_m));
-    c.H_fs = (R)l.H_fs;
-    c.H_fl = (R)l.H_fl;
-    c.T_fs = (R)l.T_fs;
-    c.T_fl = (R)l.T_fl;
-    c.inv_dH = (R)(1.0 / (l.H_fl - l.H_fs));
-    c.dT_band = (R)(l.T_fl - l.T_fs);
     c.T_ref = (R)l.T_ref;
-    c.H_ref = (R)l.H_ref;
     c.T_hot = (R)l.T_hot;
     c.T_cold = (R)l.T_cold;
-    c.H_hot = (R)enthalpy_of(l, l.T_hot);
-    c.H_cold = (R)enthalpy_of(l, l.T_cold);
     for (int f = 0; f < 3; ++f) {
         c.scale[f] = (R)std::ldexp(1.0, l.scale_exp[f]);
         c.inv_scale[f] = (R)std::ldexp(1.0, -l.scale_exp[f]);
     }
+    c.tf = make_thermal<float>(l);
+    c.td = make_thermal<double>(l);
     c.we = l.phi * l.rho_l;
     c.wm = (1.0 - l.phi) * l.rho_m;
     const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
@@ -239,12 +258,29 @@ int storage_of(lbm_precision p) {
         case LBM_F32: return ST_F32;
         case LBM_F16_OFFSET: return ST_F16;
         case LBM_BF16_OFFSET: return ST_BF16;
+        case LBM_F16_SPLIT: return ST_F16S;
+        case LBM_F32_H64: return ST_F32H;
     }
     return -1;
 }
 
-size_t elem_size(int st) { return st == ST_F64 ? 8 : (st == ST_F32 ? 4 : 2); }
 size_t real_size(int st) { return st == ST_F64 ? 8 : 4; }
+
+// Plane groups of one buffer: {number of planes, bytes per element}.
+struct PlaneGroup {
+    int planes, bytes;
+};
+int plane_groups(int st, PlaneGroup g[2]) {
+    switch (st) {
+        case ST_F64: g[0] = {27, 8}; return 1;
+        case ST_F32: g[0] = {27, 4}; return 1;
+        case ST_F16:
+        case ST_BF16: g[0] = {27, 2}; return 1;
+        case ST_F16S: g[0] = {6, 4}; g[1] = {24, 2}; return 2;
+        case ST_F32H: g[0] = {26, 4}; g[1] = {1, 8}; return 2;
+    }
+    return 0;
+}
 
 // Memory plan shared by lbm_workspace_bytes and the create calls.
 struct Plan {
@@ -285,7 +321,7 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     size_t off = 0;
     for (int b = 0; b < 2; ++b) {
         pl.off_pop[b] = off;
-        off = align256(off + (size_t)27 * pl.stride * elem_size(st));
+        off = align256(off + (size_t)bytes_per_node(st) * pl.stride);
     }
     for (int b = 0; b < 2; ++b) {
         pl.off_sr[b] = off;
@@ -918,8 +954,8 @@ struct CkptHeader {
 extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
     if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
     HIP_TRY(hipStreamSynchronize(h->stream));
-    const size_t es = elem_size(h->st), rs = real_size(h->st);
-    std::vector<char> buf((size_t)27 * h->pl.stride * es);
+    const size_t rs = real_size(h->st);
+    std::vector<char> buf((size_t)bytes_per_node(h->st) * h->pl.stride);
     HIP_TRY(hipMemcpy(buf.data(), h->pop(h->cur), buf.size(), hipMemcpyDeviceToHost));
     std::vector<char> sr((size_t)h->pl.stride * rs);
     HIP_TRY(hipMemcpy(sr.data(), h->sr(h->cur), sr.size(), hipMemcpyDeviceToHost));
@@ -963,8 +999,8 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
     }
     std::vector<lbm_params> ps(h->n);
     std::vector<double> E0(h->n), M0(h->n);
-    const size_t es = elem_size(h->st), rs = real_size(h->st);
-    std::vector<char> buf((size_t)27 * h->pl.stride * es), sr((size_t)h->pl.stride * rs);
+    const size_t rs = real_size(h->st);
+    std::vector<char> buf((size_t)bytes_per_node(h->st) * h->pl.stride), sr((size_t)h->pl.stride * rs);
     std::vector<double> acc((size_t)h->pl.slots * 2);
     bool ok = fread(ps.data(), sizeof(lbm_params), h->n, f) == (size_t)h->n;
     ok = ok && fread(E0.data(), sizeof(double), h->n, f) == (size_t)h->n;
@@ -991,13 +1027,21 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
 extern "C" lbm_status lbm_copy_state(lbm_handle *h, int32_t c, void *host, uint64_t bytes) {
     if (!h || !host) return fail(LBM_EINVAL, "NULL argument");
     if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
-    const size_t es = elem_size(h->st);
     const int64_t nn = (int64_t)h->params[c].nx * h->params[c].ny;
-    if (bytes < (uint64_t)27 * nn * es) return fail(LBM_EINVAL, "host buffer too small");
+    if (bytes < (uint64_t)bytes_per_node(h->st) * nn) return fail(LBM_EINVAL, "host buffer too small");
     HIP_TRY(hipStreamSynchronize(h->stream));
-    for (int q = 0; q < 27; ++q) {
-        const char *src = (const char *)h->pop(h->cur) + ((size_t)q * h->pl.stride + h->pl.node0[c]) * es;
-        HIP_TRY(hipMemcpy((char *)host + (size_t)q * nn * es, src, nn * es, hipMemcpyDeviceToHost));
+    PlaneGroup grp[2];
+    const int ng = plane_groups(h->st, grp);
+    const char *src = (const char *)h->pop(h->cur);
+    char *dst = (char *)host;
+    for (int q = 0; q < ng; ++q) {
+        for (int p = 0; p < grp[q].planes; ++p) {
+            const size_t eb = grp[q].bytes;
+            HIP_TRY(hipMemcpy(dst, src + ((size_t)p * h->pl.stride + h->pl.node0[c]) * eb, nn * eb,
+                              hipMemcpyDeviceToHost));
+            dst += nn * eb;
+        }
+        src += (size_t)grp[q].planes * h->pl.stride * grp[q].bytes;
     }
     return LBM_OK;
 }
@@ -1009,10 +1053,33 @@ extern "C" lbm_status lbm_debug_poke(lbm_handle *h, int32_t c, int32_t x, int32_
     const lbm_params &p = h->params[c];
     if (x < 0 || x >= p.nx || y < 0 || y >= p.ny || field < 0 || field > 2 || dir < 0 || dir > 8)
         return fail(LBM_EINVAL, "poke index out of range");
-    const size_t es = elem_size(h->st);
     const int64_t node = h->pl.node0[c] + (int64_t)y * p.nx + x;
-    char *ptr = (char *)h->pop(h->cur) + ((size_t)(field * 9 + dir) * h->pl.stride + node) * es;
-    HIP_TRY(launch_poke(h->st, ptr, value, h->stream));
+    char *base = (char *)h->pop(h->cur);
+    char *ptr;
+    int elem;
+    if (h->st == ST_F32H) {
+        if (field == 1 && dir == 0) {
+            ptr = base + (size_t)26 * h->pl.stride * 4 + (size_t)node * 8;
+            elem = 8;
+        } else {
+            const int plane = field == 0 ? dir : (field == 1 ? 8 + dir : 17 + dir);
+            ptr = base + ((size_t)plane * h->pl.stride + node) * 4;
+            elem = 4;
+        }
+    } else if (h->st == ST_F16S) {
+        if (dir == 0) {
+            ptr = base + ((size_t)(2 * field) * h->pl.stride + node) * 4;
+            elem = 4;
+        } else {
+            ptr = base + (size_t)6 * h->pl.stride * 4 + ((size_t)(8 * field + dir - 1) * h->pl.stride + node) * 2;
+            elem = 2;
+        }
+    } else {
+        const int eb = bytes_per_node(h->st) / 27;
+        ptr = base + ((size_t)(field * 9 + dir) * h->pl.stride + node) * eb;
+        elem = h->st == ST_BF16 ? 3 : eb;
+    }
+    HIP_TRY(launch_poke(elem, ptr, value, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return LBM_OK;
 }

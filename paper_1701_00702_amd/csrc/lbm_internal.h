@@ -7,9 +7,21 @@
 
 namespace lbm {
 
-enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F16S = 4, ST_F32H = 5 };
 
 enum Wall { W_LEFT = 0, W_RIGHT = 1, W_BOTTOM = 2, W_TOP = 3 };
+
+// Constants of the PCM enthalpy field, kept in both arithmetic types (the
+// mixed storage form runs this field in FP64 and the others in FP32).
+template <typename T>
+struct ThermalConst {
+    // enthalpy -> temperature, liquid fraction (Eqs. 38-39)
+    T H_fs, H_fl, T_fs, T_fl, inv_dH, dT_band, inv_cps, inv_cpl;
+    // equilibrium (Eq. 34) and relaxation rates (Theta, Eq. 31)
+    T c_pl, c_fref, inv_phi, zeta[9];
+    // reference state and isothermal walls
+    T T_ref, H_ref, T_hot, T_cold, H_hot, H_cold;
+};
 
 // Per-cavity constants in the arithmetic type R of the kernels.  One table
 // entry per cavity lives in device memory; a workgroup reads the entry of
@@ -21,22 +33,20 @@ struct CavityConst {
     int64_t node0;  // first packed node of this cavity
     int64_t acc0;   // first wall-tally slot of this cavity (2*(nx+ny) slots)
     // materials
-    R phi, inv_phi;
-    R inv_cpm, inv_cps, inv_cpl, c_pl, c_pm, c_fref, c_mref;
+    R phi, inv_phi, inv_cpm, c_pm, c_mref;
     // relaxation rates in moment order and the forcing factors 1 - s/2
-    R s[9], s_half[9], zeta[9], eta[9];
+    R s[9], s_half[9], eta[9];
     // flow: buoyancy, porous drag, explicit velocity (Eqs. 3, 7, 23-25)
     R gbeta, T0, drag_lin, drag_quad, l0, l0sq, l1;
     // interstitial exchange (Eqs. 36, 47): Sr_f = hv_f (T_m - T_f), Sr_m = hv_m (T_f - T_m)
     R hv_f, hv_m, sr_ratio;  // sr_ratio = hv_m / hv_f
-    // enthalpy -> temperature, liquid fraction (Eqs. 38-39)
-    R H_fs, H_fl, T_fs, T_fl, inv_dH, dT_band;
-    // reference state the populations are stored relative to
-    R T_ref, H_ref;
-    // isothermal walls
-    R T_hot, T_cold, H_hot, H_cold;
+    // reference temperature of the stored offsets, isothermal walls (metal)
+    R T_ref, T_hot, T_cold;
     // storage scale per field (populations are stored as (X - X_ref) * scale)
     R scale[3], inv_scale[3];
+    // PCM enthalpy field
+    ThermalConst<float> tf;
+    ThermalConst<double> td;
     // FP64 copies for the energy/mass tallies
     double we, wm;  // phi rho_l and (1 - phi) rho_m
     double g_ref[9], h_ref[9];
@@ -52,7 +62,7 @@ struct StepLaunch {
     int storage;
     int block, npt, xcd_remap, grid;  // grid: number of workgroups (>= 1)
     int pull;                         // 0: first step, populations are post-streaming already
-    const void *src;                  // 27 planes of plane_stride elements
+    const void *src;                  // population planes of plane_stride nodes each
     void *dst;
     int64_t plane_stride;
     const void *sr_src;
@@ -113,7 +123,8 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t s);
 hipError_t launch_macro(const MacroLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_init(const InitLaunch &L, int nx, int ny, hipStream_t s);
-hipError_t launch_poke(int storage, void *ptr, double value, hipStream_t s);
+hipError_t launch_poke(int elem, void *ptr, double value, hipStream_t s);
 int macro_blocks(int nx, int ny);
+int bytes_per_node(int storage);  // stored bytes of one node's 27 populations
 
 }  // namespace lbm

@@ -1,0 +1,722 @@
+// Per-node arithmetic of the enthalpy-based MRT lattice Boltzmann method for
+// solid-liquid phase change in metal foams under local thermal
+// non-equilibrium (Liu, He & Li, arXiv:1701.00702): macroscopic values,
+// the three moment-space collisions, wall reconstruction, and the storage
+// layouts of the populations.  Everything here is __host__ __device__ so the
+// kernels in lbm_kernels.hip and a host build of the same arithmetic share it.
+//
+// Populations are handled as offsets q_i = X_i - X_ref,i from a fixed
+// reference equilibrium (flow: w_i rho_0; enthalpy/metal: the equilibria at
+// rest at the middle of the mushy band).  The moment algebra is affine, so
+// the update runs on the offsets; in FP32 this keeps the small momentum of
+// the Darcy-scale flow out of the rounding of O(1) populations.
+//
+// Two arithmetic types: R for the flow and metal fields, RH for the PCM
+// enthalpy field (H, T_f, f_l and the g collision).  The rest enthalpy
+// population carries H itself, O(1), so its rounding is what limits FP32;
+// the mixed form keeps that one population and the enthalpy arithmetic in
+// FP64 and everything else in FP32.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+#define LBM_HD __host__ __device__ __forceinline__
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Lattice (Eq. 11) and weights.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int ex_of(int i) {
+    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey_of(int i) {
+    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+template <typename R>
+__host__ __device__ constexpr R w_of(int i) {
+    return i == 0 ? R(4) / R(9) : (i <= 4 ? R(1) / R(9) : R(1) / R(36));
+}
+
+// Enthalpy-field constants in the enthalpy arithmetic type.
+template <typename RH>
+struct ThermalPick;
+template <>
+struct ThermalPick<float> {
+    template <typename R>
+    LBM_HD static const ThermalConst<float> &get(const CavityConst<R> &c) { return c.tf; }
+};
+template <>
+struct ThermalPick<double> {
+    template <typename R>
+    LBM_HD static const ThermalConst<double> &get(const CavityConst<R> &c) { return c.td; }
+};
+template <typename RH, typename R>
+LBM_HD const ThermalConst<RH> &thermal(const CavityConst<R> &c) {
+    return ThermalPick<RH>::get(c);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming loads/stores (non-temporal on the GPU: every value is touched
+// once per step) and element codecs.
+// ---------------------------------------------------------------------------
+template <typename T>
+LBM_HD T ld_stream(const T *p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <typename T>
+LBM_HD void st_stream(T *p, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+struct E64 {
+    using T = double;
+    LBM_HD static double dec(double v) { return v; }
+    LBM_HD static double enc(double v) { return v; }
+};
+struct E32 {
+    using T = float;
+    LBM_HD static float dec(float v) { return v; }
+    LBM_HD static float enc(float v) { return v; }
+};
+struct E16 {  // IEEE binary16, round to nearest even
+    using T = uint16_t;
+    LBM_HD static float dec(uint16_t v) { return (float)__builtin_bit_cast(_Float16, v); }
+    LBM_HD static uint16_t enc(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+};
+struct EB16 {  // bfloat16, round to nearest even (finite values)
+    using T = uint16_t;
+    LBM_HD static float dec(uint16_t v) { return __builtin_bit_cast(float, ((uint32_t)v) << 16); }
+    LBM_HD static uint16_t enc(float v) {
+        uint32_t u = __builtin_bit_cast(uint32_t, v);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Storage layouts.  load<V>() returns the offset q_i of field f (0 flow,
+// 1 enthalpy, 2 metal), direction i, at packed node k, in type V; store()
+// writes the nine offsets of one field at node k.  beta is the per-node base
+// value the split layout stores (unused elsewhere).
+// ---------------------------------------------------------------------------
+
+// 27 planes of one element type; 16-bit forms carry a power-of-two scale.
+template <class E, bool SCALED>
+struct Plain {
+    using T = typename E::T;
+    using C = decltype(E::dec(T()));  // element arithmetic type of the codec
+    static constexpr int bytes_per_node = 27 * (int)sizeof(T);
+    template <typename V, typename R>
+    LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
+        const T *p = (const T *)base + (int64_t)(9 * f + i) * stride + k;
+        const V v = (V)E::dec(ld_stream(p));
+        return SCALED ? v * (V)c.inv_scale[f] : v;
+    }
+    template <typename V, typename R>
+    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, int64_t k,
+                             const CavityConst<R> &c) {
+        (void)beta;
+        T *p = (T *)base + (int64_t)(9 * f) * stride + k;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st_stream(p + (int64_t)i * stride, E::enc((C)(SCALED ? q[i] * (V)c.scale[f] : q[i])));
+    }
+};
+
+// FP32 planes for 26 populations and one FP64 plane for the rest enthalpy
+// population: planes [f0..f8, g1..g8, h0..h8] in FP32, then g0 in FP64;
+// 112 bytes per node.
+struct PlainH64 {
+    static constexpr int bytes_per_node = 26 * 4 + 8;
+    LBM_HD static int plane(int f, int i) { return f == 0 ? i : (f == 1 ? 8 + i : 17 + i); }
+    template <typename V, typename R>
+    LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
+        (void)c;
+        if (f == 1 && i == 0) return (V)ld_stream((const double *)((const float *)base + 26 * stride) + k);
+        return (V)ld_stream((const float *)base + (int64_t)plane(f, i) * stride + k);
+    }
+    template <typename V, typename R>
+    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, int64_t k,
+                             const CavityConst<R> &c) {
+        (void)beta;
+        (void)c;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if (f == 1 && i == 0) st_stream((double *)((float *)base + 26 * stride) + k, (double)q[0]);
+            else st_stream((float *)base + (int64_t)plane(f, i) * stride + k, (float)q[i]);
+        }
+    }
+};
+
+// Split 16-bit layout: per field, the rest population and a base value beta
+// in FP32, and the eight moving populations as FP16 remainders from the rest
+// equilibrium of the base, r_i = q_i - w_i beta (scaled).  Bases: flow
+// delta rho, enthalpy c_f,ref (T_f - T_ref), metal c_m,ref (T_m - T_ref); the
+// moving populations stay close to w_i beta, so their remainders are small
+// and FP16 keeps them to ~1e-3 relative, while the conserved content
+// (rest population, base) keeps FP32 precision.
+// Planes: 6 FP32 planes [q_f0, beta_f, q_g0, beta_g, q_h0, beta_h], then 24
+// FP16 planes [field][direction 1..8]; 72 bytes per node.
+struct Split16 {
+    static constexpr int bytes_per_node = 6 * 4 + 24 * 2;
+    template <typename V, typename R>
+    LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
+        const float *P = (const float *)base;
+        if (i == 0) return (V)ld_stream(P + (int64_t)(2 * f) * stride + k);
+        const V beta = (V)ld_stream(P + (int64_t)(2 * f + 1) * stride + k);
+        const uint16_t *Qp = (const uint16_t *)(P + 6 * stride);
+        const V r = (V)E16::dec(ld_stream(Qp + (int64_t)(8 * f + i - 1) * stride + k));
+        return w_of<V>(i) * beta + r * (V)c.inv_scale[f];
+    }
+    template <typename V, typename R>
+    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, int64_t k,
+                             const CavityConst<R> &c) {
+        float *P = (float *)base;
+        st_stream(P + (int64_t)(2 * f) * stride + k, (float)q[0]);
+        st_stream(P + (int64_t)(2 * f + 1) * stride + k, (float)beta);
+        uint16_t *Qp = (uint16_t *)(P + 6 * stride);
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            st_stream(Qp + (int64_t)(8 * f + i - 1) * stride + k,
+                      E16::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f])));
+    }
+};
+
+// Layout and arithmetic types of each storage form.
+template <int ST>
+struct LayoutOf;
+template <>
+struct LayoutOf<ST_F64> {
+    using L = Plain<E64, false>;
+    using R = double;
+    using RH = double;
+};
+template <>
+struct LayoutOf<ST_F32> {
+    using L = Plain<E32, false>;
+    using R = float;
+    using RH = float;
+};
+template <>
+struct LayoutOf<ST_F16> {
+    using L = Plain<E16, true>;
+    using R = float;
+    using RH = float;
+};
+template <>
+struct LayoutOf<ST_BF16> {
+    using L = Plain<EB16, true>;
+    using R = float;
+    using RH = float;
+};
+template <>
+struct LayoutOf<ST_F16S> {
+    using L = Split16;
+    using R = float;
+    using RH = float;
+};
+template <>
+struct LayoutOf<ST_F32H> {
+    using L = PlainH64;
+    using R = float;
+    using RH = double;
+};
+
+// ---------------------------------------------------------------------------
+// Moment transforms of Eq. (13) on offsets.  d = M q and q = M^-1 d with
+// M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+// ---------------------------------------------------------------------------
+template <typename R>
+LBM_HD void to_moments(const R q[9], R d[9]) {
+    const R s14 = (q[1] + q[2]) + (q[3] + q[4]);
+    const R s58 = (q[5] + q[6]) + (q[7] + q[8]);
+    d[0] = q[0] + s14 + s58;
+    d[1] = -R(4) * q[0] - s14 + R(2) * s58;
+    d[2] = R(4) * q[0] - R(2) * s14 + s58;
+    const R dxd = (q[5] - q[6]) - (q[7] - q[8]);
+    const R dyd = (q[5] + q[6]) - (q[7] + q[8]);
+    d[3] = (q[1] - q[3]) + dxd;
+    d[4] = R(2) * (q[3] - q[1]) + dxd;
+    d[5] = (q[2] - q[4]) + dyd;
+    d[6] = R(2) * (q[4] - q[2]) + dyd;
+    d[7] = (q[1] + q[3]) - (q[2] + q[4]);
+    d[8] = (q[5] + q[7]) - (q[6] + q[8]);
+}
+
+template <typename R>
+LBM_HD void from_moments(const R d[9], R q[9]) {
+    const R a0 = d[0] * (R(1) / R(9));
+    const R a1 = d[1] * (R(1) / R(36));
+    const R a2 = d[2] * (R(1) / R(36));
+    const R a3 = d[3] * (R(1) / R(6));
+    const R a4 = d[4] * (R(1) / R(12));
+    const R a5 = d[5] * (R(1) / R(6));
+    const R a6 = d[6] * (R(1) / R(12));
+    const R a7 = d[7] * R(0.25);
+    const R a8 = d[8] * R(0.25);
+    const R axis = a0 - a1 - R(2) * a2;
+    const R diag = a0 + R(2) * a1 + a2;
+    const R xa = a3 - R(2) * a4, ya = a5 - R(2) * a6;
+    const R xd = a3 + a4, yd = a5 + a6;
+    q[0] = a0 - R(4) * a1 + R(4) * a2;
+    q[1] = axis + xa + a7;
+    q[2] = axis + ya - a7;
+    q[3] = axis - xa + a7;
+    q[4] = axis - ya - a7;
+    q[5] = diag + xd + yd + a8;
+    q[6] = diag - xd + yd - a8;
+    q[7] = diag - xd - yd + a8;
+    q[8] = diag + xd - yd - a8;
+}
+
+template <typename R>
+LBM_HD R sum9(const R q[9]) {
+    return ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7])) + q[8];
+}
+
+// ---------------------------------------------------------------------------
+// Macroscopic values of one node from its post-streaming offsets.
+// ---------------------------------------------------------------------------
+template <typename RH>
+struct Thermo {  // PCM enthalpy field, Eqs. (37)-(39)
+    RH dH, H, Tf, fl;
+};
+template <typename R>
+struct Macro {  // everything the flow and metal collisions need
+    R Tf, fl, dTm, Tm, drho, rho, ux, uy, Gx, Gy;
+};
+
+// Eqs. (38)-(39), branches in the order the paper lists them.
+template <typename RH>
+LBM_HD void eos(const ThermalConst<RH> &t, RH H, RH &T, RH &fl) {
+    if (H <= t.H_fs) {
+        T = H * t.inv_cps;
+        fl = RH(0);
+    } else if (H >= t.H_fl) {
+        T = t.T_fl + (H - t.H_fl) * t.inv_cpl;
+        fl = RH(1);
+    } else {
+        fl = (H - t.H_fs) * t.inv_dH;
+        T = t.T_fs + fl * t.dT_band;
+    }
+}
+
+// Blends qf in place (Eq. 20) and computes everything the collisions need.
+template <typename R, typename RH>
+LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[9], Thermo<RH> &th,
+                   Macro<R> &m) {
+    const ThermalConst<RH> &t = thermal<RH>(c);
+    // Eq. (37), Eqs. (38)-(39)
+    th.dH = sum9(qg);
+    th.H = t.H_ref + th.dH;
+    eos(t, th.H, th.Tf, th.fl);
+    m.Tf = (R)th.Tf;
+    m.fl = (R)th.fl;
+    // Eq. (48)
+    m.dTm = sum9(qh) * c.inv_cpm;
+    m.Tm = c.T_ref + m.dTm;
+    // Eq. (21)
+    m.drho = sum9(qf);
+    m.rho = R(1) + m.drho;
+    // Eq. (20): f = f_l f+ + (1 - f_l) w rho, written on offsets from w rho_0.
+    const R sol = (R(1) - m.fl) * m.drho;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) qf[i] = m.fl * qf[i] + w_of<R>(i) * sol;
+    // Eq. (7): buoyancy along +axis (gravity along -axis).
+    const R G = c.gbeta * (m.Tf - c.T0) * m.fl;
+    m.Gx = c.gaxis == 0 ? G : R(0);
+    m.Gy = c.gaxis == 1 ? G : R(0);
+    // Eq. (24), then the explicit root Eq. (23) with Eq. (25).
+    const R jx = (qf[1] - qf[3]) + ((qf[5] - qf[6]) - (qf[7] - qf[8]));
+    const R jy = (qf[2] - qf[4]) + ((qf[5] + qf[6]) - (qf[7] + qf[8]));
+    const R inv_rho = R(1) / m.rho;
+    const R vx = jx * inv_rho + R(0.5) * c.phi * m.Gx;
+    const R vy = jy * inv_rho + R(0.5) * c.phi * m.Gy;
+    const R vmag = sqrt(vx * vx + vy * vy);
+    const R inv_den = R(1) / (c.l0 + sqrt(c.l0sq + c.l1 * vmag));
+    m.ux = vx * inv_den;
+    m.uy = vy * inv_den;
+}
+
+// Flow collision, Eqs. (14), (16)-(19), on the blended offsets.
+template <typename R>
+LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R q[9]) {
+    R d[9];
+    to_moments(q, d);
+    const R ux = m.ux, uy = m.uy, rho = m.rho;
+    const R uu = ux * ux + uy * uy;
+    const R umag = sqrt(uu);
+    // Eq. (3).
+    const R Fx = -c.drag_lin * ux - c.drag_quad * umag * ux + c.phi * m.Gx;
+    const R Fy = -c.drag_lin * uy - c.drag_quad * umag * uy + c.phi * m.Gy;
+    const R rip = rho * c.inv_phi;
+    R eq[9], S[9];
+    eq[1] = -R(2) * m.drho + R(3) * rip * uu;
+    eq[2] = m.drho - R(3) * rip * uu;
+    eq[3] = rho * ux;
+    eq[4] = -eq[3];
+    eq[5] = rho * uy;
+    eq[6] = -eq[5];
+    eq[7] = rip * (ux * ux - uy * uy);
+    eq[8] = rip * ux * uy;
+    const R uF = ux * Fx + uy * Fy;
+    S[1] = R(6) * rip * uF;
+    S[2] = -S[1];
+    S[3] = rho * Fx;
+    S[4] = -S[3];
+    S[5] = rho * Fy;
+    S[6] = -S[5];
+    S[7] = R(2) * rip * (ux * Fx - uy * Fy);
+    S[8] = rip * (ux * Fy + uy * Fx);
+    d[0] = m.drho;
+#pragma unroll
+    for (int k = 1; k < 9; ++k) d[k] = d[k] - c.s[k] * (d[k] - eq[k]) + c.s_half[k] * S[k];
+    from_moments(d, q);
+}
+
+// PCM enthalpy collision, Eqs. (32), (34)-(35).
+template <typename R, typename RH>
+LBM_HD void collide_pcm(const CavityConst<R> &c, const Thermo<RH> &th, const Macro<R> &m, RH S_pcm,
+                        RH q[9]) {
+    const ThermalConst<RH> &t = thermal<RH>(c);
+    RH d[9];
+    to_moments(q, d);
+    const RH dT = th.Tf - t.T_ref;
+    const RH jT = t.c_pl * th.Tf * t.inv_phi;
+    RH eq[9];
+    eq[0] = th.dH;
+    eq[1] = -RH(4) * th.dH + RH(2) * t.c_fref * dT;
+    eq[2] = RH(4) * th.dH - RH(3) * t.c_fref * dT;
+    eq[3] = jT * (RH)m.ux;
+    eq[4] = -eq[3];
+    eq[5] = jT * (RH)m.uy;
+    eq[6] = -eq[5];
+    eq[7] = RH(0);
+    eq[8] = RH(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = d[k] - t.zeta[k] * (d[k] - eq[k]);
+    d[0] += S_pcm;
+    d[1] -= RH(2) * S_pcm;
+    d[2] += S_pcm;
+    from_moments(d, q);
+}
+
+// Metal-foam collision, Eqs. (43), (45)-(46).
+template <typename R>
+LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal, R q[9]) {
+    R d[9];
+    to_moments(q, d);
+    R eq[9];
+    eq[0] = c.c_pm * m.dTm;
+    eq[1] = (-R(4) * c.c_pm + R(2) * c.c_mref) * m.dTm;
+    eq[2] = (R(4) * c.c_pm - R(3) * c.c_mref) * m.dTm;
+#pragma unroll
+    for (int k = 3; k < 9; ++k) eq[k] = R(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = d[k] - c.eta[k] * (d[k] - eq[k]);
+    d[0] += S_metal;
+    d[1] -= R(2) * S_metal;
+    d[2] += S_metal;
+    from_moments(d, q);
+}
+
+// Non-equilibrium extrapolation for wall node (x, y), applied in place to
+// the partner's pulled offsets (Eq. 52 with wall velocity 0; thermal
+// analogues with the isothermal or zero-gradient wall values).
+template <typename R, typename RH>
+LBM_HD void reconstruct_wall(const CavityConst<R> &c, int x, R qf[9], RH qg[9], R qh[9]) {
+    const ThermalConst<RH> &t = thermal<RH>(c);
+    R tf[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) tf[i] = qf[i];
+    Thermo<RH> pt;
+    Macro<R> p;
+    macros(c, tf, qg, qh, pt, p);
+    RH Tb, Hb;
+    R Tmb;
+    const bool vertical = !c.periodic && (x == 0 || x == c.nx - 1);
+    if (vertical) {
+        const bool hot = (x == 0);
+        Tb = hot ? t.T_hot : t.T_cold;
+        Hb = hot ? t.H_hot : t.H_cold;
+        Tmb = hot ? c.T_hot : c.T_cold;
+    } else {
+        Tb = pt.Tf;
+        Hb = pt.H;
+        Tmb = p.Tm;
+    }
+    const R uu = p.ux * p.ux + p.uy * p.uy;
+    const RH dTg = Tb - pt.Tf;
+    const R dTh = Tmb - p.Tm;
+    const RH jT = RH(3) * t.c_pl * pt.Tf * t.inv_phi;
+    qf[0] += -w_of<R>(0) * p.rho * (-R(1.5) * uu * c.inv_phi);
+    qg[0] += (Hb - pt.H) - RH(5) / RH(9) * t.c_fref * dTg;
+    qh[0] += (c.c_pm - R(5) / R(9) * c.c_mref) * dTh;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const R eu = R(ex_of(i)) * p.ux + R(ey_of(i)) * p.uy;
+        // f^eq(rho, 0) - f^eq(rho, u) from Eq. (27)
+        qf[i] += -w_of<R>(i) * p.rho * (R(3) * eu + R(4.5) * eu * eu * c.inv_phi - R(1.5) * uu * c.inv_phi);
+        // g^eq(H_b, T_b, 0) - g^eq(H, T, u) from Eq. (40)
+        qg[i] += w_of<RH>(i) * (t.c_fref * dTg - jT * (RH)eu);
+        // h^eq(T_mb) - h^eq(T_m) from Eq. (49)
+        qh[i] += w_of<R>(i) * c.c_mref * dTh;
+    }
+}
+
+// Wall classification and the node whose populations a node pulls: its own
+// neighbourhood, or its interior partner's for a wall node (inward normal
+// neighbour, diagonal at corners).
+struct NodeGeom {
+    bool wall, near_x, near_y;
+    int sx, sy;
+};
+
+template <typename R>
+LBM_HD NodeGeom geometry(const CavityConst<R> &c, int x, int y, bool pull) {
+    NodeGeom g;
+    const int nx = c.nx, ny = c.ny;
+    const bool vwall = !c.periodic && (x == 0 || x == nx - 1);
+    const bool hwall = (y == 0 || y == ny - 1);
+    g.wall = vwall || hwall;
+    g.sx = x;
+    g.sy = y;
+    if (pull && g.wall) {
+        if (!c.periodic) g.sx = (x == 0) ? 1 : ((x == nx - 1) ? nx - 2 : x);
+        g.sy = (y == 0) ? 1 : ((y == ny - 1) ? ny - 2 : y);
+    }
+    g.near_x = !g.wall && !c.periodic && (x == 1 || x == nx - 2);
+    g.near_y = !g.wall && (y == 1 || y == ny - 2);
+    return g;
+}
+
+// Offsets of the node's post-streaming populations: pulled from the
+// neighbours (Eqs. 15, 33, 44), or read in place for the initial state.
+template <class Lay, typename R, typename RH, bool PULL>
+LBM_HD void gather(const CavityConst<R> &c, const void *src, int64_t stride, const NodeGeom &g, int x,
+                   int y, R qf[9], RH qg[9], R qh[9]) {
+    const int nx = c.nx;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int idx = y * nx + x;
+        if (PULL) {
+            int px = g.sx - ex_of(i);
+            if (c.periodic) px = px < 0 ? px + nx : (px >= nx ? px - nx : px);
+            idx = (g.sy - ey_of(i)) * nx + px;
+        }
+        const int64_t k = c.node0 + idx;
+        qf[i] = Lay::template load<R>(src, stride, 0, i, k, c);
+        qg[i] = Lay::template load<RH>(src, stride, 1, i, k, c);
+        qh[i] = Lay::template load<R>(src, stride, 2, i, k, c);
+    }
+}
+
+// Energy and mass carried by direction i of the given offsets (FP64).
+template <typename R, typename RH>
+LBM_HD void link_content(const CavityConst<R> &c, int i, const R qf[9], const RH qg[9], const R qh[9],
+                         double &e, double &m) {
+    e = c.we * (c.g_ref[i] + (double)qg[i]) + c.wm * (c.h_ref[i] + (double)qh[i]);
+    m = (double)w_of<double>(i) + (double)qf[i];
+}
+
+// One node's full time step.
+template <class Lay, typename R, typename RH, bool PULL>
+LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
+                      const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
+                      int x, int y) {
+    const int nx = c.nx, ny = c.ny;
+    const NodeGeom g = geometry(c, x, y, PULL);
+    R qf[9], qh[9];
+    RH qg[9];
+    gather<Lay, R, RH, PULL>(c, src, stride, g, x, y, qf, qg, qh);
+    const int64_t k = c.node0 + (int64_t)y * nx + x;
+    const R sr_prev = sr_src[k];
+
+    // Wall tallies: an interior node next to a wall owns one slot per wall it
+    // touches (x: the vertical wall, y: the horizontal one).
+    double xE = 0.0, xM = 0.0, yE = 0.0, yM = 0.0;
+    if (PULL && (g.near_x || g.near_y)) {
+        // inflow: populations pulled from wall nodes (post-collision of the
+        // previous step)
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int px = x - ex_of(i), py = y - ey_of(i);
+            const bool onx = !c.periodic && (px == 0 || px == nx - 1);
+            const bool ony = (py == 0 || py == ny - 1);
+            if (onx || ony) {
+                double e, mm;
+                link_content(c, i, qf, qg, qh, e, mm);
+                if (onx) {
+                    xE += e;
+                    xM += mm;
+                } else {
+                    yE += e;
+                    yM += mm;
+                }
+            }
+        }
+    }
+
+    if (PULL && g.wall) reconstruct_wall(c, x, qf, qg, qh);
+
+    Thermo<RH> th;
+    Macro<R> m;
+    macros(c, qf, qg, qh, th, m);
+    collide_flow(c, m, qf);
+    // Eqs. (36), (47) with the backward difference of Remark III.
+    const RH srf = (RH)c.hv_f * ((RH)m.Tm - th.Tf);
+    const R srm = c.hv_m * (m.Tf - m.Tm);
+    const R srm_prev = -c.sr_ratio * sr_prev;
+    const RH S_pcm = srf + RH(0.5) * (srf - (RH)sr_prev);
+    const R S_metal = srm + R(0.5) * (srm - srm_prev);
+    collide_pcm(c, th, m, S_pcm, qg);
+    collide_metal(c, m, S_metal, qh);
+
+    if (g.near_x || g.near_y) {
+        // outflow: post-collision populations aimed at wall nodes
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int tx = x + ex_of(i), ty = y + ey_of(i);
+            const bool onx = !c.periodic && (tx == 0 || tx == nx - 1);
+            const bool ony = (ty == 0 || ty == ny - 1);
+            if (onx || ony) {
+                double e, mm;
+                link_content(c, i, qf, qg, qh, e, mm);
+                if (onx) {
+                    xE -= e;
+                    xM -= mm;
+                } else {
+                    yE -= e;
+                    yM -= mm;
+                }
+            }
+        }
+        if (g.near_x) {
+            const int64_t slot = c.acc0 + (x == 1 ? y : ny + y);
+            acc[2 * slot] += xE;
+            acc[2 * slot + 1] += xM;
+        }
+        if (g.near_y) {
+            const int64_t slot = c.acc0 + 2 * ny + (y == 1 ? x : nx + x);
+            acc[2 * slot] += yE;
+            acc[2 * slot + 1] += yM;
+        }
+    }
+
+    const ThermalConst<RH> &t = thermal<RH>(c);
+    Lay::template store<R>(dst, stride, 0, qf, m.drho, k, c);
+    Lay::template store<RH>(dst, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);
+    Lay::template store<R>(dst, stride, 2, qh, c.c_mref * m.dTm, k, c);
+    sr_dst[k] = (R)srf;
+}
+
+// Macroscopic fields of one node (post-streaming state) plus its
+// contributions to the diagnostics partial sums.
+template <class Lay, typename R, typename RH>
+LBM_HD void macro_node(const CavityConst<R> &c, const void *src, int64_t stride, bool raw, int x, int y,
+                       double out[6], double v[NPART]) {
+    const int nx = c.nx, ny = c.ny;
+    const NodeGeom g = geometry(c, x, y, !raw);
+    R qf[9], qh[9];
+    RH qg[9];
+    if (raw) gather<Lay, R, RH, false>(c, src, stride, g, x, y, qf, qg, qh);
+    else gather<Lay, R, RH, true>(c, src, stride, g, x, y, qf, qg, qh);
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) finite = finite && isfinite(qf[i]) && isfinite(qg[i]) && isfinite(qh[i]);
+    // inflow of the last step through the wall links (not yet tallied)
+    if (!raw && !g.wall) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int px = x - ex_of(i), py = y - ey_of(i);
+            const bool onx = !c.periodic && (px == 0 || px == nx - 1);
+            const bool ony = (py == 0 || py == ny - 1);
+            if (onx || ony) {
+                const int w = onx ? (px == 0 ? W_LEFT : W_RIGHT) : (py == 0 ? W_BOTTOM : W_TOP);
+                double e, mm;
+                link_content(c, i, qf, qg, qh, e, mm);
+                v[P_INE0] += w == 0 ? e : 0.0;
+                v[P_INE1] += w == 1 ? e : 0.0;
+                v[P_INE2] += w == 2 ? e : 0.0;
+                v[P_INE3] += w == 3 ? e : 0.0;
+                v[P_INM0] += w == 0 ? mm : 0.0;
+                v[P_INM1] += w == 1 ? mm : 0.0;
+                v[P_INM2] += w == 2 ? mm : 0.0;
+                v[P_INM3] += w == 3 ? mm : 0.0;
+            }
+        }
+    }
+    if (!raw && g.wall) reconstruct_wall(c, x, qf, qg, qh);
+    double sg = 0.0, sh = 0.0, sf = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        sg += c.g_ref[i] + (double)qg[i];
+        sh += c.h_ref[i] + (double)qh[i];
+        sf += (double)w_of<double>(i) + (double)qf[i];
+    }
+    Thermo<RH> th;
+    Macro<R> m;
+    macros(c, qf, qg, qh, th, m);
+    out[0] = (double)m.ux;
+    out[1] = (double)m.uy;
+    out[2] = (double)th.Tf;
+    out[3] = (double)m.Tm;
+    out[4] = (double)th.fl;
+    out[5] = (double)m.rho;
+    if (!finite) v[P_NF] = 1.0;
+    if (!g.wall) {
+        v[P_FL] = (double)th.fl;
+        // phi rho_l H + (1-phi) rho_m c_pm T_m and rho, from the offsets
+        v[P_E] = c.we * sg + c.wm * sh;
+        v[P_M] = sf;
+        v[P_DT] = fabs((double)th.Tf - (double)m.Tm);
+        v[P_U] = sqrt((double)m.ux * (double)m.ux + (double)m.uy * (double)m.uy);
+    }
+}
+
+// Initial state of one node: equilibria at rest (Eqs. 27, 40, 49) at the
+// given temperatures, stored as offsets; the previous-step source equals the
+// current one.
+template <class Lay, typename R, typename RH>
+LBM_HD void init_node(const CavityConst<R> &c, void *dst, int64_t stride, R *sr, int x, int y, double Tf,
+                      double Tm) {
+    const ThermalConst<double> &t = c.td;
+    const int nx = c.nx;
+    if (!c.periodic && x == 0) Tf = Tm = t.T_hot;
+    if (!c.periodic && x == nx - 1) Tf = Tm = t.T_cold;
+    // inverse of Eq. (38) (a tie at the solidus goes to the solid branch)
+    double H;
+    if (Tf <= t.T_fs) H = Tf / t.inv_cps;
+    else if (Tf >= t.T_fl) H = (Tf - t.T_fl) / t.inv_cpl + t.H_fl;
+    else H = t.H_fs + (Tf - t.T_fs) / (t.T_fl - t.T_fs) * (t.H_fl - t.H_fs);
+    const double dT = Tf - t.T_ref, dTm = Tm - t.T_ref;
+    const double dH = H - t.H_ref;
+    const double cf = t.c_fref, cm = c.c_mref, cpm = c.c_pm;
+    R qf[9], qh[9];
+    RH qg[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double wi = w_of<double>(i);
+        qf[i] = R(0);
+        qg[i] = (RH)(i == 0 ? dH - 5.0 / 9.0 * cf * dT : wi * cf * dT);
+        qh[i] = (R)(i == 0 ? (cpm - 5.0 / 9.0 * cm) * dTm : wi * cm * dTm);
+    }
+    const int64_t k = c.node0 + (int64_t)y * nx + x;
+    Lay::template store<R>(dst, stride, 0, qf, R(0), k, c);
+    Lay::template store<RH>(dst, stride, 1, qg, (RH)(cf * dT), k, c);
+    Lay::template store<R>(dst, stride, 2, qh, (R)(cm * dTm), k, c);
+    sr[k] = (R)((double)c.hv_f * (Tm - Tf));
+}
+
+}  // namespace lbm

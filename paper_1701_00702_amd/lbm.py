@@ -16,11 +16,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmpcm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE, LBM_EIO = 0, -1, -2, -3, -4, -5, -6
-LBM_F64, LBM_F32, LBM_F16_OFFSET, LBM_BF16_OFFSET = 0, 1, 2, 3
-PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_OFFSET, "bf16": LBM_BF16_OFFSET}
-ELEM_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16_OFFSET: 2, LBM_BF16_OFFSET: 2}
-ELEM_DTYPE = {LBM_F64: np.float64, LBM_F32: np.float32, LBM_F16_OFFSET: np.float16,
-              LBM_BF16_OFFSET: np.uint16}
+LBM_F64, LBM_F32, LBM_F16_OFFSET, LBM_BF16_OFFSET, LBM_F16_SPLIT, LBM_F32_H64 = 0, 1, 2, 3, 4, 5
+PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_OFFSET, "bf16": LBM_BF16_OFFSET,
+              "f16split": LBM_F16_SPLIT, "f32h64": LBM_F32_H64}
+STATE_BYTES_PER_NODE = {LBM_F64: 216, LBM_F32: 108, LBM_F16_OFFSET: 54, LBM_BF16_OFFSET: 54,
+                        LBM_F16_SPLIT: 72, LBM_F32_H64: 112}
 
 
 class LbmError(RuntimeError):
@@ -266,9 +266,10 @@ def lbm_load(h: int, path: str):
 
 
 def lbm_copy_state(h: int, cavity: int, shape, precision) -> np.ndarray:
+    """Raw stored bytes of one cavity (uint8, planes in storage order)."""
     ny, nx = shape
     prec = _prec(precision)
-    a = np.empty((27, ny, nx), dtype=ELEM_DTYPE[prec])
+    a = np.empty(STATE_BYTES_PER_NODE[prec] * ny * nx, dtype=np.uint8)
     _check(_lib.lbm_copy_state(h, cavity, a.ctypes.data_as(ctypes.c_void_p), a.nbytes))
     return a
 
