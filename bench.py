@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=[None] + list(BYTES_PER_NODE))
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--npt", type=int, default=1)
     ap.add_argument("--xcd", type=int, default=1)
     ap.add_argument("--persistent", type=int, default=0)

@@ -22,12 +22,15 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
-    """Compile every source to an object in parallel, then link."""
+def build(verbose: bool = False, extra_flags=(), out: str = LIB) -> str:
+    """Compile every source to an object in parallel, then link.  extra_flags
+    (e.g. -DLBM_NT_LOADS=0) and out build variants of the library."""
     objs, procs = [], []
+    objdir = CSRC if out == LIB else os.path.dirname(os.path.abspath(out))
+    tag = "" if out == LIB else "." + os.path.basename(out)
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
-        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", src, "-o", obj]
+        obj = os.path.join(objdir, os.path.basename(src) + tag + ".o")
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + list(extra_flags) + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
         procs.append(subprocess.Popen(cmd))
@@ -35,13 +38,13 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -309,10 +309,14 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
         pl.node0.push_back(pl.nodes);
         pl.acc0.push_back(pl.slots);
         const int64_t nn = (int64_t)p[c].nx * p[c].ny;
-        pl.nodes += nn;
+        // each cavity starts on a 64-node boundary, so aligned tiles store
+        // whole cache lines
+        pl.nodes += (nn + 63) & ~(int64_t)63;
         pl.slots += 2 * ((int64_t)p[c].nx + p[c].ny);
         pl.max_nodes = std::max(pl.max_nodes, nn);
-        tiles += (int64_t)p[c].ny * ((p[c].nx + 63) / 64);
+        // interior rows and the wall ring, in tiles of at least 64 nodes
+        const int64_t ring = 2 * (int64_t)p[c].nx;
+        tiles += ((int64_t)p[c].nx * (p[c].ny - 2) + 63) / 64 + 1 + (ring + 63) / 64;
     }
     if (pl.nodes >= ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "more than 2^31 nodes in total");
     if (tiles >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
@@ -367,8 +371,8 @@ struct lbm_handle {
     int cur = 0;
     int64_t step = 0;
     std::vector<double> E0, M0;
-    lbm_launch_config lc{256, 1, 1, 0};
-    std::vector<Tile> tiles;             // host copy, sorted by cavity, row, x
+    lbm_launch_config lc{512, 1, 1, 0};
+    std::vector<Tile> tiles;             // host copy, sorted by cavity: interior, then ring
     std::vector<int> cav_tile0, cav_ntiles;
     int graph_chunk = 32;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -404,8 +408,12 @@ lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
     for (int c = 0; c < h->n; ++c) {
         h->cav_tile0[c] = (int)h->tiles.size();
         const int nx = h->params[c].nx, ny = h->params[c].ny;
-        for (int y = 0; y < ny; ++y)
-            for (int x0 = 0; x0 < nx; x0 += tw) h->tiles.push_back(Tile{c, y, x0, std::min(nx, x0 + tw)});
+        const int ring = 2 * nx;  // bottom and top rows
+        // interior tiles start on 64-node boundaries of the cavity (which is
+        // 64-aligned in the packed index); lanes on row 0 idle
+        for (int k0 = (nx / 64) * 64; k0 < nx * (ny - 1); k0 += tw)
+            h->tiles.push_back(Tile{c, TILE_INTERIOR, k0, std::min(nx * (ny - 1), k0 + tw)});
+        for (int r0 = 0; r0 < ring; r0 += tw) h->tiles.push_back(Tile{c, TILE_WALL, r0, std::min(ring, r0 + tw)});
         h->cav_ntiles[c] = (int)h->tiles.size() - h->cav_tile0[c];
     }
     if ((int)h->tiles.size() > h->pl.max_tiles) return fail(LBM_EINVAL, "tile table overflow");

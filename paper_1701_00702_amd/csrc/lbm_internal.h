@@ -53,9 +53,14 @@ struct CavityConst {
     double T_init;
 };
 
-// A tile is a run of nodes [x0, x1) on row y of one cavity.
+// A tile is a run [k0, k1) of one cavity's nodes.  Row tiles (kind 0)
+// index the rows 1..ny-2 linearly, k = y * nx + x, and start on 64-node
+// boundaries (lanes of row 0 idle); the wall columns are part of their
+// rows.  Wall tiles (kind 1) index the bottom and top rows, r in [0, 2 nx).
+// Tiles never straddle cavities.
+enum { TILE_INTERIOR = 0, TILE_WALL = 1 };
 struct Tile {
-    int32_t cav, y, x0, x1;
+    int32_t cav, kind, k0, k1;
 };
 
 struct StepLaunch {

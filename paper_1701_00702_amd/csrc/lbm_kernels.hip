@@ -75,10 +75,27 @@ __global__ __launch_bounds__(512) void step_kernel(const void *__restrict__ src,
     for (int t = b; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
         const CavityConst<R> &c = cav[tl.cav];
+        if (tl.kind == TILE_INTERIOR) {
 #pragma unroll
-        for (int j = 0; j < NPT; ++j) {
-            const int x = tl.x0 + (int)threadIdx.x + j * (int)blockDim.x;
-            if (x < tl.x1) step_node<Lay, R, RH, PULL>(c, src, dst, stride, sr_src, sr_dst, acc, x, tl.y);
+            for (int j = 0; j < NPT; ++j) {
+                const int k = tl.k0 + (int)threadIdx.x + j * (int)blockDim.x;
+                if (k < tl.k1) {
+                    const int y = k / c.nx, x = k - y * c.nx;
+                    // whole rows: the wall columns ride along (each stored
+                    // cache line then has one writer)
+                    if (y >= 1) step_node<Lay, R, RH, PULL, NODE_ANY>(c, src, dst, stride, sr_src, sr_dst, acc, x, y);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                const int r = tl.k0 + (int)threadIdx.x + j * (int)blockDim.x;
+                if (r < tl.k1) {
+                    int x, y;
+                    ring_node(c, r, x, y);
+                    step_node<Lay, R, RH, PULL, NODE_WALL>(c, src, dst, stride, sr_src, sr_dst, acc, x, y);
+                }
+            }
         }
     }
 }

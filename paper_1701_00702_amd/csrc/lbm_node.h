@@ -60,12 +60,19 @@ LBM_HD const ThermalConst<RH> &thermal(const CavityConst<R> &c) {
 }
 
 // ---------------------------------------------------------------------------
-// Streaming loads/stores (non-temporal on the GPU: every value is touched
-// once per step) and element codecs.
+// Streaming loads/stores and element codecs.  Every population is read and
+// written once per step; whether the GPU accesses carry the non-temporal
+// hint is a build option (LBM_NT_LOADS, LBM_NT_STORES).
 // ---------------------------------------------------------------------------
+#ifndef LBM_NT_LOADS
+#define LBM_NT_LOADS 0
+#endif
+#ifndef LBM_NT_STORES
+#define LBM_NT_STORES 1
+#endif
 template <typename T>
 LBM_HD T ld_stream(const T *p) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if defined(__HIP_DEVICE_COMPILE__) && LBM_NT_LOADS
     return __builtin_nontemporal_load(p);
 #else
     return *p;
@@ -73,7 +80,7 @@ LBM_HD T ld_stream(const T *p) {
 }
 template <typename T>
 LBM_HD void st_stream(T *p, T v) {
-#if defined(__HIP_DEVICE_COMPILE__)
+#if defined(__HIP_DEVICE_COMPILE__) && LBM_NT_STORES
     __builtin_nontemporal_store(v, p);
 #else
     *p = v;
@@ -501,6 +508,35 @@ LBM_HD NodeGeom geometry(const CavityConst<R> &c, int x, int y, bool pull) {
     return g;
 }
 
+// Node kinds a kernel instantiation handles: interior nodes only, wall
+// nodes only, or either (decided per node).
+enum { NODE_INTERIOR = 0, NODE_WALL = 1, NODE_ANY = 2 };
+
+template <typename R, int KIND>
+LBM_HD NodeGeom geometry_of(const CavityConst<R> &c, int x, int y, bool pull) {
+    NodeGeom g = geometry(c, x, y, pull);
+    if (KIND == NODE_INTERIOR) g.wall = false;
+    if (KIND == NODE_WALL) {
+        g.wall = true;
+        g.near_x = g.near_y = false;
+    }
+    return g;
+}
+
+// Position of wall node r of the bottom and top rows (the wall columns are
+// handled with their rows).
+template <typename R>
+LBM_HD void ring_node(const CavityConst<R> &c, int r, int &x, int &y) {
+    const int nx = c.nx;
+    if (r < nx) {
+        x = r;
+        y = 0;
+    } else {
+        x = r - nx;
+        y = c.ny - 1;
+    }
+}
+
 // Offsets of the node's post-streaming populations: pulled from the
 // neighbours (Eqs. 15, 33, 44), or read in place for the initial state.
 template <class Lay, typename R, typename RH, bool PULL>
@@ -530,13 +566,15 @@ LBM_HD void link_content(const CavityConst<R> &c, int i, const R qf[9], const RH
     m = (double)w_of<double>(i) + (double)qf[i];
 }
 
-// One node's full time step.
-template <class Lay, typename R, typename RH, bool PULL>
+// One node's full time step.  KIND selects which of the interior and wall
+// code paths this instantiation carries (the caller guarantees the node is
+// of that kind).
+template <class Lay, typename R, typename RH, bool PULL, int KIND = NODE_ANY>
 LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
                       const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
                       int x, int y) {
     const int nx = c.nx, ny = c.ny;
-    const NodeGeom g = geometry(c, x, y, PULL);
+    const NodeGeom g = geometry_of<R, KIND>(c, x, y, PULL);
     R qf[9], qh[9];
     RH qg[9];
     gather<Lay, R, RH, PULL>(c, src, stride, g, x, y, qf, qg, qh);

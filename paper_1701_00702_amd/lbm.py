@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbmpcm.so")
+# LBMPCM_LIBRARY selects another build of the same sources (e.g. a variant
+# compiled with other cache hints); the default is the in-tree library.
+LIB_PATH = os.environ.get("LBMPCM_LIBRARY") or os.path.join(_HERE, "liblbmpcm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE, LBM_EIO = 0, -1, -2, -3, -4, -5, -6
 LBM_F64, LBM_F32, LBM_F16_OFFSET, LBM_BF16_OFFSET, LBM_F16_SPLIT, LBM_F32_H64 = 0, 1, 2, 3, 4, 5
