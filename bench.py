@@ -31,7 +31,7 @@ BYTES_PER_NODE = {"f64": 448, "f32": 224, "f32h64": 232, "f16split": 152, "f16":
 PEAK_HBM_GBPS = 8000.0
 METRIC = "MLUPS (3 coupled MRT fields) + achieved HBM GB/s vs peak; FP16-store vs FP32"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1701_00702_amd", "csrc", n)
-                  for n in ("lbm_kernels.hip", "lbm_internal.h")] + \
+                  for n in ("lbm_kernels.hip", "lbm_node.h", "lbm_internal.h", "lbm_api.hip")] + \
     [os.path.join(ROOT, "paper_1701_00702_amd", "build.py")]
 
 

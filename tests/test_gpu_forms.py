@@ -21,7 +21,7 @@ from test_gpu_parity import diag_errors, field_errors, run_pair
 
 pytestmark = pytest.mark.gpu
 
-BENCH_LAUNCH = dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0)
+BENCH_LAUNCH = dict(block=512, nodes_per_thread=1, xcd_remap=1, persistent=0)
 
 
 @pytest.fixture(scope="module")
