@@ -25,6 +25,7 @@ PARAM_FIELDS = (
     "porosity", "Ra", "Pr", "Da", "Ste", "k_ratio", "cap_ratio", "Nu_i",
     "F_phi", "dp_over_L", "k_f", "cf_ref", "cm_ref", "J",
     "T_hot", "T_cold", "T_init", "T_solidus", "T_liquidus",
+    "thermal_lattice", "thermal_collision", "varpi", "zeta_e", "wall_type", "wall_T", "L_char",
 )
 
 _DEFAULTS = dict(
@@ -38,6 +39,15 @@ _DEFAULTS = dict(
     # Mushy band: solidus at the cold/initial temperature, liquidus 0.002 above,
     # so the initial state T = 0 sits exactly at the solidus (solid).
     T_solidus=0.0, T_liquidus=0.002,
+    thermal_lattice=9,      # 9: D2Q9 thermal fields; 5: D2Q5 (Appendix B)
+    thermal_collision=0,    # 0: MRT; 1: BGK thermal collisions (Sec. V A)
+    varpi=0.0,              # <= 0: 2/3 (D2Q5 only)
+    zeta_e=0.0,             # <= 0: zeta_e = 2 - zeta_alpha (Eq. 53)
+    wall_type=(0, 0, 0, 0),  # left, right, bottom, top; 0: the cavity's own
+                             # (hot left, cold right, adiabatic top/bottom),
+                             # 1: isothermal at wall_T, 2: adiabatic
+    wall_T=(0.0, 0.0, 0.0, 0.0),
+    L_char=0.0,             # <= 0: nx - 1 (periodic channel: ny - 1)
 )
 
 
@@ -98,6 +108,23 @@ def case_p1():
                     T_hot=1.0, T_cold=0.0, T_init=0.0,
                     T_solidus=0.299, T_liquidus=0.301)
     return p, 90000, 0, "f64"
+
+
+def case_corner(n=200):
+    """Conduction-induced solidification in a corner (Sec. IV A): liquid PCM
+    at T_i = 0.3 in an n x n box, the left and bottom walls lowered to
+    T_c = -1 (isothermal), the right and top walls adiabatic (far field of
+    the semi-infinite domain), no flow (Ra = 0), L = n/2, lambda = 10,
+    St = 4, k_f = 0.01, c_f,ref = 0.5 c_pf, band [-0.05, 0.05] around
+    T_melt = 0, H_v = 5.9.  Runs to Fo = 0.02 (20 000 steps at n = 200)."""
+    L = n / 2.0
+    p = make_params(nx=n, ny=n, porosity=0.8, Ra=0.0, Pr=1.0, Da=1.0, Ste=4.0,
+                    k_ratio=10.0, cap_ratio=1.0, Nu_i=5.9, F_phi=0.068, k_f=0.01,
+                    cf_ref=0.5, cm_ref=1.0, T_hot=0.0, T_cold=-1.0, T_init=0.3,
+                    T_solidus=-0.05, T_liquidus=0.05, wall_type=(1, 2, 1, 2),
+                    wall_T=(-1.0, 0.0, -1.0, 0.0), L_char=L)
+    steps = int(round(0.02 * L * L / 0.01))
+    return p, steps, 0, "f64"
 
 
 def case_c5(n_cavities=256, seed=7):

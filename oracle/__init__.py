@@ -50,6 +50,8 @@ class OracleParams(ctypes.Structure):
         ("T_fl", ctypes.c_double), ("T_hot", ctypes.c_double), ("T_cold", ctypes.c_double),
         ("k_f", ctypes.c_double), ("k_m", ctypes.c_double), ("L", ctypes.c_double),
         ("s", ctypes.c_double * Q), ("zeta", ctypes.c_double * Q), ("eta", ctypes.c_double * Q),
+        ("qt", ctypes.c_int), ("varpi", ctypes.c_double), ("wall_type", ctypes.c_int * 4),
+        ("wall_T", ctypes.c_double * 4),
     ]
 
 
@@ -89,6 +91,9 @@ def load():
     lib.oracle_feq.argtypes = [ctypes.c_double] * 4 + [dp]
     lib.oracle_geq.argtypes = [ctypes.c_double] * 7 + [dp]
     lib.oracle_heq.argtypes = [ctypes.c_double] * 3 + [dp]
+    lib.oracle_geq5.argtypes = [ctypes.c_double] * 8 + [dp]
+    lib.oracle_heq5.argtypes = [ctypes.c_double] * 4 + [dp]
+    lib.oracle_lattice5.argtypes = [dp, dp]
     lib.oracle_eos.argtypes = [P, ctypes.c_double, dp, dp]
     lib.oracle_enthalpy_of_T.argtypes = [P, ctypes.c_double]
     lib.oracle_enthalpy_of_T.restype = ctypes.c_double
@@ -124,6 +129,13 @@ def make_struct(lp: dict, window=None) -> OracleParams:
         arr = getattr(s, k)
         for i, v in enumerate(lp[k]):
             arr[i] = float(v)
+    s.qt = int(lp.get("qt", 9))
+    s.varpi = float(lp.get("varpi", 0.0))
+    wt = lp.get("wall_type", [1, 1, 2, 2])
+    wT = lp.get("wall_T", [lp["T_hot"], lp["T_cold"], 0.0, 0.0])
+    for w in range(4):
+        s.wall_type[w] = int(wt[w])
+        s.wall_T[w] = float(wT[w])
     return s
 
 
@@ -200,6 +212,26 @@ def lattice_tables():
     Minv = np.zeros(Q * Q)
     lib.oracle_lattice(ex, ey, _ptr(w), _ptr(M), _ptr(Minv))
     return np.array(ex[:]), np.array(ey[:]), w, M.reshape(Q, Q), Minv.reshape(Q, Q)
+
+
+def lattice5_tables():
+    """D2Q5 transformation matrix (Eq. B1) and its numerical inverse."""
+    M = np.zeros(25)
+    Minv = np.zeros(25)
+    load().oracle_lattice5(_ptr(M), _ptr(Minv))
+    return M.reshape(5, 5), Minv.reshape(5, 5)
+
+
+def geq5(H, T, ux, uy, phi, c_fref, c_pl, varpi):
+    out = np.zeros(5)
+    load().oracle_geq5(H, T, ux, uy, phi, c_fref, c_pl, varpi, _ptr(out))
+    return out
+
+
+def heq5(T_m, c_pm, c_mref, varpi):
+    out = np.zeros(5)
+    load().oracle_heq5(T_m, c_pm, c_mref, varpi, _ptr(out))
+    return out
 
 
 def feq(rho, ux, uy, phi):

@@ -35,6 +35,13 @@
  * isothermal value of their vertical wall; adiabatic walls copy the partner's
  * temperature; the source derivative is zero at the first step; the
  * liquid fraction of the current step enters the blend and the buoyancy.
+ *
+ * Variants of the thermal fields: the D2Q9 MRT models of Sec. III B/C, the
+ * D2Q5 MRT models of Appendix B (Eqs. B1-B5, weight parameter varpi), and,
+ * through the relaxation-rate tables the caller passes, the BGK thermal
+ * models of Sec. V A (every rate 1/tau) and other zeta_e values (Sec. V D).
+ * Each wall is isothermal at a given temperature or adiabatic; at a corner
+ * an isothermal vertical wall wins, then an isothermal horizontal wall.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -61,7 +68,19 @@ static const double MM[Q][Q] = {
     {0, 0, 0, 0, 0, 1, -1, 1, -1},
 };
 
+/* D2Q5 transformation matrix, Eq. (B1); its velocities are the first five
+ * of Eq. (11). */
+#define Q5 5
+static const double M5[Q5][Q5] = {
+    {1, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0},
+    {0, 0, 1, 0, -1},
+    {0, 1, 1, 1, 1},
+    {0, 1, -1, 1, -1},
+};
+
 enum { W_NONE = -1, W_LEFT = 0, W_RIGHT = 1, W_BOTTOM = 2, W_TOP = 3 };
+enum { WALL_ISOTHERMAL = 1, WALL_ADIABATIC = 2 };
 
 typedef struct {
     /* geometry: a window [gx0, gx0+nx) x [gy0, gy0+ny) of an NX x NY cavity */
@@ -77,6 +96,12 @@ typedef struct {
     double s[Q];        /* flow relaxation rates, Eq. (16) order */
     double zeta[Q];     /* PCM relaxation rates, Theta in Eq. (31) */
     double eta[Q];      /* metal relaxation rates, Q in Eq. (42) */
+    /* thermal lattice: 9 (Sec. III) or 5 (Appendix B; zeta and eta then
+     * hold the five rates of Theta and Q in the moment order of Eq. B1) */
+    int qt;
+    double varpi;       /* D2Q5 weight parameter, Eq. (B2) */
+    int wall_type[4];   /* left, right, bottom, top: isothermal or adiabatic */
+    double wall_T[4];   /* temperature of the isothermal walls */
 } oracle_params;
 
 typedef struct {
@@ -94,6 +119,7 @@ typedef struct {
 typedef struct {
     oracle_params p;
     double Minv[Q][Q];
+    double M5inv[Q5][Q5];
     double *f, *g, *h;    /* post-streaming state, [node][Q] */
     double *fs, *gs, *hs; /* post-collision populations, [node][Q] */
     double *srf, *srm;    /* previous-step interstitial sources */
@@ -106,35 +132,45 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 /* Linear algebra: inverse of M by Gauss-Jordan elimination.           */
 /* ------------------------------------------------------------------ */
-static int invert9(const double a_in[Q][Q], double inv[Q][Q])
+static int invert_n(int n, const double *a_in, double *inv)
 {
     double a[Q][2 * Q];
-    for (int r = 0; r < Q; ++r)
-        for (int c = 0; c < 2 * Q; ++c)
-            a[r][c] = c < Q ? a_in[r][c] : (c - Q == r ? 1.0 : 0.0);
-    for (int col = 0; col < Q; ++col) {
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < 2 * n; ++c)
+            a[r][c] = c < n ? a_in[r * n + c] : (c - n == r ? 1.0 : 0.0);
+    for (int col = 0; col < n; ++col) {
         int piv = col;
-        for (int r = col + 1; r < Q; ++r)
+        for (int r = col + 1; r < n; ++r)
             if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
         if (a[piv][col] == 0.0) return -1;
         if (piv != col)
-            for (int c = 0; c < 2 * Q; ++c) {
+            for (int c = 0; c < 2 * n; ++c) {
                 double t = a[col][c];
                 a[col][c] = a[piv][c];
                 a[piv][c] = t;
             }
         double d = a[col][col];
-        for (int c = 0; c < 2 * Q; ++c) a[col][c] /= d;
-        for (int r = 0; r < Q; ++r) {
+        for (int c = 0; c < 2 * n; ++c) a[col][c] /= d;
+        for (int r = 0; r < n; ++r) {
             if (r == col) continue;
             double fct = a[r][col];
             if (fct == 0.0) continue;
-            for (int c = 0; c < 2 * Q; ++c) a[r][c] -= fct * a[col][c];
+            for (int c = 0; c < 2 * n; ++c) a[r][c] -= fct * a[col][c];
         }
     }
-    for (int r = 0; r < Q; ++r)
-        for (int c = 0; c < Q; ++c) inv[r][c] = a[r][Q + c];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) inv[r * n + c] = a[r][n + c];
     return 0;
+}
+
+static int invert9(const double a_in[Q][Q], double inv[Q][Q])
+{
+    return invert_n(Q, &a_in[0][0], &inv[0][0]);
+}
+
+static int invert5(const double a_in[Q5][Q5], double inv[Q5][Q5])
+{
+    return invert_n(Q5, &a_in[0][0], &inv[0][0]);
 }
 
 static void matvec(const double A[Q][Q], const double *x, double *y)
@@ -142,6 +178,15 @@ static void matvec(const double A[Q][Q], const double *x, double *y)
     for (int r = 0; r < Q; ++r) {
         double acc = 0.0;
         for (int c = 0; c < Q; ++c) acc += A[r][c] * x[c];
+        y[r] = acc;
+    }
+}
+
+static void matvec5(const double A[Q5][Q5], const double *x, double *y)
+{
+    for (int r = 0; r < Q5; ++r) {
+        double acc = 0.0;
+        for (int c = 0; c < Q5; ++c) acc += A[r][c] * x[c];
         y[r] = acc;
     }
 }
@@ -178,6 +223,46 @@ void oracle_heq(double T_m, double c_pm, double c_mref, double *out)
 {
     out[0] = c_pm * T_m - 5.0 / 9.0 * c_mref * T_m;
     for (int i = 1; i < Q; ++i) out[i] = WT[i] * c_mref * T_m;
+}
+
+/* Eq. (B3): D2Q5 PCM enthalpy equilibrium, sound speed c_sT^2 = varpi/2. */
+void oracle_geq5(double H, double T, double ux, double uy, double phi, double c_fref, double c_pl,
+                 double varpi, double *out)
+{
+    const double cs2 = varpi / 2.0;
+    out[0] = H - varpi * c_fref * T;
+    for (int i = 1; i < Q5; ++i) {
+        double eu = EX[i] * ux + EY[i] * uy;
+        out[i] = 0.25 * varpi * c_pl * T * (c_fref / c_pl + eu / (phi * cs2));
+    }
+}
+
+/* Eq. (B5): D2Q5 metal-foam internal-energy equilibrium. */
+void oracle_heq5(double T_m, double c_pm, double c_mref, double varpi, double *out)
+{
+    out[0] = c_pm * T_m - varpi * c_mref * T_m;
+    for (int i = 1; i < Q5; ++i) out[i] = 0.25 * varpi * c_mref * T_m;
+}
+
+/* Thermal equilibria of the configured lattice (unused directions zero). */
+static void geq_of(const oracle_params *p, double H, double T, double ux, double uy, double *out)
+{
+    if (p->qt == Q5) {
+        for (int i = Q5; i < Q; ++i) out[i] = 0.0;
+        oracle_geq5(H, T, ux, uy, p->phi, p->c_fref, p->c_pl, p->varpi, out);
+    } else {
+        oracle_geq(H, T, ux, uy, p->phi, p->c_fref, p->c_pl, out);
+    }
+}
+
+static void heq_of(const oracle_params *p, double T_m, double *out)
+{
+    if (p->qt == Q5) {
+        for (int i = Q5; i < Q; ++i) out[i] = 0.0;
+        oracle_heq5(T_m, p->c_pm, p->c_mref, p->varpi, out);
+    } else {
+        oracle_heq(T_m, p->c_pm, p->c_mref, out);
+    }
 }
 
 /* Eqs. (38)-(39): temperature and liquid fraction from the enthalpy,
@@ -217,12 +302,12 @@ static void node_macros(const oracle_params *p, const double *fp, const double *
 {
     /* Eq. (37) then Eqs. (38)-(39). */
     double H = 0.0;
-    for (int i = 0; i < Q; ++i) H += g[i];
+    for (int i = 0; i < p->qt; ++i) H += g[i];
     m->H = H;
     oracle_eos(p, H, &m->T_f, &m->f_l);
     /* Eq. (48). */
     double eh = 0.0;
-    for (int i = 0; i < Q; ++i) eh += h[i];
+    for (int i = 0; i < p->qt; ++i) eh += h[i];
     m->T_m = eh / p->c_pm;
     /* Eq. (21). */
     double rho = 0.0;
@@ -273,9 +358,39 @@ void oracle_node_macros(const oracle_params *p, const double *fp, const double *
 /* ------------------------------------------------------------------ */
 /* Collision of the three fields at one node.                          */
 /* ------------------------------------------------------------------ */
-static void collide_node(const oracle_params *p, const double Minv[Q][Q], const double *fp,
-                         const double *g, const double *h, double srf_prev, double srm_prev,
-                         double *fo, double *go, double *ho, double *srf_new, double *srm_new)
+
+/* D2Q5 thermal collisions of Appendix B: moments by Eq. (B1), equilibrium
+ * moments Eqs. (B2) and (B4), sources S (1, 0, 0, varpi, 0), relaxation
+ * matrices Theta and Q in the moment order of Eq. (B1). */
+static void collide_thermal_d2q5(const oracle_params *p, const double M5inv[Q5][Q5],
+                                 const macros *mc, double S_pcm, double S_metal, const double *g,
+                                 const double *h, double *go, double *ho)
+{
+    const double phi = p->phi, vp = p->varpi;
+    const double src_dir[Q5] = {1.0, 0.0, 0.0, vp, 0.0};
+    double n[Q5], neq[Q5], ns[Q5];
+    matvec5(M5, g, n);
+    neq[0] = mc->H;
+    neq[1] = p->c_pl * mc->T_f * mc->ux / phi;
+    neq[2] = p->c_pl * mc->T_f * mc->uy / phi;
+    neq[3] = vp * p->c_fref * mc->T_f;
+    neq[4] = 0.0;
+    for (int k = 0; k < Q5; ++k) ns[k] = n[k] - p->zeta[k] * (n[k] - neq[k]) + S_pcm * src_dir[k];
+    matvec5(M5inv, ns, go);
+    matvec5(M5, h, n);
+    neq[0] = p->c_pm * mc->T_m;
+    neq[1] = 0.0;
+    neq[2] = 0.0;
+    neq[3] = vp * p->c_mref * mc->T_m;
+    neq[4] = 0.0;
+    for (int k = 0; k < Q5; ++k) ns[k] = n[k] - p->eta[k] * (n[k] - neq[k]) + S_metal * src_dir[k];
+    matvec5(M5inv, ns, ho);
+    for (int i = Q5; i < Q; ++i) go[i] = ho[i] = 0.0;
+}
+static void collide_node(const oracle_params *p, const double Minv[Q][Q],
+                         const double M5inv[Q5][Q5], const double *fp, const double *g,
+                         const double *h, double srf_prev, double srm_prev, double *fo, double *go,
+                         double *ho, double *srf_new, double *srm_new)
 {
     macros mc;
     node_macros(p, fp, g, h, &mc);
@@ -321,6 +436,10 @@ static void collide_node(const oracle_params *p, const double Minv[Q][Q], const 
     double S_metal = srm + 0.5 * (srm - srm_prev);
     *srf_new = srf;
     *srm_new = srm;
+    if (p->qt == Q5) {
+        collide_thermal_d2q5(p, M5inv, &mc, S_pcm, S_metal, g, h, go, ho);
+        return;
+    }
     static const double src_dir[Q] = {1, -2, 1, 0, 0, 0, 0, 0, 0}; /* Eqs. (35), (46) */
 
     /* ---- PCM enthalpy field, Eqs. (32), (34) ---- */
@@ -354,9 +473,11 @@ void oracle_collide_node(const oracle_params *p, const double *fp, const double 
                          const double *h, double srf_prev, double srm_prev, double *fo,
                          double *go, double *ho, double *sr_new2)
 {
-    double Minv[Q][Q];
+    double Minv[Q][Q], M5inv[Q5][Q5];
     invert9(MM, Minv);
-    collide_node(p, Minv, fp, g, h, srf_prev, srm_prev, fo, go, ho, &sr_new2[0], &sr_new2[1]);
+    invert5(M5, M5inv);
+    collide_node(p, Minv, M5inv, fp, g, h, srf_prev, srm_prev, fo, go, ho, &sr_new2[0],
+                 &sr_new2[1]);
 }
 
 void oracle_lattice(int *ex, int *ey, double *w, double *M, double *Minv)
@@ -374,6 +495,17 @@ void oracle_lattice(int *ex, int *ey, double *w, double *M, double *Minv)
     }
 }
 
+void oracle_lattice5(double *M, double *Minv)
+{
+    double inv[Q5][Q5];
+    invert5(M5, inv);
+    for (int i = 0; i < Q5; ++i)
+        for (int j = 0; j < Q5; ++j) {
+            M[i * Q5 + j] = M5[i][j];
+            Minv[i * Q5 + j] = inv[i][j];
+        }
+}
+
 /* ------------------------------------------------------------------ */
 /* Geometry helpers.                                                   */
 /* ------------------------------------------------------------------ */
@@ -385,6 +517,22 @@ static int wall_of(const oracle_params *p, int X, int Y)
     }
     if (Y == 0) return W_BOTTOM;
     if (Y == p->NY - 1) return W_TOP;
+    return W_NONE;
+}
+
+/* Wall whose thermal condition node (X, Y) carries: an isothermal vertical
+ * wall, else an isothermal horizontal wall, else W_NONE (adiabatic). */
+static int thermal_wall_of(const oracle_params *p, int X, int Y)
+{
+    int v = W_NONE, h = W_NONE;
+    if (!p->periodic_x) {
+        if (X == 0) v = W_LEFT;
+        else if (X == p->NX - 1) v = W_RIGHT;
+    }
+    if (Y == 0) h = W_BOTTOM;
+    else if (Y == p->NY - 1) h = W_TOP;
+    if (v != W_NONE && p->wall_type[v] == WALL_ISOTHERMAL) return v;
+    if (h != W_NONE && p->wall_type[h] == WALL_ISOTHERMAL) return h;
     return W_NONE;
 }
 
@@ -417,7 +565,11 @@ oracle_state *oracle_new(const oracle_params *p)
     oracle_state *s = (oracle_state *)calloc(1, sizeof(oracle_state));
     if (!s) return NULL;
     s->p = *p;
-    if (invert9(MM, s->Minv) != 0) {
+    if (p->qt != Q && p->qt != Q5) {
+        free(s);
+        return NULL;
+    }
+    if (invert9(MM, s->Minv) != 0 || invert5(M5, s->M5inv) != 0) {
         free(s);
         return NULL;
     }
@@ -464,13 +616,12 @@ void oracle_set_initial(oracle_state *s, const double *T_f0, const double *T_m0)
             long k = idx(p, x, y);
             int X = x + p->gx0, Y = y + p->gy0;
             double Tf = T_f0[k], Tm = T_m0[k];
-            int w = wall_of(p, X, Y);
-            if (w == W_LEFT) Tf = Tm = p->T_hot;
-            if (w == W_RIGHT) Tf = Tm = p->T_cold;
+            int w = thermal_wall_of(p, X, Y);
+            if (w != W_NONE) Tf = Tm = p->wall_T[w];
             double H = oracle_enthalpy_of_T(p, Tf);
             oracle_feq(p->rho_l, 0.0, 0.0, p->phi, &s->f[k * Q]);
-            oracle_geq(H, Tf, 0.0, 0.0, p->phi, p->c_fref, p->c_pl, &s->g[k * Q]);
-            oracle_heq(Tm, p->c_pm, p->c_mref, &s->h[k * Q]);
+            geq_of(p, H, Tf, 0.0, 0.0, &s->g[k * Q]);
+            heq_of(p, Tm, &s->h[k * Q]);
             s->srf[k] = p->h_v * (Tm - Tf) / (p->phi * p->rho_l);
             s->srm[k] = p->h_v * (Tf - Tm) / ((1.0 - p->phi) * p->rho_m);
             s->valid[k] = 1;
@@ -482,7 +633,7 @@ void oracle_set_initial(oracle_state *s, const double *T_f0, const double *T_m0)
 
 /* Wall values and non-equilibrium extrapolation, Eq. (52) and its thermal
  * analogues, for wall node k with interior partner kp. */
-static void reconstruct_wall(oracle_state *s, int wall, long k, long kp)
+static void reconstruct_wall(oracle_state *s, int X, int Y, long k, long kp)
 {
     const oracle_params *p = &s->p;
     double *fb = &s->f[k * Q], *gb = &s->g[k * Q], *hb = &s->h[k * Q];
@@ -490,11 +641,9 @@ static void reconstruct_wall(oracle_state *s, int wall, long k, long kp)
     macros mf;
     node_macros(p, fp, gp, hp, &mf);
     double Tb, Hb, Tmb;
-    if (wall == W_LEFT) {
-        Tb = Tmb = p->T_hot;
-        Hb = oracle_enthalpy_of_T(p, Tb);
-    } else if (wall == W_RIGHT) {
-        Tb = Tmb = p->T_cold;
+    int wall = thermal_wall_of(p, X, Y);
+    if (wall != W_NONE) {
+        Tb = Tmb = p->wall_T[wall];
         Hb = oracle_enthalpy_of_T(p, Tb);
     } else { /* adiabatic: zero normal gradient */
         Tb = mf.T_f;
@@ -506,12 +655,12 @@ static void reconstruct_wall(oracle_state *s, int wall, long k, long kp)
     oracle_feq(mf.rho, 0.0, 0.0, p->phi, eqb);
     oracle_feq(mf.rho, mf.ux, mf.uy, p->phi, eqf);
     for (int i = 0; i < Q; ++i) fb[i] = eqb[i] + (fp[i] - eqf[i]);
-    oracle_geq(Hb, Tb, 0.0, 0.0, p->phi, p->c_fref, p->c_pl, eqb);
-    oracle_geq(mf.H, mf.T_f, mf.ux, mf.uy, p->phi, p->c_fref, p->c_pl, eqf);
-    for (int i = 0; i < Q; ++i) gb[i] = eqb[i] + (gp[i] - eqf[i]);
-    oracle_heq(Tmb, p->c_pm, p->c_mref, eqb);
-    oracle_heq(mf.T_m, p->c_pm, p->c_mref, eqf);
-    for (int i = 0; i < Q; ++i) hb[i] = eqb[i] + (hp[i] - eqf[i]);
+    geq_of(p, Hb, Tb, 0.0, 0.0, eqb);
+    geq_of(p, mf.H, mf.T_f, mf.ux, mf.uy, eqf);
+    for (int i = 0; i < p->qt; ++i) gb[i] = eqb[i] + (gp[i] - eqf[i]);
+    heq_of(p, Tmb, eqb);
+    heq_of(p, mf.T_m, eqf);
+    for (int i = 0; i < p->qt; ++i) hb[i] = eqb[i] + (hp[i] - eqf[i]);
 }
 
 /* One time step. */
@@ -527,9 +676,9 @@ static void step_once(oracle_state *s)
         for (int x = 0; x < nx; ++x) {
             long k = idx(p, x, y);
             double srf_new, srm_new;
-            collide_node(p, (const double(*)[Q])s->Minv, &s->f[k * Q], &s->g[k * Q], &s->h[k * Q],
-                         s->srf[k], s->srm[k], &s->fs[k * Q], &s->gs[k * Q], &s->hs[k * Q],
-                         &srf_new, &srm_new);
+            collide_node(p, (const double(*)[Q])s->Minv, (const double(*)[Q5])s->M5inv,
+                         &s->f[k * Q], &s->g[k * Q], &s->h[k * Q], s->srf[k], s->srm[k],
+                         &s->fs[k * Q], &s->gs[k * Q], &s->hs[k * Q], &srf_new, &srm_new);
             s->srf[k] = srf_new;
             s->srm[k] = srm_new;
         }
@@ -545,11 +694,13 @@ static void step_once(oracle_state *s)
                     if (p->periodic_x) tx = (tx + nx) % nx;
                     if (tx < 0 || tx >= nx || ty < 0 || ty >= ny) continue;
                     int wt = wall_of(p, tx, ty);
+                    /* energy moves only along the thermal lattice's links */
+                    double e = i < p->qt ? we * s->gs[k * Q + i] + wm * s->hs[k * Q + i] : 0.0;
                     if (w != W_NONE && wt == W_NONE) { /* wall -> interior */
-                        s->flux_E[w] += we * s->gs[k * Q + i] + wm * s->hs[k * Q + i];
+                        s->flux_E[w] += e;
                         s->flux_M[w] += s->fs[k * Q + i];
                     } else if (w == W_NONE && wt != W_NONE) { /* interior -> wall */
-                        s->flux_E[wt] -= we * s->gs[k * Q + i] + wm * s->hs[k * Q + i];
+                        s->flux_E[wt] -= e;
                         s->flux_M[wt] -= s->fs[k * Q + i];
                     }
                 }
@@ -571,8 +722,10 @@ static void step_once(oracle_state *s)
                 }
                 long ks = idx(p, sx, sy);
                 s->f[k * Q + i] = s->fs[ks * Q + i];
-                s->g[k * Q + i] = s->gs[ks * Q + i];
-                s->h[k * Q + i] = s->hs[ks * Q + i];
+                if (i < p->qt) {
+                    s->g[k * Q + i] = s->gs[ks * Q + i];
+                    s->h[k * Q + i] = s->hs[ks * Q + i];
+                }
                 ok = ok && s->valid[ks];
             }
             s->valid_new[k] = (unsigned char)ok;
@@ -593,7 +746,7 @@ static void step_once(oracle_state *s)
                 continue;
             }
             long kp = idx(p, px, py);
-            reconstruct_wall(s, w, k, kp);
+            reconstruct_wall(s, X, Y, k, kp);
             s->valid_new[k] = s->valid_new[kp];
         }
     unsigned char *t = s->valid;
@@ -649,11 +802,11 @@ static void totals(const oracle_state *s, double *E, double *Mass)
             if (wall_of(p, x + p->gx0, y + p->gy0) != W_NONE) continue;
             long k = idx(p, x, y);
             double sg = 0.0, sh = 0.0, sf = 0.0;
-            for (int i = 0; i < Q; ++i) {
+            for (int i = 0; i < p->qt; ++i) {
                 sg += s->g[k * Q + i];
                 sh += s->h[k * Q + i];
-                sf += s->f[k * Q + i];
             }
+            for (int i = 0; i < Q; ++i) sf += s->f[k * Q + i];
             e += p->phi * p->rho_l * sg + (1.0 - p->phi) * p->rho_m * sh;
             m += sf;
         }

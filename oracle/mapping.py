@@ -13,17 +13,67 @@ paper's definitions:
 * Forchheimer coefficient from the porosity, Eq. (4), unless given;
 * characteristic length L = nx - 1 (walls on the first and last node
   columns; for the periodic-in-x channel, the distance between the two
-  horizontal walls, ny - 1), reference temperature T_0 = T_cold (Sec. IV B).
+  horizontal walls, ny - 1) unless given, reference temperature
+  T_0 = T_cold (Sec. IV B);
+* thermal lattice D2Q9 (Sec. III B/C) or D2Q5 (Appendix B, c_sT^2 = varpi/2,
+  zeta_e = 2 - zeta_alpha), MRT or BGK thermal collisions (Sec. V A), an
+  optional fixed zeta_e (Sec. V D);
+* walls: isothermal or adiabatic, each of the four; by default the cavity
+  of Sec. IV B (hot left, cold right, adiabatic top and bottom).
 """
 from __future__ import annotations
 
 import math
 
 
+WALL_DEFAULT, WALL_ISOTHERMAL, WALL_ADIABATIC = 0, 1, 2
+
+
 def char_length(p: dict) -> float:
     """Distance between the two walls that carry the imposed temperature
-    difference (cavity) or the no-slip condition (periodic channel)."""
+    difference (cavity) or the no-slip condition (periodic channel), unless
+    the problem gives its own length."""
+    if p.get("L_char", 0.0) > 0:
+        return float(p["L_char"])
     return float(p["ny"] - 1) if int(p["bc_x"]) == 1 else float(p["nx"] - 1)
+
+
+def thermal_lattice(p: dict):
+    """(number of thermal velocities, varpi, c_sT^2)."""
+    qt = int(p.get("thermal_lattice", 0)) or 9
+    if qt not in (5, 9):
+        raise ValueError("thermal_lattice must be 9 or 5")
+    if qt == 9:
+        return 9, 0.0, 1.0 / 3.0
+    varpi = float(p.get("varpi", 0.0))
+    if varpi <= 0:
+        varpi = 2.0 / 3.0
+    if not varpi < 1.0:
+        raise ValueError("varpi must lie in (0, 1) (Eq. B2)")
+    return 5, varpi, varpi / 2.0
+
+
+def walls(p: dict):
+    """Resolved (types, temperatures) of the left, right, bottom and top walls."""
+    types = [int(t) for t in p.get("wall_type", (0, 0, 0, 0))]
+    temps = [float(t) for t in p.get("wall_T", (0.0, 0.0, 0.0, 0.0))]
+    if len(types) != 4 or len(temps) != 4 or any(t not in (0, 1, 2) for t in types):
+        raise ValueError("wall_type needs four entries among 0 (default), 1 (isothermal), 2 (adiabatic)")
+    if int(p["bc_x"]) == 1 and (types[0] or types[1]):
+        raise ValueError("a periodic-in-x problem has no left or right wall")
+    default = [(WALL_ISOTHERMAL, float(p["T_hot"])), (WALL_ISOTHERMAL, float(p["T_cold"])),
+               (WALL_ADIABATIC, 0.0), (WALL_ADIABATIC, 0.0)]
+    if int(p["bc_x"]) == 1:
+        default[0] = default[1] = (WALL_ADIABATIC, 0.0)
+    out_t, out_T = [], []
+    for w in range(4):
+        if types[w] == WALL_DEFAULT:
+            t, T = default[w]
+        else:
+            t, T = types[w], (temps[w] if types[w] == WALL_ISOTHERMAL else 0.0)
+        out_t.append(t)
+        out_T.append(T)
+    return out_t, out_T
 
 
 def stable_k_f(p: dict) -> float:
@@ -40,7 +90,11 @@ def stable_k_f(p: dict) -> float:
     L = char_length(p)
     dpL = p["dp_over_L"] if p["dp_over_L"] > 0 else 0.0135
     d_p = dpL * L
-    limits = [0.5 / (J * p["Pr"]), 0.5 * c_fref, 0.5 * rho_m * c_mref / lam]
+    _, _, cs2T = thermal_lattice(p)
+    # tau = 0.5 + alpha_ref / c_s^2 <= 2  <=>  alpha_ref <= 1.5 c_s^2
+    limits = [0.5 / (J * p["Pr"]), 1.5 * cs2T * c_fref]
+    if lam > 0:
+        limits.append(1.5 * cs2T * rho_m * c_mref / lam)
     if p["Nu_i"] > 0:
         limits.append(0.5 * d_p * d_p / (p["Nu_i"] * (1.0 / phi + 1.0 / ((1.0 - phi) * rho_m))))
     return min(limits)
@@ -89,19 +143,42 @@ def lattice_params(p: dict) -> dict:
     if not T_fl > T_fs:
         raise ValueError("liquidus must lie above solidus")
 
+    qt, varpi, cs2T = thermal_lattice(p)
+    wall_type, wall_T = walls(p)
+    collision = int(p.get("thermal_collision", 0))
+    if collision not in (0, 1):
+        raise ValueError("thermal_collision must be 0 (MRT) or 1 (BGK)")
+    zeta_e_given = float(p.get("zeta_e", 0.0))
+
     # Eq. (26) / Sec. III C: s_v^-1 = 0.5 + nu_e / c_s^2.
     s_v = 1.0 / (0.5 + 3.0 * nu_e)
-    # Eq. (A19): alpha_f,ref = k_f/(rho_l c_f,ref) = c_s^2 (1/zeta_alpha - 1/2).
+    # Eq. (A19): alpha_f,ref = k_f/(rho_l c_f,ref) = c_s^2 (1/zeta_alpha - 1/2),
+    # with the thermal lattice's sound speed (c_sT^2 = varpi/2 for D2Q5).
     alpha_fref = k_f / (rho_l * c_fref)
-    zeta_a = 1.0 / (0.5 + 3.0 * alpha_fref)
+    zeta_a = 1.0 / (0.5 + alpha_fref / cs2T)
     # After Eq. (51): alpha_m,ref = k_m/(rho_m c_m,ref) = c_s^2 (1/eta_alpha - 1/2).
     alpha_mref = k_m / (rho_m * c_mref)
-    eta_a = 1.0 / (0.5 + 3.0 * alpha_mref)
-    # Sec. III C free rates; zeta_e = zeta_eps = 2 - zeta_alpha (Eq. 53);
-    # the conserved-moment rates zeta_0 and s_rho multiply zero and are 1.
+    eta_a = 1.0 / (0.5 + alpha_mref / cs2T)
+    # Sec. III C free rates; zeta_e = zeta_eps = 2 - zeta_alpha (Eq. 53) unless
+    # zeta_e is given (Sec. V D); the conserved-moment rates zeta_0 and s_rho
+    # multiply zero and are 1.  D2Q5 (Appendix B): Theta = diag(zeta_0,
+    # zeta_a, zeta_a, zeta_e, zeta_eps), Q = diag(eta_0, eta_a, eta_a, eta_e,
+    # eta_eps), the free rates as for D2Q9; entries 5..8 unused (1).  BGK
+    # (Sec. V A): every thermal rate 1/tau_g or 1/tau_h.
     s = [1.0, 1.1, 1.1, 1.0, 1.2, 1.0, 1.2, s_v, s_v]
-    zeta = [1.0, 2.0 - zeta_a, 2.0 - zeta_a, zeta_a, zeta_a, zeta_a, zeta_a, 1.2, 1.2]
-    eta = [1.0, 1.1, 1.1, eta_a, eta_a, eta_a, eta_a, 1.2, 1.2]
+    if collision == 1:
+        if zeta_e_given > 0:
+            raise ValueError("zeta_e cannot be set for BGK thermal collisions")
+        zeta = [zeta_a] * qt + [1.0] * (9 - qt)
+        eta = [eta_a] * qt + [1.0] * (9 - qt)
+    else:
+        ze = zeta_e_given if zeta_e_given > 0 else 2.0 - zeta_a
+        if qt == 9:
+            zeta = [1.0, ze, 2.0 - zeta_a, zeta_a, zeta_a, zeta_a, zeta_a, 1.2, 1.2]
+            eta = [1.0, 1.1, 1.1, eta_a, eta_a, eta_a, eta_a, 1.2, 1.2]
+        else:
+            zeta = [1.0, zeta_a, zeta_a, ze, 2.0 - zeta_a, 1.0, 1.0, 1.0, 1.0]
+            eta = [1.0, eta_a, eta_a, 1.1, 1.1, 1.0, 1.0, 1.0, 1.0]
     for name, r in (("s", s), ("zeta", zeta), ("eta", eta)):
         if not all(0.0 < v < 2.0 for v in r):
             raise ValueError(f"relaxation rates {name} must lie in (0, 2): {r}")
@@ -117,7 +194,8 @@ def lattice_params(p: dict) -> dict:
         T_hot=float(p["T_hot"]), T_cold=float(p["T_cold"]),
         k_f=k_f, k_m=k_m, L=L, alpha_f=alpha_f, d_p=d_p, z=z,
         tau_v=1.0 / s_v, tau_g=1.0 / zeta_a, tau_h=1.0 / eta_a,
-        s=s, zeta=zeta, eta=eta,
+        s=s, zeta=zeta, eta=eta, qt=qt, varpi=varpi, cs2T=cs2T,
+        wall_type=wall_type, wall_T=wall_T, thermal_collision=collision,
     )
 
 

@@ -1,0 +1,314 @@
+"""Whole-update pins of the oracle's thermal variants and wall conditions.
+
+* The closed forms of the D2Q9 pins (LTNE sine modes, steady conduction,
+  Neumann's Stefan solution, the energy/mass balance identity) hold for the
+  D2Q5 models of Appendix B and the BGK models of Sec. V A as well: they
+  recover the same macroscopic equations (5)-(6).
+* Conduction-induced solidification in a corner (Sec. IV A): the paper's
+  parameters on a smaller grid, against an independent explicit finite-
+  difference solve of Eqs. (5)-(6) with the enthalpy relation of Eq. (38);
+  the problem is symmetric about y = x, and the velocity stays zero.
+* Per-wall conditions: a conduction run with isothermal bottom/top walls is
+  the transpose of the same run with isothermal left/right walls.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+from scipy.optimize import brentq
+from scipy.special import erf
+
+import oracle
+from lbm_workloads import case_c1, case_corner, initial_temperatures, make_params
+from oracle.mapping import lattice_params, steps_for_fourier
+
+VARIANTS = {
+    "d2q5": dict(thermal_lattice=5),
+    "d2q5_varpi0.5": dict(thermal_lattice=5, varpi=0.5),
+    "d2q9_bgk": dict(thermal_collision=1),
+    "d2q5_bgk": dict(thermal_lattice=5, thermal_collision=1),
+}
+
+
+def _ltne_params(nx, Nu_i, **over):
+    return make_params(nx=nx, ny=4, porosity=0.9, Ra=0.0, Pr=5.0, Da=1.0, Ste=1.0, k_ratio=10.0,
+                       cap_ratio=2.0, Nu_i=Nu_i, k_f=0.02, cf_ref=0.3, cm_ref=0.7,
+                       T_hot=1.0, T_cold=0.0, T_init=0.0, T_solidus=-2.0, T_liquidus=-1.0, **over)
+
+
+def _ltne_exact(lp, x, t, kmax=3000):
+    """Linear steady profile plus the sine modes of the two-temperature
+    system of Eqs. (5)-(6) without flow or phase change."""
+    L = lp["L"]
+    af = lp["k_f"] / (lp["rho_l"] * lp["c_pl"])
+    am = lp["k_m"] / (lp["rho_m"] * lp["c_pm"])
+    a = lp["h_v"] / (lp["phi"] * lp["rho_l"] * lp["c_pl"])
+    b = lp["h_v"] / ((1 - lp["phi"]) * lp["rho_m"] * lp["c_pm"])
+    Tf = 1 - x / L
+    Tm = 1 - x / L
+    for k in range(1, kmax + 1):
+        kap = k * math.pi / L
+        A = np.array([[-af * kap ** 2 - a, a], [b, -am * kap ** 2 - b]])
+        c = -2 / (k * math.pi)
+        v = expm(A * t) @ np.array([c, c])
+        s = np.sin(kap * x)
+        Tf = Tf + v[0] * s
+        Tm = Tm + v[1] * s
+    return Tf, Tm
+
+
+def _ltne_err(nx, Nu_i, over, Fo=0.05):
+    p = _ltne_params(nx, Nu_i, **over)
+    lp = lattice_params(p)
+    o = oracle.Oracle(p)
+    T0 = np.zeros((4, nx))
+    o.set_initial(T0, T0)
+    n = int(round(steps_for_fourier(lp, Fo)))
+    o.step(n)
+    f = o.fields()
+    Tf, Tm = _ltne_exact(lp, np.arange(nx, dtype=float), n)
+    assert np.abs(f["T_pcm"][1] - f["T_pcm"][2]).max() < 1e-14
+    return np.abs(f["T_pcm"][1] - Tf).max(), np.abs(f["T_mf"][1] - Tm).max(), np.abs(Tf - Tm).max()
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_ltne_conduction_modes_variants(name):
+    e33 = _ltne_err(33, 0.002, VARIANTS[name])
+    e65 = _ltne_err(65, 0.002, VARIANTS[name])
+    assert e65[2] > 0.1
+    assert e65[0] < 5e-4 and e65[1] < 5e-4, e65
+    assert e33[0] / e65[0] > 3.5 and e33[1] / e65[1] > 3.5, (e33, e65)
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_steady_conduction_nusselt_is_one_variants(name):
+    p = _ltne_params(33, 0.05, **VARIANTS[name])
+    lp = lattice_params(p)
+    o = oracle.Oracle(p)
+    T0 = np.zeros((4, 33))
+    o.set_initial(T0, T0)
+    o.step(int(steps_for_fourier(lp, 2.0)))
+    d = o.diagnostics()
+    assert abs(d["Nu_hot"] - 1) < 1e-8 and abs(d["Nu_cold"] - 1) < 1e-8
+    np.testing.assert_allclose(o.fields()["T_pcm"][1], 1 - np.arange(33) / 32.0, atol=1e-10)
+
+
+@pytest.mark.parametrize("name", ["d2q5", "d2q9_bgk"])
+def test_stefan_front_neumann_variants(name):
+    nx = 129
+    p = make_params(nx=nx, ny=4, porosity=0.9, Ra=0.0, Pr=5.0, Da=1.0, Ste=1.0, k_ratio=10.0,
+                    cap_ratio=1.0, Nu_i=8.0, k_f=0.02, T_hot=1.0, T_cold=0.0, T_init=0.0,
+                    T_solidus=0.0, T_liquidus=0.002, **VARIANTS[name])
+    lp = lattice_params(p)
+    o = oracle.Oracle(p)
+    T0 = np.zeros((4, nx))
+    o.set_initial(T0, T0)
+    n = int(round(steps_for_fourier(lp, 0.02)))
+    o.step(n)
+    fl = o.fields()["f_l"][1]
+    s_int = fl[1:-1].sum() + 0.5
+    phi = lp["phi"]
+    rc = phi * lp["rho_l"] * lp["c_pl"] + (1 - phi) * lp["rho_m"] * lp["c_pm"]
+    ke = phi * lp["k_f"] + (1 - phi) * lp["k_m"]
+    St_e = rc * (lp["T_hot"] - lp["T_fs"]) / (phi * lp["rho_l"] * lp["L_a"])
+    lam = brentq(lambda l: l * math.exp(l * l) * erf(l) - St_e / math.sqrt(math.pi), 1e-6, 5)
+    s_ex = 2 * lam * math.sqrt(ke / rc * n)
+    assert abs(s_int - s_ex) < 0.05, (s_int, s_ex)
+
+
+@pytest.mark.parametrize("name", ["d2q5", "d2q5_bgk"])
+def test_energy_and_mass_balance_variants(name):
+    p, _, seed, _ = case_c1()
+    p = dict(p, **VARIANTS[name])
+    Tf, Tm = initial_temperatures(p, seed)
+    o = oracle.Oracle(p)
+    o.set_initial(Tf, Tm)
+    o.step(1500)
+    d = o.diagnostics()
+    assert d["E_int"] - d["E_int0"] > 100
+    assert abs(d["energy_residual"]) <= 1e-12 * abs(d["E_int"])
+    assert abs(d["mass_residual"]) <= 1e-12 * abs(d["M_int"])
+    assert d["flux_E"][0] > 0.99 * (d["E_int"] - d["E_int0"])
+
+
+# ---------------------------------------------------------------------------
+# Conduction-induced solidification in a corner (Sec. IV A)
+# ---------------------------------------------------------------------------
+
+def _fd_corner(lp, T_init, steps, sub=4):
+    """Explicit finite differences of Eqs. (5)-(6) with u = 0 on the same
+    nodes: phi dH/dt = phi k_f lap T_f + h_v (T_m - T_f) with H(T) from
+    Eq. (38), (1-phi) rho_m c_pm dT_m/dt = (1-phi) k_m lap T_m
+    + h_v (T_f - T_m).  Isothermal nodes are held at their wall temperature,
+    adiabatic ones copy their inward neighbour (diagonal at corners)."""
+    nx, ny = lp["nx"], lp["ny"]
+    phi, hv = lp["phi"], lp["h_v"]
+    H_fs, H_fl, T_fs, T_fl = lp["H_fs"], lp["H_fl"], lp["T_fs"], lp["T_fl"]
+
+    def T_of_H(H):
+        return np.where(H <= H_fs, H / lp["c_ps"],
+                        np.where(H >= H_fl, T_fl + (H - H_fl) / lp["c_pl"],
+                                 T_fs + (H - H_fs) / (H_fl - H_fs) * (T_fl - T_fs)))
+
+    def H_of_T(T):
+        return np.where(T <= T_fs, lp["c_ps"] * T,
+                        np.where(T >= T_fl, lp["c_pl"] * (T - T_fl) + H_fl,
+                                 H_fs + (T - T_fs) / (T_fl - T_fs) * (H_fl - H_fs)))
+
+    Tm = np.full((ny, nx), T_init)
+    H = H_of_T(Tm.copy())
+    iso = np.zeros((ny, nx), dtype=bool)
+    Tiso = np.zeros((ny, nx))
+    wt, wT = lp["wall_type"], lp["wall_T"]
+    # corners follow the vertical wall if isothermal, else the horizontal one
+    for (sl, w) in (((slice(None), 0), 0), ((slice(None), nx - 1), 1)):
+        if wt[w] == 1:
+            iso[sl] = True
+            Tiso[sl] = wT[w]
+    for (sl, w) in (((0, slice(1, nx - 1)), 2), ((ny - 1, slice(1, nx - 1)), 3)):
+        if wt[w] == 1:
+            iso[sl] = True
+            Tiso[sl] = wT[w]
+    for (y, x, w) in ((0, 0, 2), (0, nx - 1, 2), (ny - 1, 0, 3), (ny - 1, nx - 1, 3)):
+        if not iso[y, x] and wt[w] == 1:
+            iso[y, x] = True
+            Tiso[y, x] = wT[w]
+
+    def apply_walls(T):
+        T[iso] = Tiso[iso]
+        # adiabatic: copy the inward neighbour
+        for w, (dst, src) in enumerate((((slice(1, -1), 0), (slice(1, -1), 1)),
+                                        ((slice(1, -1), -1), (slice(1, -1), -2)),
+                                        ((0, slice(1, -1)), (1, slice(1, -1))),
+                                        ((-1, slice(1, -1)), (-2, slice(1, -1))))):
+            if wt[w] == 2:
+                T[dst] = T[src]
+        for (y, x, sy, sx) in ((0, 0, 1, 1), (0, -1, 1, -2), (-1, 0, -2, 1), (-1, -1, -2, -2)):
+            if not iso[y, x]:
+                T[y, x] = T[sy, sx]
+        return T
+
+    dt = 1.0 / sub
+    am = lp["k_m"] / (lp["rho_m"] * lp["c_pm"])
+    b = hv / ((1 - phi) * lp["rho_m"] * lp["c_pm"])
+    for _ in range(steps * sub):
+        Tf = apply_walls(T_of_H(H))
+        Tm = apply_walls(Tm)
+        lf = Tf[1:-1, :-2] + Tf[1:-1, 2:] + Tf[:-2, 1:-1] + Tf[2:, 1:-1] - 4 * Tf[1:-1, 1:-1]
+        lm = Tm[1:-1, :-2] + Tm[1:-1, 2:] + Tm[:-2, 1:-1] + Tm[2:, 1:-1] - 4 * Tm[1:-1, 1:-1]
+        ex = Tm[1:-1, 1:-1] - Tf[1:-1, 1:-1]
+        H[1:-1, 1:-1] += dt * (lp["k_f"] * lf + hv / phi * ex)
+        Tm[1:-1, 1:-1] += dt * (am * lm - b * ex)
+    Tf = apply_walls(T_of_H(H))
+    Tm = apply_walls(Tm)
+    fl = np.clip((H_of_T(Tf) - H_fs) / (H_fl - H_fs), 0.0, 1.0)
+    return Tf, Tm, fl
+
+
+def _front(fl_line):
+    """Distance from the wall of the first f_l = 0.5 crossing (solid side first)."""
+    i = int(np.where(fl_line >= 0.5)[0][0])
+    a, b = fl_line[i - 1], fl_line[i]
+    return (i - 1) + (0.5 - a) / (b - a)
+
+
+def test_corner_solidification_against_finite_differences():
+    p, steps, _, _ = case_corner(100)
+    lp = lattice_params(p)
+    assert lp["L"] == 50.0 and lp["wall_type"] == [1, 2, 1, 2]
+    assert abs(steps_for_fourier(lp, 0.02) - steps) < 1e-9
+    o = oracle.Oracle(p)
+    T0 = np.full((p["ny"], p["nx"]), p["T_init"])
+    o.set_initial(T0, T0)
+    o.step(steps)
+    f = o.fields()
+    d = o.diagnostics()
+    assert d["u_max"] == 0.0 and np.all(f["ux"] == 0.0) and np.all(f["uy"] == 0.0)
+    assert abs(d["energy_residual"]) <= 1e-12 * abs(d["E_int"])
+    # symmetric about y = x (Sec. IV A)
+    np.testing.assert_allclose(f["f_l"], f["f_l"].T, atol=1e-12)
+    np.testing.assert_allclose(f["T_pcm"], f["T_pcm"].T, atol=1e-12)
+    Tf, Tm, fl = _fd_corner(lp, p["T_init"], steps)
+    # a solid layer of several nodes has grown from both cold walls
+    fronts_lb = [_front(f["f_l"][y, :]) for y in range(30, 90, 10)]
+    fronts_fd = [_front(fl[y, :]) for y in range(30, 90, 10)]
+    assert min(fronts_lb) > 5
+    # the paper asks for agreement with its FDM to plotting accuracy; the two
+    # discretisations of the same equations agree to a fraction of a node
+    assert max(abs(a - b) for a, b in zip(fronts_lb, fronts_fd)) < 0.25, (fronts_lb, fronts_fd)
+    diag_lb = _front(np.diag(f["f_l"]))
+    diag_fd = _front(np.diag(fl))
+    assert abs(diag_lb - diag_fd) < 0.25
+    assert diag_lb > min(fronts_lb) + 3      # the corner freezes deeper
+    assert np.abs(f["T_pcm"] - Tf).max() < 0.01
+    assert np.abs(f["T_mf"] - Tm).max() < 0.01
+    # latent heat: isotherms are closer in the solid than in the liquid
+    row = f["T_pcm"][70]
+    k = int(round(fronts_lb[4]))
+    assert (row[k] - row[1]) / (k - 1) > (row[k + 8] - row[k]) / 8
+
+
+def test_isothermal_bottom_top_is_transposed_left_right():
+    # Conduction with phase change in a square: hot left / cold right walls
+    # with adiabatic top and bottom, against hot bottom / cold top with
+    # adiabatic sides.  Without flow the second is the transpose of the first.
+    base = dict(nx=40, ny=40, porosity=0.85, Ra=0.0, Pr=5.0, Da=1.0, Ste=0.8, k_ratio=20.0,
+                cap_ratio=1.3, Nu_i=1.0, k_f=0.02, T_hot=1.0, T_cold=0.0, T_init=0.0,
+                T_solidus=0.0, T_liquidus=0.01)
+    a = make_params(**base)
+    b = make_params(**dict(base, wall_type=(2, 2, 1, 1), wall_T=(0.0, 0.0, 1.0, 0.0)))
+    out = []
+    for p in (a, b):
+        o = oracle.Oracle(p)
+        T0 = np.zeros((40, 40))
+        o.set_initial(T0, T0)
+        o.step(800)
+        out.append((o.fields(), o.diagnostics()))
+    (fa, da), (fb, db) = out
+    assert fa["f_l"].mean() > 0.05
+    for k in ("T_pcm", "T_mf", "f_l"):
+        np.testing.assert_allclose(fb[k], fa[k].T, rtol=0, atol=1e-12)
+    # corner links count for the vertical walls in both runs, so only the
+    # total inflow is transpose-invariant
+    assert abs(sum(db["flux_E"]) - sum(da["flux_E"])) < 1e-10 * abs(sum(da["flux_E"]))
+
+
+@pytest.mark.parametrize("qt", [9, 5])
+def test_wall_nodes_carry_their_wall_values(qt):
+    # Eq. (52) and its thermal analogues replace only the equilibrium part of
+    # the partner's populations, so the rebuilt wall node holds exactly the
+    # wall temperature (isothermal) or the partner's temperature (adiabatic),
+    # in both phases, after every step.  Mixed wall types, flow and melting.
+    p = make_params(nx=24, ny=20, porosity=0.9, Ra=1e5, Pr=5.0, Da=1e-2, Ste=1.0, k_ratio=5.0,
+                    cap_ratio=1.2, Nu_i=0.5, k_f=0.02, T_hot=1.0, T_cold=0.0, T_init=0.2,
+                    T_solidus=0.3, T_liquidus=0.35, thermal_lattice=qt,
+                    wall_type=(1, 2, 2, 1), wall_T=(1.0, 0.0, 0.0, 0.1))
+    lp = lattice_params(p)
+    o = oracle.Oracle(p)
+    T0 = np.full((20, 24), 0.2)
+    o.set_initial(T0, T0)
+    nx, ny = 24, 20
+    for _ in range(3):
+        o.step(37)
+        f = o.fields()
+        assert np.hypot(f["ux"], f["uy"]).max() > 1e-6
+        for y in range(ny):
+            for x in range(nx):
+                vert = 0 if x == 0 else (1 if x == nx - 1 else None)
+                hor = 2 if y == 0 else (3 if y == ny - 1 else None)
+                if vert is None and hor is None:
+                    continue
+                iso = [w for w in (vert, hor) if w is not None and lp["wall_type"][w] == 1]
+                if iso:
+                    T = lp["wall_T"][iso[0]]
+                    assert abs(f["T_pcm"][y, x] - T) < 1e-13 and abs(f["T_mf"][y, x] - T) < 1e-13, (x, y)
+                else:
+                    px = 1 if x == 0 else (nx - 2 if x == nx - 1 else x)
+                    py = 1 if y == 0 else (ny - 2 if y == ny - 1 else y)
+                    assert abs(f["T_pcm"][y, x] - f["T_pcm"][py, px]) < 1e-13, (x, y)
+                    assert abs(f["T_mf"][y, x] - f["T_mf"][py, px]) < 1e-13, (x, y)
+        # the left corners follow the isothermal left wall, the top-right
+        # corner the isothermal top wall
+        assert f["T_pcm"][0, 0] == 1.0 or abs(f["T_pcm"][0, 0] - 1.0) < 1e-13
+        assert abs(f["T_pcm"][ny - 1, nx - 1] - 0.1) < 1e-13
