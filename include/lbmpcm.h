@@ -4,7 +4,8 @@
  * change in metal foams under local thermal non-equilibrium
  * (Q. Liu, Y.-L. He, Q. Li, arXiv:1701.00702).
  *
- * One time step updates three coupled D2Q9 populations per node:
+ * One time step updates three coupled population sets per node (D2Q9 flow;
+ * D2Q9 thermal fields, or the D2Q5 thermal fields of Appendix B):
  *   f  flow field with the Brinkman-Forchheimer (generalized non-Darcy) force
  *      and the volumetric no-slip treatment of the solid phase (Sec. III A,
  *      Eqs. 12-27);
@@ -13,8 +14,10 @@
  *   h  metal-foam internal energy (Sec. III B 2, Eqs. 41-49);
  * coupled by the interstitial heat-exchange sources (Eqs. 36, 47) and closed
  * by non-equilibrium extrapolation on the walls (Sec. III C, Eq. 52).
- * The problem is the cavity of Sec. IV B: isothermal hot wall at x = 0, cold
- * wall at x = nx-1, adiabatic horizontal walls, gravity along -y.
+ * The default problem is the cavity of Sec. IV B: isothermal hot wall at
+ * x = 0, cold wall at x = nx-1, adiabatic horizontal walls, gravity along
+ * -y; each wall can instead be isothermal at its own temperature or
+ * adiabatic (e.g. the corner solidification of Sec. IV A).
  *
  * Conventions shared by every entry point:
  *  - Host field arrays are row-major double[ny][nx], x fastest, owned by the
@@ -50,8 +53,8 @@ typedef enum {
     LBM_EIO = -6         /* checkpoint file could not be written or read */
 } lbm_status;
 
-/* Storage of the 27 populations per node.  Arithmetic is FP64 for LBM_F64
- * and FP32 otherwise.  Every form stores, per field, the offset of each
+/* Storage of the populations of a node (27 with D2Q9 thermal fields, 19 with
+ * D2Q5 ones).  Arithmetic is FP64 for LBM_F64 and FP32 otherwise.  Every form stores, per field, the offset of each
  * population from the rest equilibrium at a fixed reference state (flow: the
  * lattice weights times the reference density; enthalpy and metal fields:
  * the equilibria at rest at the middle of the mushy band).
@@ -65,7 +68,11 @@ typedef enum {
  *                      equilibrium of that base (72 bytes per node)
  *   LBM_F32_H64        as LBM_F32, except the rest population of the enthalpy
  *                      field, which carries H itself, in FP64, and the
- *                      enthalpy-field arithmetic in FP64 (112 bytes per node). */
+ *                      enthalpy-field arithmetic in FP64 (112 bytes per node).
+ * With D2Q5 thermal fields (lbm_params.thermal_lattice = 5) the forms
+ * LBM_F64, LBM_F32 and LBM_F32_H64 are available: 152, 76 and 80 bytes per
+ * node, planes [f0..f8, g0..g4, h0..h4] (LBM_F32_H64: [f0..f8, g1..g4,
+ * h0..h4] in FP32, then g0 in FP64). */
 typedef enum {
     LBM_F64 = 0,
     LBM_F32 = 1,
@@ -96,9 +103,31 @@ typedef struct lbm_params {
     double cf_ref;        /* c_f,ref; <= 0: 0.2 c_pl                              */
     double cm_ref;        /* c_m,ref; <= 0: 1.0 c_pm                              */
     double J;             /* viscosity ratio nu_e / nu_f; <= 0: 1                 */
-    double T_hot, T_cold; /* isothermal wall temperatures; T_0 = T_cold          */
+    double T_hot, T_cold; /* temperatures of the default hot (x=0) and cold
+                             (x=nx-1) walls; Delta T = T_hot - T_cold sets the
+                             latent heat, the buoyancy scale and the Nusselt
+                             numbers; T_0 = T_cold (Eq. 7)                     */
     double T_init;        /* initial temperature of both phases                   */
     double T_solidus, T_liquidus;
+    int32_t thermal_lattice;   /* 0 or 9: D2Q9 thermal fields (Sec. III B/C);
+                                  5: D2Q5 thermal fields (Appendix B)          */
+    int32_t thermal_collision; /* 0: MRT (rates of Sec. III C); 1: BGK thermal
+                                  collisions, every rate 1/tau (Sec. V A)     */
+    double varpi;              /* D2Q5 weight parameter in (0,1), Eq. (B2);
+                                  <= 0: 2/3 (c_sT^2 = 1/3)                     */
+    double zeta_e;             /* > 0: fixed zeta_e = zeta_eps in (0,2)
+                                  (Sec. V D); <= 0: zeta_e = zeta_eps =
+                                  2 - zeta_alpha (Eq. 53, Sec. III C)         */
+    int32_t wall_type[4];      /* left, right, bottom, top: 0 the cavity's own
+                                  (isothermal T_hot / T_cold left / right,
+                                  adiabatic bottom and top), 1 isothermal at
+                                  wall_T, 2 adiabatic.  At a corner an
+                                  isothermal vertical wall wins, then an
+                                  isothermal horizontal wall.  Periodic
+                                  problems (bc_x = 1) take 0 left and right. */
+    double wall_T[4];          /* temperatures of walls of type 1             */
+    double L_char;             /* > 0: characteristic length for Ra, Da, d_p,
+                                  Fo and Nu; <= 0: nx - 1 (periodic: ny - 1)  */
 } lbm_params;
 
 /* Derived lattice constants of one cavity (read-only view). */
@@ -106,9 +135,14 @@ typedef struct lbm_lattice {
     double L;                        /* characteristic length nx-1 (channel: ny-1) */
     double k_f, k_m, nu_f, nu_e, K, F_phi, gbeta, h_v, L_a, d_p, z;
     double tau_v, tau_g, tau_h;
-    double s[9], zeta[9], eta[9];    /* relaxation rates in moment order of Eq. (13) */
+    double s[9], zeta[9], eta[9];    /* relaxation rates in moment order of Eq. (13);
+                                        D2Q5: zeta[0..4], eta[0..4] in the
+                                        moment order of Eq. (B1), rest 1 */
     double H_fs, H_fl, T_ref, H_ref;
     double scale_exp[3];             /* storage scale exponents (f, g, h) */
+    double q_thermal;                /* thermal velocities: 9 or 5 */
+    double varpi;                    /* D2Q5 weight parameter (0 on D2Q9) */
+    double wall_type[4], wall_T[4];  /* resolved: 1 isothermal, 2 adiabatic */
 } lbm_lattice;
 
 /* Diagnostics of one cavity at the current step (all FP64).
@@ -231,12 +265,14 @@ lbm_status lbm_load(lbm_handle *h, const char *path);
 /* Copy the raw stored populations of one cavity to host memory, for
  * bit-level comparisons: every stored plane of the cavity in storage order
  * ([plane][ny][nx], planes as listed for lbm_precision), i.e. (bytes per
- * node) * nx * ny bytes: 216, 108, 54, 54, 72 or 112 per node. */
+ * node) * nx * ny bytes: 216, 108, 54, 54, 72 or 112 per node on D2Q9,
+ * 152, 76 or 80 on D2Q5. */
 lbm_status lbm_copy_state(lbm_handle *h, int32_t cavity, void *host, uint64_t bytes);
 
 /* Overwrite one stored population of the current state with value,
  * converted to the element type it is stored in (test hook for the
- * failure-detection path).  field: 0 f, 1 g, 2 h; dir: 0..8. */
+ * failure-detection path).  field: 0 f, 1 g, 2 h; dir: 0..8 (0..4 for g
+ * and h on D2Q5). */
 lbm_status lbm_debug_poke(lbm_handle *h, int32_t cavity, int32_t x, int32_t y, int32_t field,
                           int32_t dir, double value);
 

@@ -160,8 +160,10 @@ def lattice_params(p: dict) -> dict:
     alpha_mref = k_m / (rho_m * c_mref)
     eta_a = 1.0 / (0.5 + alpha_mref / cs2T)
     # Sec. III C free rates; zeta_e = zeta_eps = 2 - zeta_alpha (Eq. 53) unless
-    # zeta_e is given (Sec. V D); the conserved-moment rates zeta_0 and s_rho
-    # multiply zero and are 1.  D2Q5 (Appendix B): Theta = diag(zeta_0,
+    # zeta_e is given (Sec. V D), which then sets the pair zeta_e = zeta_eps
+    # as Sec. III C does (moving zeta_e alone is unstable with flow even at
+    # the Sec. IV B parameters, where Sec. V D reports runs up to 1.8); the
+    # conserved-moment rates zeta_0 and s_rho multiply zero and are 1.  D2Q5 (Appendix B): Theta = diag(zeta_0,
     # zeta_a, zeta_a, zeta_e, zeta_eps), Q = diag(eta_0, eta_a, eta_a, eta_e,
     # eta_eps), the free rates as for D2Q9; entries 5..8 unused (1).  BGK
     # (Sec. V A): every thermal rate 1/tau_g or 1/tau_h.
@@ -174,10 +176,10 @@ def lattice_params(p: dict) -> dict:
     else:
         ze = zeta_e_given if zeta_e_given > 0 else 2.0 - zeta_a
         if qt == 9:
-            zeta = [1.0, ze, 2.0 - zeta_a, zeta_a, zeta_a, zeta_a, zeta_a, 1.2, 1.2]
+            zeta = [1.0, ze, ze, zeta_a, zeta_a, zeta_a, zeta_a, 1.2, 1.2]
             eta = [1.0, 1.1, 1.1, eta_a, eta_a, eta_a, eta_a, 1.2, 1.2]
         else:
-            zeta = [1.0, zeta_a, zeta_a, ze, 2.0 - zeta_a, 1.0, 1.0, 1.0, 1.0]
+            zeta = [1.0, zeta_a, zeta_a, ze, ze, 1.0, 1.0, 1.0, 1.0]
             eta = [1.0, eta_a, eta_a, 1.1, 1.1, 1.0, 1.0, 1.0, 1.0]
     for name, r in (("s", s), ("zeta", zeta), ("eta", eta)):
         if not all(0.0 < v < 2.0 for v in r):

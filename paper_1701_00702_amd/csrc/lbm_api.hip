@@ -47,10 +47,15 @@ namespace {
 
 struct Lattice {
     int nx, ny, periodic, gaxis;
+    int qt;                 // thermal velocities: 9 or 5
+    double varpi, cs2T;     // D2Q5 weight parameter, thermal sound speed squared
     double phi, rho_l, rho_m, c_pl, c_ps, c_pm, c_fref, c_mref;
     double L, k_f, k_m, nu_f, nu_e, K, F_phi, gbeta, T0, h_v, L_a, d_p, z;
     double T_fs, T_fl, H_fs, H_fl, T_ref, H_ref;
     double T_hot, T_cold, T_init;
+    int wall_type[4];       // resolved: 1 isothermal, 2 adiabatic
+    double wall_T[4];
+    double zeta_a, eta_a;
     double s[9], zeta[9], eta[9];
     int scale_exp[3];
 };
@@ -63,8 +68,12 @@ double enthalpy_of(const Lattice &l, double T) {
 }
 
 // Characteristic length: distance between the walls that carry the imposed
-// temperature difference; for the periodic channel, between the no-slip walls.
-double char_length(const lbm_params &p) { return p.bc_x == 1 ? p.ny - 1.0 : p.nx - 1.0; }
+// temperature difference; for the periodic channel, between the no-slip
+// walls; or the problem's own.
+double char_length(const lbm_params &p) {
+    if (p.L_char > 0) return p.L_char;
+    return p.bc_x == 1 ? p.ny - 1.0 : p.nx - 1.0;
+}
 
 lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     if (p.nx < 4 || p.ny < 4) return fail(LBM_EINVAL, "grid %dx%d: each side needs >= 4 nodes", p.nx, p.ny);
@@ -82,6 +91,36 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     if (!(p.Nu_i >= 0.0)) return fail(LBM_EINVAL, "Nu_i must be non-negative");
     if (!(p.T_hot > p.T_cold)) return fail(LBM_EINVAL, "T_hot must exceed T_cold");
     if (!(p.T_liquidus > p.T_solidus)) return fail(LBM_EINVAL, "T_liquidus must exceed T_solidus");
+    if (p.thermal_lattice != 0 && p.thermal_lattice != 9 && p.thermal_lattice != 5)
+        return fail(LBM_EINVAL, "thermal_lattice must be 9 or 5");
+    if (p.thermal_collision != 0 && p.thermal_collision != 1)
+        return fail(LBM_EINVAL, "thermal_collision must be 0 (MRT) or 1 (BGK)");
+    l.qt = p.thermal_lattice == 5 ? 5 : 9;
+    if (l.qt == 5 && prec != LBM_F64 && prec != LBM_F32 && prec != LBM_F32_H64)
+        return fail(LBM_EINVAL, "D2Q5 thermal fields are stored as LBM_F64, LBM_F32 or LBM_F32_H64");
+    l.varpi = 0.0;
+    l.cs2T = 1.0 / 3.0;
+    if (l.qt == 5) {
+        l.varpi = p.varpi > 0 ? p.varpi : 2.0 / 3.0;
+        if (!(l.varpi < 1.0)) return fail(LBM_EINVAL, "varpi %g not in (0,1) (Eq. B2)", p.varpi);
+        l.cs2T = 0.5 * l.varpi;
+    }
+    if (p.thermal_collision == 1 && p.zeta_e > 0)
+        return fail(LBM_EINVAL, "zeta_e cannot be set for BGK thermal collisions");
+    for (int w = 0; w < 4; ++w)
+        if (p.wall_type[w] < 0 || p.wall_type[w] > 2)
+            return fail(LBM_EINVAL, "wall_type[%d] = %d: 0 default, 1 isothermal, 2 adiabatic", w, p.wall_type[w]);
+    if (p.bc_x == 1 && (p.wall_type[W_LEFT] != 0 || p.wall_type[W_RIGHT] != 0))
+        return fail(LBM_EINVAL, "a periodic-in-x problem has no left or right wall");
+    {
+        // the cavity of Sec. IV B unless a wall says otherwise
+        const int def_t[4] = {p.bc_x == 1 ? 2 : 1, p.bc_x == 1 ? 2 : 1, 2, 2};
+        const double def_T[4] = {p.bc_x == 1 ? 0.0 : p.T_hot, p.bc_x == 1 ? 0.0 : p.T_cold, 0.0, 0.0};
+        for (int w = 0; w < 4; ++w) {
+            l.wall_type[w] = p.wall_type[w] == 0 ? def_t[w] : p.wall_type[w];
+            l.wall_T[w] = p.wall_type[w] == 0 ? def_T[w] : (p.wall_type[w] == 1 ? p.wall_T[w] : 0.0);
+        }
+    }
     l.nx = p.nx;
     l.ny = p.ny;
     l.periodic = p.bc_x;
@@ -101,9 +140,10 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     double kf = p.k_f;
     if (!(kf > 0)) {
         // largest k_f with tau_v, tau_g, tau_h <= 2 and z <= 0.5
+        // tau = 0.5 + alpha_ref / c_s^2 <= 2  <=>  alpha_ref <= 1.5 c_s^2
         kf = 0.5 / (J * p.Pr);
-        kf = std::min(kf, 0.5 * l.rho_l * l.c_fref);
-        if (p.k_ratio > 0) kf = std::min(kf, 0.5 * l.rho_m * l.c_mref / p.k_ratio);
+        kf = std::min(kf, 1.5 * l.cs2T * l.rho_l * l.c_fref);
+        if (p.k_ratio > 0) kf = std::min(kf, 1.5 * l.cs2T * l.rho_m * l.c_mref / p.k_ratio);
         if (p.Nu_i > 0)
             kf = std::min(kf, 0.5 * l.d_p * l.d_p /
                                   (p.Nu_i * (1.0 / (l.phi * l.rho_l * l.c_pl) +
@@ -131,14 +171,40 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     l.T_cold = p.T_cold;
     l.T_init = p.T_init;
     // relaxation rates: s_v from nu_e (Eq. 26); zeta_alpha, eta_alpha from the
-    // reference diffusivities (Eq. A19 and after Eq. 51); free rates and
-    // zeta_e = zeta_eps = 2 - zeta_alpha (Sec. III C, Eq. 53)
+    // reference diffusivities with the thermal lattice's sound speed (Eq. A19
+    // and after Eq. 51; App. B); free rates and zeta_e = zeta_eps =
+    // 2 - zeta_alpha (Sec. III C, Eq. 53), or the given zeta_e (Sec. V D)
+    // for the pair zeta_e = zeta_eps.
+    // D2Q5 rates in the moment order of Eq. (B1), entries 5..8 unused (1).
+    // BGK (Sec. V A): every thermal rate 1/tau.
     const double s_v = 1.0 / (0.5 + 3.0 * l.nu_e);
-    const double za = 1.0 / (0.5 + 3.0 * kf / (l.rho_l * l.c_fref));
-    const double ea = 1.0 / (0.5 + 3.0 * l.k_m / (l.rho_m * l.c_mref));
+    const double za = 1.0 / (0.5 + kf / (l.rho_l * l.c_fref) / l.cs2T);
+    const double ea = 1.0 / (0.5 + l.k_m / (l.rho_m * l.c_mref) / l.cs2T);
+    const double ze = p.zeta_e > 0 ? p.zeta_e : 2.0 - za;
+    l.zeta_a = za;
+    l.eta_a = ea;
     const double s[9] = {1.0, 1.1, 1.1, 1.0, 1.2, 1.0, 1.2, s_v, s_v};
-    const double zt[9] = {1.0, 2.0 - za, 2.0 - za, za, za, za, za, 1.2, 1.2};
-    const double et[9] = {1.0, 1.1, 1.1, ea, ea, ea, ea, 1.2, 1.2};
+    double zt[9], et[9];
+    if (p.thermal_collision == 1) {
+        for (int k = 0; k < 9; ++k) {
+            zt[k] = k < l.qt ? za : 1.0;
+            et[k] = k < l.qt ? ea : 1.0;
+        }
+    } else if (l.qt == 9) {
+        const double z9[9] = {1.0, ze, ze, za, za, za, za, 1.2, 1.2};
+        const double e9[9] = {1.0, 1.1, 1.1, ea, ea, ea, ea, 1.2, 1.2};
+        for (int k = 0; k < 9; ++k) {
+            zt[k] = z9[k];
+            et[k] = e9[k];
+        }
+    } else {
+        const double z5[9] = {1.0, za, za, ze, ze, 1.0, 1.0, 1.0, 1.0};
+        const double e5[9] = {1.0, ea, ea, 1.1, 1.1, 1.0, 1.0, 1.0, 1.0};
+        for (int k = 0; k < 9; ++k) {
+            zt[k] = z5[k];
+            et[k] = e5[k];
+        }
+    }
     for (int k = 0; k < 9; ++k) {
         l.s[k] = s[k];
         l.zeta[k] = zt[k];
@@ -187,12 +253,14 @@ ThermalConst<T> make_thermal(const Lattice &l) {
     t.c_fref = (T)l.c_fref;
     t.inv_phi = (T)(1.0 / l.phi);
     for (int k = 0; k < 9; ++k) t.zeta[k] = (T)l.zeta[k];
+    t.varpi = (T)l.varpi;
+    t.inv_cs2 = (T)(l.qt == 9 ? 3.0 : 2.0 / l.varpi);
     t.T_ref = (T)l.T_ref;
     t.H_ref = (T)l.H_ref;
-    t.T_hot = (T)l.T_hot;
-    t.T_cold = (T)l.T_cold;
-    t.H_hot = (T)enthalpy_of(l, l.T_hot);
-    t.H_cold = (T)enthalpy_of(l, l.T_cold);
+    for (int w = 0; w < 4; ++w) {
+        t.T_wall[w] = (T)l.wall_T[w];
+        t.H_wall[w] = (T)enthalpy_of(l, l.wall_T[w]);
+    }
     return t;
 }
 
@@ -231,8 +299,11 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
     c.hv_m = (R)hvm;
     c.sr_ratio = (R)((l.phi * l.rho_l) / ((1.0 - l.phi) * l.rho_m));
     c.T_ref = (R)l.T_ref;
-    c.T_hot = (R)l.T_hot;
-    c.T_cold = (R)l.T_cold;
+    c.varpi = (R)l.varpi;
+    for (int w = 0; w < 4; ++w) {
+        c.T_wall[w] = (R)l.wall_T[w];
+        c.wall_iso[w] = l.wall_type[w] == 1 ? 1 : 0;
+    }
     for (int f = 0; f < 3; ++f) {
         c.scale[f] = (R)std::ldexp(1.0, l.scale_exp[f]);
         c.inv_scale[f] = (R)std::ldexp(1.0, -l.scale_exp[f]);
@@ -241,10 +312,13 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
     c.td = make_thermal<double>(l);
     c.we = l.phi * l.rho_l;
     c.wm = (1.0 - l.phi) * l.rho_m;
+    // reference equilibria at rest (Eqs. 40, 49 / Eqs. B3, B5)
     const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const double wrest = l.qt == 9 ? 5.0 / 9.0 : l.varpi;
     for (int i = 0; i < 9; ++i) {
-        c.g_ref[i] = i == 0 ? l.H_ref - 5.0 / 9.0 * l.c_fref * l.T_ref : w[i] * l.c_fref * l.T_ref;
-        c.h_ref[i] = i == 0 ? (l.c_pm - 5.0 / 9.0 * l.c_mref) * l.T_ref : w[i] * l.c_mref * l.T_ref;
+        const double wi = l.qt == 9 ? w[i] : (i < 5 ? 0.25 * l.varpi : 0.0);
+        c.g_ref[i] = i == 0 ? l.H_ref - wrest * l.c_fref * l.T_ref : wi * l.c_fref * l.T_ref;
+        c.h_ref[i] = i == 0 ? (l.c_pm - wrest * l.c_mref) * l.T_ref : wi * l.c_mref * l.T_ref;
     }
     c.T_init = l.T_init;
     return c;
@@ -252,7 +326,15 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int storage_of(lbm_precision p) {
+int storage_of(lbm_precision p, int qt = 9) {
+    if (qt == 5) {
+        switch (p) {
+            case LBM_F64: return ST5_F64;
+            case LBM_F32: return ST5_F32;
+            case LBM_F32_H64: return ST5_F32H;
+            default: return -1;
+        }
+    }
     switch (p) {
         case LBM_F64: return ST_F64;
         case LBM_F32: return ST_F32;
@@ -264,7 +346,7 @@ int storage_of(lbm_precision p) {
     return -1;
 }
 
-size_t real_size(int st) { return st == ST_F64 ? 8 : 4; }
+size_t real_size(int st) { return (st == ST_F64 || st == ST5_F64) ? 8 : 4; }
 
 // Plane groups of one buffer: {number of planes, bytes per element}.
 struct PlaneGroup {
@@ -278,12 +360,16 @@ int plane_groups(int st, PlaneGroup g[2]) {
         case ST_BF16: g[0] = {27, 2}; return 1;
         case ST_F16S: g[0] = {6, 4}; g[1] = {24, 2}; return 2;
         case ST_F32H: g[0] = {26, 4}; g[1] = {1, 8}; return 2;
+        case ST5_F64: g[0] = {19, 8}; return 1;
+        case ST5_F32: g[0] = {19, 4}; return 1;
+        case ST5_F32H: g[0] = {18, 4}; g[1] = {1, 8}; return 2;
     }
     return 0;
 }
 
 // Memory plan shared by lbm_workspace_bytes and the create calls.
 struct Plan {
+    int st = -1;  // storage form (precision and thermal lattice)
     std::vector<Lattice> lat;
     std::vector<int64_t> node0, acc0;
     int64_t nodes = 0, stride = 0, slots = 0, max_nodes = 0;
@@ -296,7 +382,10 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     if (!p) return fail(LBM_EINVAL, "params is NULL");
     if (n < 1) return fail(LBM_EINVAL, "need at least one cavity");
     if (storage_of(prec) < 0) return fail(LBM_EINVAL, "unknown precision %d", (int)prec);
-    const int st = storage_of(prec);
+    const int qt0 = p[0].thermal_lattice == 5 ? 5 : 9;
+    for (int c = 1; c < n; ++c)
+        if ((p[c].thermal_lattice == 5 ? 5 : 9) != qt0)
+            return fail(LBM_EINVAL, "cavity %d: every cavity of a batch needs the same thermal lattice", c);
     pl.lat.resize(n);
     int64_t tiles = 0;
     for (int c = 0; c < n; ++c) {
@@ -321,6 +410,8 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     if (pl.nodes >= ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "more than 2^31 nodes in total");
     if (tiles >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
     pl.max_tiles = (int)tiles;
+    pl.st = storage_of(prec, qt0);
+    const int st = pl.st;
     pl.stride = (pl.nodes + 127) & ~(int64_t)127;
     size_t off = 0;
     for (int b = 0; b < 2; ++b) {
@@ -588,7 +679,7 @@ lbm_status create_common(const lbm_params *p, int n, lbm_precision prec, void *w
         return s;
     }
     h->prec = prec;
-    h->st = storage_of(prec);
+    h->st = h->pl.st;
     h->n = n;
     h->params.assign(p, p + n);
     h->stream = (hipStream_t)stream;
@@ -809,8 +900,8 @@ void fill_lattice(const Lattice &l, lbm_lattice *out) {
     out->d_p = l.d_p;
     out->z = l.z;
     out->tau_v = 1.0 / l.s[7];
-    out->tau_g = 1.0 / l.zeta[3];
-    out->tau_h = 1.0 / l.eta[3];
+    out->tau_g = 1.0 / l.zeta_a;
+    out->tau_h = 1.0 / l.eta_a;
     for (int k = 0; k < 9; ++k) {
         out->s[k] = l.s[k];
         out->zeta[k] = l.zeta[k];
@@ -821,6 +912,12 @@ void fill_lattice(const Lattice &l, lbm_lattice *out) {
     out->T_ref = l.T_ref;
     out->H_ref = l.H_ref;
     for (int f = 0; f < 3; ++f) out->scale_exp[f] = l.scale_exp[f];
+    out->q_thermal = l.qt;
+    out->varpi = l.varpi;
+    for (int w = 0; w < 4; ++w) {
+        out->wall_type[w] = l.wall_type[w];
+        out->wall_T[w] = l.wall_T[w];
+    }
 }
 }  // namespace
 
@@ -868,7 +965,7 @@ std::string tune_key(lbm_handle *h) {
     for (char &ch : arch)
         if (ch == ' ') ch = '_';
     char buf[256];
-    snprintf(buf, sizeof(buf), "%s:prec%d:n%d:nodes%lld:nx%d:ny%d", arch.c_str(), (int)h->prec, h->n,
+    snprintf(buf, sizeof(buf), "%s:st%d:n%d:nodes%lld:nx%d:ny%d", arch.c_str(), h->st, h->n,
              (long long)h->pl.nodes, h->params[0].nx, h->params[0].ny);
     return buf;
 }
@@ -1059,18 +1156,21 @@ extern "C" lbm_status lbm_debug_poke(lbm_handle *h, int32_t c, int32_t x, int32_
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
     const lbm_params &p = h->params[c];
-    if (x < 0 || x >= p.nx || y < 0 || y >= p.ny || field < 0 || field > 2 || dir < 0 || dir > 8)
+    const int qt = h->pl.lat[c].qt;
+    if (x < 0 || x >= p.nx || y < 0 || y >= p.ny || field < 0 || field > 2 || dir < 0 ||
+        dir > (field == 0 ? 8 : qt - 1))
         return fail(LBM_EINVAL, "poke index out of range");
     const int64_t node = h->pl.node0[c] + (int64_t)y * p.nx + x;
     char *base = (char *)h->pop(h->cur);
     char *ptr;
     int elem;
-    if (h->st == ST_F32H) {
+    if (h->st == ST_F32H || h->st == ST5_F32H) {
+        const int nf32 = 8 + 2 * qt;
         if (field == 1 && dir == 0) {
-            ptr = base + (size_t)26 * h->pl.stride * 4 + (size_t)node * 8;
+            ptr = base + (size_t)nf32 * h->pl.stride * 4 + (size_t)node * 8;
             elem = 8;
         } else {
-            const int plane = field == 0 ? dir : (field == 1 ? 8 + dir : 17 + dir);
+            const int plane = field == 0 ? dir : (field == 1 ? 8 + dir : 8 + qt + dir);
             ptr = base + ((size_t)plane * h->pl.stride + node) * 4;
             elem = 4;
         }
@@ -1083,8 +1183,9 @@ extern "C" lbm_status lbm_debug_poke(lbm_handle *h, int32_t c, int32_t x, int32_
             elem = 2;
         }
     } else {
-        const int eb = bytes_per_node(h->st) / 27;
-        ptr = base + ((size_t)(field * 9 + dir) * h->pl.stride + node) * eb;
+        const int eb = bytes_per_node(h->st) / (9 + 2 * qt);
+        const int plane = field == 0 ? dir : 9 + (field - 1) * qt + dir;
+        ptr = base + ((size_t)plane * h->pl.stride + node) * eb;
         elem = h->st == ST_BF16 ? 3 : eb;
     }
     HIP_TRY(launch_poke(elem, ptr, value, h->stream));

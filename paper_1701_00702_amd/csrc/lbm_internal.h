@@ -7,7 +7,12 @@
 
 namespace lbm {
 
-enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F16S = 4, ST_F32H = 5 };
+// Storage forms.  The first six carry D2Q9 thermal fields (27 populations
+// per node); the last three the D2Q5 thermal fields of Appendix B (19).
+enum Storage {
+    ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F16S = 4, ST_F32H = 5,
+    ST5_F64 = 6, ST5_F32 = 7, ST5_F32H = 8
+};
 
 enum Wall { W_LEFT = 0, W_RIGHT = 1, W_BOTTOM = 2, W_TOP = 3 };
 
@@ -17,10 +22,13 @@ template <typename T>
 struct ThermalConst {
     // enthalpy -> temperature, liquid fraction (Eqs. 38-39)
     T H_fs, H_fl, T_fs, T_fl, inv_dH, dT_band, inv_cps, inv_cpl;
-    // equilibrium (Eq. 34) and relaxation rates (Theta, Eq. 31)
+    // equilibrium (Eq. 34 / Eq. B2) and relaxation rates (Theta, Eq. 31 /
+    // App. B; D2Q5 uses the first five in the moment order of Eq. B1)
     T c_pl, c_fref, inv_phi, zeta[9];
-    // reference state and isothermal walls
-    T T_ref, H_ref, T_hot, T_cold, H_hot, H_cold;
+    // D2Q5: varpi and 1/c_sT^2 = 2/varpi (D2Q9: 1/c_s^2 = 3)
+    T varpi, inv_cs2;
+    // reference state and the isothermal wall values per wall
+    T T_ref, H_ref, T_wall[4], H_wall[4];
 };
 
 // Per-cavity constants in the arithmetic type R of the kernels.  One table
@@ -40,8 +48,10 @@ struct CavityConst {
     R gbeta, T0, drag_lin, drag_quad, l0, l0sq, l1;
     // interstitial exchange (Eqs. 36, 47): Sr_f = hv_f (T_m - T_f), Sr_m = hv_m (T_f - T_m)
     R hv_f, hv_m, sr_ratio;  // sr_ratio = hv_m / hv_f
-    // reference temperature of the stored offsets, isothermal walls (metal)
-    R T_ref, T_hot, T_cold;
+    // reference temperature of the stored offsets; per wall (left, right,
+    // bottom, top): isothermal (1) or adiabatic (0) and its temperature
+    R T_ref, T_wall[4], varpi;
+    int32_t wall_iso[4];
     // storage scale per field (populations are stored as (X - X_ref) * scale)
     R scale[3], inv_scale[3];
     // PCM enthalpy field
@@ -130,6 +140,6 @@ hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_init(const InitLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_poke(int elem, void *ptr, double value, hipStream_t s);
 int macro_blocks(int nx, int ny);
-int bytes_per_node(int storage);  // stored bytes of one node's 27 populations
+int bytes_per_node(int storage);  // stored bytes of one node's populations
 
 }  // namespace lbm

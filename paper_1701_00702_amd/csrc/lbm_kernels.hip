@@ -5,8 +5,9 @@
 // One launch of step_kernel advances every node of every cavity by one time
 // step.  One thread per node, pull streaming, structure-of-arrays planes,
 // A/B buffers; per node (lbm_node.h):
-//   1. pull the 27 post-collision populations of the neighbours (Eqs. 15, 33,
-//      44); a wall node instead pulls the populations of its interior partner
+//   1. pull the post-collision populations of the neighbours (Eqs. 15, 33,
+//      44; 27 with D2Q9 thermal fields, 19 with the D2Q5 ones of Appendix B);
+//      a wall node instead pulls the populations of its interior partner
 //      and rebuilds its own by non-equilibrium extrapolation (Eq. 52 and its
 //      thermal analogues);
 //   2. H (Eq. 37), T_f and f_l without iteration (Eqs. 38-39), T_m (Eq. 48),
@@ -15,8 +16,9 @@
 //   3. the flow collision in moment space with forcing (Eqs. 14, 16-19);
 //   4. interstitial sources with the backward-difference time derivative
 //      (Eqs. 36, 47, Remark III);
-//   5. the enthalpy and metal-foam collisions (Eqs. 32, 34-35; 43, 45-46);
-//   6. store the 27 post-collision populations and the source, and tally the
+//   5. the enthalpy and metal-foam collisions (Eqs. 32, 34-35; 43, 45-46;
+//      Eqs. B1-B5 on D2Q5);
+//   6. store the post-collision populations and the source, and tally the
 //      energy/mass carried across wall links (FP64, one slot per
 //      wall-adjacent node, no atomics).
 // The 9x9 transforms are expanded by hand (entries 0, +-1, +-2, +-4) and the
@@ -35,6 +37,9 @@ int bytes_per_node(int storage) {
         case ST_BF16: return LayoutOf<ST_BF16>::L::bytes_per_node;
         case ST_F16S: return LayoutOf<ST_F16S>::L::bytes_per_node;
         case ST_F32H: return LayoutOf<ST_F32H>::L::bytes_per_node;
+        case ST5_F64: return LayoutOf<ST5_F64>::L::bytes_per_node;
+        case ST5_F32: return LayoutOf<ST5_F32>::L::bytes_per_node;
+        case ST5_F32H: return LayoutOf<ST5_F32H>::L::bytes_per_node;
     }
     return 0;
 }
@@ -48,6 +53,9 @@ int bytes_per_node(int storage) {
         case ST_BF16: return FN<ST_BF16>(__VA_ARGS__);                     \
         case ST_F16S: return FN<ST_F16S>(__VA_ARGS__);                     \
         case ST_F32H: return FN<ST_F32H>(__VA_ARGS__);                     \
+        case ST5_F64: return FN<ST5_F64>(__VA_ARGS__);                     \
+        case ST5_F32: return FN<ST5_F32>(__VA_ARGS__);                     \
+        case ST5_F32H: return FN<ST5_F32H>(__VA_ARGS__);                   \
         default: return hipErrorInvalidValue;                              \
     }
 

@@ -11,6 +11,11 @@
 // the update runs on the offsets; in FP32 this keeps the small momentum of
 // the Darcy-scale flow out of the rounding of O(1) populations.
 //
+// The thermal fields run on D2Q9 (Sec. III B/C) or on the D2Q5 lattice of
+// Appendix B (its five velocities are the first five of Eq. 11); a layout
+// carries the number QT of thermal velocities.  Population arrays are sized
+// nine throughout; D2Q5 leaves entries 5..8 of g and h unused.
+//
 // Two arithmetic types: R for the flow and metal fields, RH for the PCM
 // enthalpy field (H, T_f, f_l and the g collision).  The rest enthalpy
 // population carries H itself, O(1), so its rounding is what limits FP32;
@@ -115,19 +120,23 @@ struct EB16 {  // bfloat16, round to nearest even (finite values)
 // ---------------------------------------------------------------------------
 // Storage layouts.  load<V>() returns the offset q_i of field f (0 flow,
 // 1 enthalpy, 2 metal), direction i, at packed node k, in type V; store()
-// writes the nine offsets of one field at node k.  beta is the per-node base
-// value the split layout stores (unused elsewhere).
+// writes the offsets of one field at node k (nine for the flow, QT for the
+// thermal fields).  beta is the per-node base value the split layout stores
+// (unused elsewhere).
 // ---------------------------------------------------------------------------
 
-// 27 planes of one element type; 16-bit forms carry a power-of-two scale.
-template <class E, bool SCALED>
+// 9 + 2 QT planes of one element type, [f0..f8, g0..g(QT-1), h0..h(QT-1)];
+// 16-bit forms carry a power-of-two scale.
+template <class E, bool SCALED, int QT_ = 9>
 struct Plain {
     using T = typename E::T;
     using C = decltype(E::dec(T()));  // element arithmetic type of the codec
-    static constexpr int bytes_per_node = 27 * (int)sizeof(T);
+    static constexpr int QT = QT_;
+    static constexpr int bytes_per_node = (9 + 2 * QT) * (int)sizeof(T);
+    LBM_HD static int plane(int f, int i) { return f == 0 ? i : 9 + (f - 1) * QT + i; }
     template <typename V, typename R>
     LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
-        const T *p = (const T *)base + (int64_t)(9 * f + i) * stride + k;
+        const T *p = (const T *)base + (int64_t)plane(f, i) * stride + k;
         const V v = (V)E::dec(ld_stream(p));
         return SCALED ? v * (V)c.inv_scale[f] : v;
     }
@@ -135,22 +144,27 @@ struct Plain {
     LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, int64_t k,
                              const CavityConst<R> &c) {
         (void)beta;
-        T *p = (T *)base + (int64_t)(9 * f) * stride + k;
+        T *p = (T *)base + (int64_t)plane(f, 0) * stride + k;
+        const int n = f == 0 ? 9 : QT;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st_stream(p + (int64_t)i * stride, E::enc((C)(SCALED ? q[i] * (V)c.scale[f] : q[i])));
+        for (int i = 0; i < 9; ++i)
+            if (i < n) st_stream(p + (int64_t)i * stride, E::enc((C)(SCALED ? q[i] * (V)c.scale[f] : q[i])));
     }
 };
 
-// FP32 planes for 26 populations and one FP64 plane for the rest enthalpy
-// population: planes [f0..f8, g1..g8, h0..h8] in FP32, then g0 in FP64;
-// 112 bytes per node.
+// FP32 planes for all populations but the rest enthalpy one, which gets an
+// FP64 plane: [f0..f8, g1..g(QT-1), h0..h(QT-1)] in FP32 (8 + 2 QT planes),
+// then g0 in FP64; 112 bytes per node on D2Q9, 80 on D2Q5.
+template <int QT_ = 9>
 struct PlainH64 {
-    static constexpr int bytes_per_node = 26 * 4 + 8;
-    LBM_HD static int plane(int f, int i) { return f == 0 ? i : (f == 1 ? 8 + i : 17 + i); }
+    static constexpr int QT = QT_;
+    static constexpr int NF32 = 8 + 2 * QT;
+    static constexpr int bytes_per_node = NF32 * 4 + 8;
+    LBM_HD static int plane(int f, int i) { return f == 0 ? i : (f == 1 ? 8 + i : 8 + QT + i); }
     template <typename V, typename R>
     LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
         (void)c;
-        if (f == 1 && i == 0) return (V)ld_stream((const double *)((const float *)base + 26 * stride) + k);
+        if (f == 1 && i == 0) return (V)ld_stream((const double *)((const float *)base + NF32 * stride) + k);
         return (V)ld_stream((const float *)base + (int64_t)plane(f, i) * stride + k);
     }
     template <typename V, typename R>
@@ -158,9 +172,11 @@ struct PlainH64 {
                              const CavityConst<R> &c) {
         (void)beta;
         (void)c;
+        const int n = f == 0 ? 9 : QT;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            if (f == 1 && i == 0) st_stream((double *)((float *)base + 26 * stride) + k, (double)q[0]);
+            if (i >= n) continue;
+            if (f == 1 && i == 0) st_stream((double *)((float *)base + NF32 * stride) + k, (double)q[0]);
             else st_stream((float *)base + (int64_t)plane(f, i) * stride + k, (float)q[i]);
         }
     }
@@ -176,6 +192,7 @@ struct PlainH64 {
 // Planes: 6 FP32 planes [q_f0, beta_f, q_g0, beta_g, q_h0, beta_h], then 24
 // FP16 planes [field][direction 1..8]; 72 bytes per node.
 struct Split16 {
+    static constexpr int QT = 9;
     static constexpr int bytes_per_node = 6 * 4 + 24 * 2;
     template <typename V, typename R>
     LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
@@ -235,7 +252,25 @@ struct LayoutOf<ST_F16S> {
 };
 template <>
 struct LayoutOf<ST_F32H> {
-    using L = PlainH64;
+    using L = PlainH64<9>;
+    using R = float;
+    using RH = double;
+};
+template <>
+struct LayoutOf<ST5_F64> {
+    using L = Plain<E64, false, 5>;
+    using R = double;
+    using RH = double;
+};
+template <>
+struct LayoutOf<ST5_F32> {
+    using L = Plain<E32, false, 5>;
+    using R = float;
+    using RH = float;
+};
+template <>
+struct LayoutOf<ST5_F32H> {
+    using L = PlainH64<5>;
     using R = float;
     using RH = double;
 };
@@ -292,6 +327,36 @@ LBM_HD R sum9(const R q[9]) {
     return ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7])) + q[8];
 }
 
+// Zeroth moment of QT populations.
+template <int QT, typename R>
+LBM_HD R sumq(const R q[9]) {
+    if (QT == 9) return sum9(q);
+    return ((q[0] + q[1]) + (q[2] + q[3])) + q[4];
+}
+
+// D2Q5 transforms of Eq. (B1) on offsets: d = M q, and its inverse
+// q0 = d0 - d3, q1,3 = (d3 + d4)/4 +- d1/2, q2,4 = (d3 - d4)/4 +- d2/2.
+template <typename R>
+LBM_HD void to_moments5(const R q[9], R d[5]) {
+    const R ax = q[1] + q[3], ay = q[2] + q[4];
+    d[0] = ((q[0] + q[1]) + (q[2] + q[3])) + q[4];
+    d[1] = q[1] - q[3];
+    d[2] = q[2] - q[4];
+    d[3] = ax + ay;
+    d[4] = ax - ay;
+}
+
+template <typename R>
+LBM_HD void from_moments5(const R d[5], R q[9]) {
+    const R a = (d[3] + d[4]) * R(0.25), b = (d[3] - d[4]) * R(0.25);
+    const R hx = d[1] * R(0.5), hy = d[2] * R(0.5);
+    q[0] = d[0] - d[3];
+    q[1] = a + hx;
+    q[3] = a - hx;
+    q[2] = b + hy;
+    q[4] = b - hy;
+}
+
 // ---------------------------------------------------------------------------
 // Macroscopic values of one node from its post-streaming offsets.
 // ---------------------------------------------------------------------------
@@ -320,18 +385,18 @@ LBM_HD void eos(const ThermalConst<RH> &t, RH H, RH &T, RH &fl) {
 }
 
 // Blends qf in place (Eq. 20) and computes everything the collisions need.
-template <typename R, typename RH>
+template <int QT, typename R, typename RH>
 LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[9], Thermo<RH> &th,
                    Macro<R> &m) {
     const ThermalConst<RH> &t = thermal<RH>(c);
     // Eq. (37), Eqs. (38)-(39)
-    th.dH = sum9(qg);
+    th.dH = sumq<QT>(qg);
     th.H = t.H_ref + th.dH;
     eos(t, th.H, th.Tf, th.fl);
     m.Tf = (R)th.Tf;
     m.fl = (R)th.fl;
     // Eq. (48)
-    m.dTm = sum9(qh) * c.inv_cpm;
+    m.dTm = sumq<QT>(qh) * c.inv_cpm;
     m.Tm = c.T_ref + m.dTm;
     // Eq. (21)
     m.drho = sum9(qf);
@@ -438,26 +503,77 @@ LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal,
     from_moments(d, q);
 }
 
+// D2Q5 enthalpy collision (Appendix B): equilibrium moments Eq. (B2) on
+// offsets, Theta in the moment order of Eq. (B1), source S (1, 0, 0, varpi, 0).
+template <typename R, typename RH>
+LBM_HD void collide_pcm5(const CavityConst<R> &c, const Thermo<RH> &th, const Macro<R> &m, RH S_pcm,
+                         RH q[9]) {
+    const ThermalConst<RH> &t = thermal<RH>(c);
+    RH d[5];
+    to_moments5(q, d);
+    const RH jT = t.c_pl * th.Tf * t.inv_phi;
+    RH eq[5];
+    eq[0] = th.dH;
+    eq[1] = jT * (RH)m.ux;
+    eq[2] = jT * (RH)m.uy;
+    eq[3] = t.varpi * t.c_fref * (th.Tf - t.T_ref);
+    eq[4] = RH(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) d[k] = d[k] - t.zeta[k] * (d[k] - eq[k]);
+    d[0] += S_pcm;
+    d[3] += t.varpi * S_pcm;
+    from_moments5(d, q);
+}
+
+// D2Q5 metal-foam collision (Appendix B): Eq. (B4), Q, S (1, 0, 0, varpi, 0).
+template <typename R>
+LBM_HD void collide_metal5(const CavityConst<R> &c, const Macro<R> &m, R S_metal, R q[9]) {
+    R d[5];
+    to_moments5(q, d);
+    R eq[5];
+    eq[0] = c.c_pm * m.dTm;
+    eq[1] = R(0);
+    eq[2] = R(0);
+    eq[3] = c.varpi * c.c_mref * m.dTm;
+    eq[4] = R(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) d[k] = d[k] - c.eta[k] * (d[k] - eq[k]);
+    d[0] += S_metal;
+    d[3] += c.varpi * S_metal;
+    from_moments5(d, q);
+}
+
+// Wall whose thermal condition a wall node carries: an isothermal vertical
+// wall, else an isothermal horizontal wall, else -1 (adiabatic: the node
+// copies its partner's temperature).
+template <typename R>
+LBM_HD int thermal_wall(const CavityConst<R> &c, int x, int y) {
+    const int v = c.periodic ? -1 : (x == 0 ? W_LEFT : (x == c.nx - 1 ? W_RIGHT : -1));
+    const int h = y == 0 ? W_BOTTOM : (y == c.ny - 1 ? W_TOP : -1);
+    if (v >= 0 && c.wall_iso[v]) return v;
+    if (h >= 0 && c.wall_iso[h]) return h;
+    return -1;
+}
+
 // Non-equilibrium extrapolation for wall node (x, y), applied in place to
 // the partner's pulled offsets (Eq. 52 with wall velocity 0; thermal
 // analogues with the isothermal or zero-gradient wall values).
-template <typename R, typename RH>
-LBM_HD void reconstruct_wall(const CavityConst<R> &c, int x, R qf[9], RH qg[9], R qh[9]) {
+template <int QT, typename R, typename RH>
+LBM_HD void reconstruct_wall(const CavityConst<R> &c, int x, int y, R qf[9], RH qg[9], R qh[9]) {
     const ThermalConst<RH> &t = thermal<RH>(c);
     R tf[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) tf[i] = qf[i];
     Thermo<RH> pt;
     Macro<R> p;
-    macros(c, tf, qg, qh, pt, p);
+    macros<QT>(c, tf, qg, qh, pt, p);
     RH Tb, Hb;
     R Tmb;
-    const bool vertical = !c.periodic && (x == 0 || x == c.nx - 1);
-    if (vertical) {
-        const bool hot = (x == 0);
-        Tb = hot ? t.T_hot : t.T_cold;
-        Hb = hot ? t.H_hot : t.H_cold;
-        Tmb = hot ? c.T_hot : c.T_cold;
+    const int w = thermal_wall(c, x, y);
+    if (w >= 0) {
+        Tb = t.T_wall[w];
+        Hb = t.H_wall[w];
+        Tmb = c.T_wall[w];
     } else {
         Tb = pt.Tf;
         Hb = pt.H;
@@ -466,19 +582,28 @@ LBM_HD void reconstruct_wall(const CavityConst<R> &c, int x, R qf[9], RH qg[9], 
     const R uu = p.ux * p.ux + p.uy * p.uy;
     const RH dTg = Tb - pt.Tf;
     const R dTh = Tmb - p.Tm;
-    const RH jT = RH(3) * t.c_pl * pt.Tf * t.inv_phi;
+    // g^eq(H_b, T_b, 0) - g^eq(H, T, u) from Eq. (40) / Eq. (B3); h likewise
+    // from Eq. (49) / Eq. (B5)
+    const RH jT = t.inv_cs2 * t.c_pl * pt.Tf * t.inv_phi;
     qf[0] += -w_of<R>(0) * p.rho * (-R(1.5) * uu * c.inv_phi);
-    qg[0] += (Hb - pt.H) - RH(5) / RH(9) * t.c_fref * dTg;
-    qh[0] += (c.c_pm - R(5) / R(9) * c.c_mref) * dTh;
+    if (QT == 9) {
+        qg[0] += (Hb - pt.H) - RH(5) / RH(9) * t.c_fref * dTg;
+        qh[0] += (c.c_pm - R(5) / R(9) * c.c_mref) * dTh;
+    } else {
+        qg[0] += (Hb - pt.H) - t.varpi * t.c_fref * dTg;
+        qh[0] += (c.c_pm - c.varpi * c.c_mref) * dTh;
+    }
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
         const R eu = R(ex_of(i)) * p.ux + R(ey_of(i)) * p.uy;
         // f^eq(rho, 0) - f^eq(rho, u) from Eq. (27)
         qf[i] += -w_of<R>(i) * p.rho * (R(3) * eu + R(4.5) * eu * eu * c.inv_phi - R(1.5) * uu * c.inv_phi);
-        // g^eq(H_b, T_b, 0) - g^eq(H, T, u) from Eq. (40)
-        qg[i] += w_of<RH>(i) * (t.c_fref * dTg - jT * (RH)eu);
-        // h^eq(T_mb) - h^eq(T_m) from Eq. (49)
-        qh[i] += w_of<R>(i) * c.c_mref * dTh;
+        if (i < QT) {
+            const RH wg = QT == 9 ? w_of<RH>(i) : RH(0.25) * t.varpi;
+            const R wh = QT == 9 ? w_of<R>(i) : R(0.25) * c.varpi;
+            qg[i] += wg * (t.c_fref * dTg - jT * (RH)eu);
+            qh[i] += wh * c.c_mref * dTh;
+        }
     }
 }
 
@@ -553,16 +678,22 @@ LBM_HD void gather(const CavityConst<R> &c, const void *src, int64_t stride, con
         }
         const int64_t k = c.node0 + idx;
         qf[i] = Lay::template load<R>(src, stride, 0, i, k, c);
-        qg[i] = Lay::template load<RH>(src, stride, 1, i, k, c);
-        qh[i] = Lay::template load<R>(src, stride, 2, i, k, c);
+        if (i < Lay::QT) {
+            qg[i] = Lay::template load<RH>(src, stride, 1, i, k, c);
+            qh[i] = Lay::template load<R>(src, stride, 2, i, k, c);
+        } else {
+            qg[i] = RH(0);
+            qh[i] = R(0);
+        }
     }
 }
 
-// Energy and mass carried by direction i of the given offsets (FP64).
-template <typename R, typename RH>
+// Energy and mass carried by direction i of the given offsets (FP64);
+// energy moves only along the thermal lattice's links.
+template <int QT, typename R, typename RH>
 LBM_HD void link_content(const CavityConst<R> &c, int i, const R qf[9], const RH qg[9], const R qh[9],
                          double &e, double &m) {
-    e = c.we * (c.g_ref[i] + (double)qg[i]) + c.wm * (c.h_ref[i] + (double)qh[i]);
+    e = i < QT ? c.we * (c.g_ref[i] + (double)qg[i]) + c.wm * (c.h_ref[i] + (double)qh[i]) : 0.0;
     m = (double)w_of<double>(i) + (double)qf[i];
 }
 
@@ -594,7 +725,7 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
             const bool ony = (py == 0 || py == ny - 1);
             if (onx || ony) {
                 double e, mm;
-                link_content(c, i, qf, qg, qh, e, mm);
+                link_content<Lay::QT>(c, i, qf, qg, qh, e, mm);
                 if (onx) {
                     xE += e;
                     xM += mm;
@@ -606,11 +737,11 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
         }
     }
 
-    if (PULL && g.wall) reconstruct_wall(c, x, qf, qg, qh);
+    if (PULL && g.wall) reconstruct_wall<Lay::QT>(c, x, y, qf, qg, qh);
 
     Thermo<RH> th;
     Macro<R> m;
-    macros(c, qf, qg, qh, th, m);
+    macros<Lay::QT>(c, qf, qg, qh, th, m);
     collide_flow(c, m, qf);
     // Eqs. (36), (47) with the backward difference of Remark III.
     const RH srf = (RH)c.hv_f * ((RH)m.Tm - th.Tf);
@@ -618,8 +749,13 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
     const R srm_prev = -c.sr_ratio * sr_prev;
     const RH S_pcm = srf + RH(0.5) * (srf - (RH)sr_prev);
     const R S_metal = srm + R(0.5) * (srm - srm_prev);
-    collide_pcm(c, th, m, S_pcm, qg);
-    collide_metal(c, m, S_metal, qh);
+    if (Lay::QT == 9) {
+        collide_pcm(c, th, m, S_pcm, qg);
+        collide_metal(c, m, S_metal, qh);
+    } else {
+        collide_pcm5(c, th, m, S_pcm, qg);
+        collide_metal5(c, m, S_metal, qh);
+    }
 
     if (g.near_x || g.near_y) {
         // outflow: post-collision populations aimed at wall nodes
@@ -630,7 +766,7 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
             const bool ony = (ty == 0 || ty == ny - 1);
             if (onx || ony) {
                 double e, mm;
-                link_content(c, i, qf, qg, qh, e, mm);
+                link_content<Lay::QT>(c, i, qf, qg, qh, e, mm);
                 if (onx) {
                     xE -= e;
                     xM -= mm;
@@ -672,7 +808,8 @@ LBM_HD void macro_node(const CavityConst<R> &c, const void *src, int64_t stride,
     else gather<Lay, R, RH, true>(c, src, stride, g, x, y, qf, qg, qh);
     bool finite = true;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) finite = finite && isfinite(qf[i]) && isfinite(qg[i]) && isfinite(qh[i]);
+    for (int i = 0; i < 9; ++i)
+        finite = finite && isfinite(qf[i]) && (i >= Lay::QT || (isfinite(qg[i]) && isfinite(qh[i])));
     // inflow of the last step through the wall links (not yet tallied)
     if (!raw && !g.wall) {
 #pragma unroll
@@ -683,7 +820,7 @@ LBM_HD void macro_node(const CavityConst<R> &c, const void *src, int64_t stride,
             if (onx || ony) {
                 const int w = onx ? (px == 0 ? W_LEFT : W_RIGHT) : (py == 0 ? W_BOTTOM : W_TOP);
                 double e, mm;
-                link_content(c, i, qf, qg, qh, e, mm);
+                link_content<Lay::QT>(c, i, qf, qg, qh, e, mm);
                 v[P_INE0] += w == 0 ? e : 0.0;
                 v[P_INE1] += w == 1 ? e : 0.0;
                 v[P_INE2] += w == 2 ? e : 0.0;
@@ -695,17 +832,19 @@ LBM_HD void macro_node(const CavityConst<R> &c, const void *src, int64_t stride,
             }
         }
     }
-    if (!raw && g.wall) reconstruct_wall(c, x, qf, qg, qh);
+    if (!raw && g.wall) reconstruct_wall<Lay::QT>(c, x, y, qf, qg, qh);
     double sg = 0.0, sh = 0.0, sf = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        sg += c.g_ref[i] + (double)qg[i];
-        sh += c.h_ref[i] + (double)qh[i];
+        if (i < Lay::QT) {
+            sg += c.g_ref[i] + (double)qg[i];
+            sh += c.h_ref[i] + (double)qh[i];
+        }
         sf += (double)w_of<double>(i) + (double)qf[i];
     }
     Thermo<RH> th;
     Macro<R> m;
-    macros(c, qf, qg, qh, th, m);
+    macros<Lay::QT>(c, qf, qg, qh, th, m);
     out[0] = (double)m.ux;
     out[1] = (double)m.uy;
     out[2] = (double)th.Tf;
@@ -731,8 +870,9 @@ LBM_HD void init_node(const CavityConst<R> &c, void *dst, int64_t stride, R *sr,
                       double Tm) {
     const ThermalConst<double> &t = c.td;
     const int nx = c.nx;
-    if (!c.periodic && x == 0) Tf = Tm = t.T_hot;
-    if (!c.periodic && x == nx - 1) Tf = Tm = t.T_cold;
+    const bool wall = (!c.periodic && (x == 0 || x == nx - 1)) || y == 0 || y == c.ny - 1;
+    const int w = wall ? thermal_wall(c, x, y) : -1;
+    if (w >= 0) Tf = Tm = t.T_wall[w];
     // inverse of Eq. (38) (a tie at the solidus goes to the solid branch)
     double H;
     if (Tf <= t.T_fs) H = Tf / t.inv_cps;
@@ -741,14 +881,18 @@ LBM_HD void init_node(const CavityConst<R> &c, void *dst, int64_t stride, R *sr,
     const double dT = Tf - t.T_ref, dTm = Tm - t.T_ref;
     const double dH = H - t.H_ref;
     const double cf = t.c_fref, cm = c.c_mref, cpm = c.c_pm;
+    // equilibria at rest, Eqs. (40), (49) / Eqs. (B3), (B5): the moving
+    // weights are w_i (D2Q9) or varpi/4 (D2Q5), the rest one takes the rest
+    const int QT = Lay::QT;
+    const double wrest = QT == 9 ? 5.0 / 9.0 : t.varpi;
     R qf[9], qh[9];
     RH qg[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const double wi = w_of<double>(i);
+        const double wi = QT == 9 ? w_of<double>(i) : 0.25 * t.varpi;
         qf[i] = R(0);
-        qg[i] = (RH)(i == 0 ? dH - 5.0 / 9.0 * cf * dT : wi * cf * dT);
-        qh[i] = (R)(i == 0 ? (cpm - 5.0 / 9.0 * cm) * dTm : wi * cm * dTm);
+        qg[i] = (RH)(i == 0 ? dH - wrest * cf * dT : wi * cf * dT);
+        qh[i] = (R)(i == 0 ? (cpm - wrest * cm) * dTm : wi * cm * dTm);
     }
     const int64_t k = c.node0 + (int64_t)y * nx + x;
     Lay::template store<R>(dst, stride, 0, qf, R(0), k, c);

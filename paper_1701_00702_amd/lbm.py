@@ -23,6 +23,15 @@ PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_OFFSET, "bf16": LBM
               "f16split": LBM_F16_SPLIT, "f32h64": LBM_F32_H64}
 STATE_BYTES_PER_NODE = {LBM_F64: 216, LBM_F32: 108, LBM_F16_OFFSET: 54, LBM_BF16_OFFSET: 54,
                         LBM_F16_SPLIT: 72, LBM_F32_H64: 112}
+# with D2Q5 thermal fields (19 populations per node)
+STATE_BYTES_PER_NODE_D2Q5 = {LBM_F64: 152, LBM_F32: 76, LBM_F32_H64: 80}
+
+
+def state_bytes_per_node(precision, thermal_lattice=9) -> int:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if int(thermal_lattice) == 5:
+        return STATE_BYTES_PER_NODE_D2Q5[prec]
+    return STATE_BYTES_PER_NODE[prec]
 
 
 class LbmError(RuntimeError):
@@ -42,6 +51,10 @@ class lbm_params(ctypes.Structure):
         ("cm_ref", ctypes.c_double), ("J", ctypes.c_double), ("T_hot", ctypes.c_double),
         ("T_cold", ctypes.c_double), ("T_init", ctypes.c_double), ("T_solidus", ctypes.c_double),
         ("T_liquidus", ctypes.c_double),
+        ("thermal_lattice", ctypes.c_int32), ("thermal_collision", ctypes.c_int32),
+        ("varpi", ctypes.c_double), ("zeta_e", ctypes.c_double),
+        ("wall_type", ctypes.c_int32 * 4), ("wall_T", ctypes.c_double * 4),
+        ("L_char", ctypes.c_double),
     ]
 
 
@@ -51,7 +64,9 @@ class lbm_lattice(ctypes.Structure):
                  "tau_v", "tau_g", "tau_h")] + \
                [("s", ctypes.c_double * 9), ("zeta", ctypes.c_double * 9), ("eta", ctypes.c_double * 9)] + \
                [(n, ctypes.c_double) for n in ("H_fs", "H_fl", "T_ref", "H_ref")] + \
-               [("scale_exp", ctypes.c_double * 3)]
+               [("scale_exp", ctypes.c_double * 3), ("q_thermal", ctypes.c_double),
+                ("varpi", ctypes.c_double), ("wall_type", ctypes.c_double * 4),
+                ("wall_T", ctypes.c_double * 4)]
 
 
 DIAG_NAMES = ["step", "Fo", "liquid_fraction", "Nu_hot", "Nu_hot_pcm", "Nu_cold",
@@ -131,8 +146,16 @@ def _params_array(params):
         params = [params]
     arr = (lbm_params * len(params))()
     for i, p in enumerate(params):
-        for name, _ in lbm_params._fields_:
-            setattr(arr[i], name, p[name])
+        for name, typ in lbm_params._fields_:
+            if hasattr(typ, "_length_"):
+                dst = getattr(arr[i], name)
+                vals = list(p[name])
+                if len(vals) != typ._length_:
+                    raise ValueError(f"{name} needs {typ._length_} entries")
+                for k, v in enumerate(vals):
+                    dst[k] = v
+            else:
+                setattr(arr[i], name, p[name])
     return arr
 
 
@@ -267,11 +290,10 @@ def lbm_load(h: int, path: str):
     _check(_lib.lbm_load(h, path.encode()))
 
 
-def lbm_copy_state(h: int, cavity: int, shape, precision) -> np.ndarray:
+def lbm_copy_state(h: int, cavity: int, shape, precision, thermal_lattice=9) -> np.ndarray:
     """Raw stored bytes of one cavity (uint8, planes in storage order)."""
     ny, nx = shape
-    prec = _prec(precision)
-    a = np.empty(STATE_BYTES_PER_NODE[prec] * ny * nx, dtype=np.uint8)
+    a = np.empty(state_bytes_per_node(precision, thermal_lattice) * ny * nx, dtype=np.uint8)
     _check(_lib.lbm_copy_state(h, cavity, a.ctypes.data_as(ctypes.c_void_p), a.nbytes))
     return a
 
@@ -329,4 +351,5 @@ class Solver:
         return lbm_diagnostics(self.h, c, allow_nonfinite)
 
     def state(self, c=0):
-        return lbm_copy_state(self.h, c, self.shape(c), self.precision)
+        return lbm_copy_state(self.h, c, self.shape(c), self.precision,
+                              self.params[c].get("thermal_lattice", 9) or 9)

@@ -54,12 +54,40 @@ def test_host_mapping_matches_paper_and_checker():
         assert a["gbeta"] == pytest.approx(b["gbeta"], rel=1e-14)
 
 
+@pytest.mark.parametrize("over", [dict(thermal_lattice=5), dict(thermal_lattice=5, varpi=0.4),
+                                  dict(thermal_collision=1), dict(thermal_lattice=5, thermal_collision=1),
+                                  dict(zeta_e=1.2), dict(thermal_lattice=5, zeta_e=0.6),
+                                  dict(wall_type=(1, 2, 1, 0), wall_T=(-1.0, 0.0, 0.5, 0.0)),
+                                  dict(L_char=40.0)])
+def test_host_mapping_of_variants_matches_checker(over):
+    from paper_1701_00702_amd import lbm
+    p = dict(W.case_c1()[0], **over)
+    prec = "f64"
+    a, b = lbm.lbm_lattice_of(p, prec), lattice_params(p)
+    for k in ("L", "k_f", "k_m", "h_v", "d_p", "z", "gbeta", "K", "tau_g", "tau_h", "varpi"):
+        assert a[k] == pytest.approx(b[k], rel=1e-14, abs=1e-300), k
+    for k in ("s", "zeta", "eta", "wall_T"):
+        assert a[k] == pytest.approx(b[k], rel=1e-14), k
+    assert a["wall_type"] == b["wall_type"] and a["q_thermal"] == b["qt"]
+
+
+def test_corner_case_maps_like_the_checker():
+    from paper_1701_00702_amd import lbm
+    p = W.case_corner()[0]
+    a, b = lbm.lbm_lattice_of(p, "f64"), lattice_params(p)
+    assert a["L"] == 100.0 and a["wall_type"] == [1, 2, 1, 2] and a["wall_T"][0] == -1.0
+    assert a["h_v"] == pytest.approx(b["h_v"], rel=1e-14) and a["z"] == pytest.approx(b["z"], rel=1e-14)
+
+
 def test_host_validation_rejects_bad_sets():
     from paper_1701_00702_amd import lbm
     base = W.case_c1()[0]
     bad = [dict(base, porosity=1.0), dict(base, nx=3), dict(base, cf_ref=1.9), dict(base, Ste=0.0),
            dict(base, k_f=5e-3, Nu_i=60.0), dict(base, T_hot=0.0), dict(base, T_liquidus=-1.0),
-           dict(base, bc_x=2)]
+           dict(base, bc_x=2), dict(base, thermal_lattice=7), dict(base, thermal_collision=2),
+           dict(base, thermal_lattice=5, varpi=1.5), dict(base, thermal_collision=1, zeta_e=1.0),
+           dict(base, wall_type=(3, 0, 0, 0)),
+           dict(base, bc_x=1, wall_type=(1, 0, 0, 0))]
     for q in bad:
         with pytest.raises(lbm.LbmError) as e:
             lbm.lbm_lattice_of(q, "f32")
@@ -67,6 +95,14 @@ def test_host_validation_rejects_bad_sets():
         assert lbm.lbm_last_error()
     with pytest.raises(lbm.LbmError):
         lbm.lbm_workspace_bytes([base], 7)
+    # D2Q5 storage exists in FP64, FP32 and FP32 with the FP64 rest enthalpy
+    q5 = dict(base, thermal_lattice=5)
+    for prec in ("f16", "bf16", "f16split"):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_lattice_of(q5, prec)
+    # a batch shares one thermal lattice
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_workspace_bytes([base, q5], "f32")
 
 
 def test_workspace_plan_sizes():
@@ -81,3 +117,8 @@ def test_workspace_plan_sizes():
     nodes = sum(q["nx"] * q["ny"] for q in c5)
     assert nodes == 24198641
     assert lbm.lbm_workspace_bytes(c5, "f32") >= 2 * 27 * 4 * nodes
+    # D2Q5: 19 populations per node
+    q5 = dict(p3, thermal_lattice=5)
+    b5 = lbm.lbm_workspace_bytes(q5, "f32")
+    assert b5 >= 2 * 19 * 4 * n and b32 - b5 >= 2 * 8 * 4 * n * 0.99
+    assert lbm.state_bytes_per_node("f32h64", 5) == 80 and lbm.state_bytes_per_node("f64", 5) == 152

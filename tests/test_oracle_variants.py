@@ -168,11 +168,14 @@ def test_bgk_is_velocity_space_bgk(qt):
 def test_fixed_zeta_e_and_rate_tables():
     base = _lp()
     za = base["zeta"][3]
+    # a given zeta_e moves the pair zeta_e = zeta_eps that Sec. III C sets
+    # together; everything else keeps its Sec. III C value
     lp = _lp(zeta_e=1.8)
-    assert lp["zeta"][1] == 1.8 and lp["zeta"][2] == 2.0 - za     # only zeta_e moves
+    assert lp["zeta"][1] == 1.8 and lp["zeta"][2] == 1.8
+    assert base["zeta"][1] == base["zeta"][2] == 2.0 - za
     assert lp["zeta"][3:] == base["zeta"][3:] and lp["eta"] == base["eta"]
     lp5 = _lp(thermal_lattice=5, zeta_e=0.6)
-    assert lp5["zeta"][:5] == [1.0, za, za, 0.6, 2.0 - za]
+    assert lp5["zeta"][:5] == [1.0, za, za, 0.6, 0.6]
     assert lp5["eta"][:5] == [1.0, base["eta"][3], base["eta"][3], 1.1, 1.1]
     with pytest.raises(ValueError):
         _lp(thermal_collision=1, zeta_e=1.2)
