@@ -644,9 +644,8 @@ lbm_status setup(lbm_handle *h) {
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
     h->n_cu = ncu > 0 ? ncu : 256;
     HIP_TRY(hipMemsetAsync(h->ws, 0, h->pl.total, h->stream));
-    // cavity table
-    std::vector<char> tab;
-    if (h->st == ST_F64) {
+    // cavity table in the kernels' arithmetic type (FP64 forms: double)
+    if (real_size(h->st) == 8) {
         std::vector<CavityConst<double>> t;
         for (int c = 0; c < h->n; ++c) t.push_back(make_const<double>(h->pl.lat[c], h->pl.node0[c], h->pl.acc0[c]));
         HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
