@@ -10,7 +10,9 @@ on.  MLUPS counts every node (walls included) advancing all 27 populations.
 Algorithmic HBM bytes per node and step: the stored populations read once
 and written once, plus the previous-step source read and written: FP64
 448 B, FP32 224 B, FP32 with the FP64 rest enthalpy population 232 B,
-split 16-bit 152 B, 16-bit offsets 116 B.
+split 16-bit 152 B, 16-bit offsets 116 B.  With the D2Q5 thermal fields of
+Appendix B (--thermal-lattice 5, 19 populations per node): FP64 320 B,
+FP32 160 B, FP32 with the FP64 rest enthalpy population 168 B.
 """
 from __future__ import annotations
 
@@ -28,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BYTES_PER_NODE = {"f64": 448, "f32": 224, "f32h64": 232, "f16split": 152, "f16": 116, "bf16": 116}
+BYTES_PER_NODE_D2Q5 = {"f64": 320, "f32": 160, "f32h64": 168}
+
+
+def bytes_per_node(precision: str, thermal_lattice: int = 9) -> int:
+    return BYTES_PER_NODE_D2Q5[precision] if thermal_lattice == 5 else BYTES_PER_NODE[precision]
 PEAK_HBM_GBPS = 8000.0
 METRIC = "MLUPS (3 coupled MRT fields) + achieved HBM GB/s vs peak; FP16-store vs FP32"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1701_00702_amd", "csrc", n)
@@ -59,10 +66,11 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_from_profile(sha: str, workload_name: str, precision: str):
+def traffic_from_profile(sha: str, workload_name: str, precision: str, thermal_lattice: int = 9):
     """HBM bytes per launch measured with rocprofv3 counters, if the summary
     in profiles/ was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_step_kernel_{workload_name}_{precision}.md")
+    tag = f"{workload_name}_d2q5_{precision}" if thermal_lattice == 5 else f"{workload_name}_{precision}"
+    path = os.path.join(ROOT, "profiles", f"traffic_step_kernel_{tag}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -131,6 +139,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=[None] + list(BYTES_PER_NODE))
+    ap.add_argument("--thermal-lattice", type=int, default=9, choices=[9, 5],
+                    help="9: D2Q9 thermal fields (the paper's main method); 5: D2Q5 (Appendix B)")
     ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--npt", type=int, default=1)
     ap.add_argument("--xcd", type=int, default=1)
@@ -162,6 +172,12 @@ def main():
 
     params, seed, prec, desc = workload(args.workload)
     prec = args.precision or prec
+    qt = args.thermal_lattice
+    if qt == 5:
+        if prec not in BYTES_PER_NODE_D2Q5:
+            raise SystemExit(f"D2Q5 thermal fields are stored as {sorted(BYTES_PER_NODE_D2Q5)}")
+        params = [dict(p, thermal_lattice=5) for p in params]
+        desc += ", D2Q5 thermal fields (Appendix B)"
     stream = torch.cuda.Stream()
     s, ws = make_solver(lbm, torch, params, prec, stream)
     for c, p in enumerate(params):
@@ -177,15 +193,15 @@ def main():
     d = s.diagnostics(0, allow_nonfinite=True)
     ms_step = ms / args.steps
     mlups = nodes / (ms_step * 1e-3) / 1e6
-    alg = BYTES_PER_NODE[prec] * nodes
+    alg = bytes_per_node(prec, qt) * nodes
     achieved = alg / (ms_step * 1e-3) / 1e9
     sha = kernel_sha()
-    traffic = traffic_from_profile(sha, args.workload, prec)
+    traffic = traffic_from_profile(sha, args.workload, prec, qt)
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
-        "config": {"workload": desc, "nodes": nodes, "storage": prec, "launch": launch,
+        "config": {"workload": desc, "nodes": nodes, "storage": prec, "thermal_lattice": qt, "launch": launch,
                    "seed": seed, "step_kernel": "lbm::step_kernel (fused pull-stream + NEE walls + 3 MRT collisions)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS,
@@ -200,17 +216,23 @@ def main():
 
     if args.forms:
         forms = {}
-        for wl, pr in (("c3", "f32h64"), ("c3", "f16split"), ("c3", "f16"), ("c3", "bf16"),
-                       ("c4", "f32"), ("c4", "f16split")):
+        for wl, pr, q in (("c3", "f32h64", 9), ("c3", "f16split", 9), ("c3", "f16", 9), ("c3", "bf16", 9),
+                          ("c4", "f32", 9), ("c4", "f16split", 9),
+                          ("c3", "f32", 5), ("c3", "f32h64", 5), ("c3", "f64", 5), ("c3", "f64", 9)):
+            if q == qt and wl == args.workload and pr == prec:
+                continue
             ps, sd, _, _ = workload(wl)
+            if q == 5:
+                ps = [dict(p, thermal_lattice=5) for p in ps]
             s2, ws2 = make_solver(lbm, torch, ps, pr, stream)
             T_pcm, T_mf = W.initial_temperatures(ps[0], sd)
             s2.set_initial(0, T_pcm, T_mf)
             lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent)
             n2 = ps[0]["nx"] * ps[0]["ny"]
             t = time_steps(lbm, torch, s2, stream, 100, 10) / 100
-            forms[f"{wl}_{pr}"] = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t,
-                                   "alg_GBps": BYTES_PER_NODE[pr] * n2 / (t * 1e-3) / 1e9}
+            name = f"{wl}_d2q5_{pr}" if q == 5 else f"{wl}_{pr}"
+            forms[name] = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t,
+                           "alg_GBps": bytes_per_node(pr, q) * n2 / (t * 1e-3) / 1e9}
             s2.close()
             del ws2
             torch.cuda.empty_cache()

@@ -54,10 +54,11 @@ typedef enum {
 } lbm_status;
 
 /* Storage of the populations of a node (27 with D2Q9 thermal fields, 19 with
- * D2Q5 ones).  Arithmetic is FP64 for LBM_F64 and FP32 otherwise.  Every form stores, per field, the offset of each
- * population from the rest equilibrium at a fixed reference state (flow: the
- * lattice weights times the reference density; enthalpy and metal fields:
- * the equilibria at rest at the middle of the mushy band).
+ * D2Q5 ones).  Arithmetic is FP64 for LBM_F64 and FP32 otherwise.  Every
+ * form stores, per field, the offset of each population from the rest
+ * equilibrium at a fixed reference state (flow: the lattice weights times
+ * the reference density; enthalpy and metal fields: the equilibria at rest
+ * at the middle of the mushy band on D2Q9, at T_init on D2Q5).
  *   LBM_F64, LBM_F32   the offsets in FP64 / FP32 (216 / 108 bytes per node)
  *   LBM_F16_OFFSET     the offsets in binary16 times a power-of-two scale (54)
  *   LBM_BF16_OFFSET    the offsets in bfloat16 (54)

@@ -165,8 +165,17 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     l.T_fl = p.T_liquidus;
     l.H_fs = l.c_ps * l.T_fs;
     l.H_fl = l.c_pl * l.T_fl + l.L_a;
-    l.T_ref = 0.5 * (l.T_fs + l.T_fl);
-    l.H_ref = 0.5 * (l.H_fs + l.H_fl);
+    // reference state of the stored offsets: on D2Q9 the middle of the
+    // mushy band; on D2Q5 the initial interior state, whose nodes then hold
+    // exact zeros (each measured best for its lattice over a full FP32 run:
+    // the D2Q5 rest population otherwise drifts the energy balance)
+    if (l.qt == 9) {
+        l.T_ref = 0.5 * (l.T_fs + l.T_fl);
+        l.H_ref = 0.5 * (l.H_fs + l.H_fl);
+    } else {
+        l.T_ref = p.T_init;
+        l.H_ref = enthalpy_of(l, p.T_init);
+    }
     l.T_hot = p.T_hot;
     l.T_cold = p.T_cold;
     l.T_init = p.T_init;

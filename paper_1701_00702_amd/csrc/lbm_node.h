@@ -6,10 +6,12 @@
 // kernels in lbm_kernels.hip and a host build of the same arithmetic share it.
 //
 // Populations are handled as offsets q_i = X_i - X_ref,i from a fixed
-// reference equilibrium (flow: w_i rho_0; enthalpy/metal: the equilibria at
-// rest at the middle of the mushy band).  The moment algebra is affine, so
-// the update runs on the offsets; in FP32 this keeps the small momentum of
-// the Darcy-scale flow out of the rounding of O(1) populations.
+// reference equilibrium at rest (flow: w_i rho_0; enthalpy/metal: the
+// equilibria at the middle of the mushy band on D2Q9, at the initial
+// temperature on D2Q5, where a node the heat has not reached yet then holds
+// exact zeros).  The moment algebra is affine, so the update runs on the
+// offsets; in FP32 this keeps the small momentum of the Darcy-scale flow
+// out of the rounding of O(1) populations.
 //
 // The thermal fields run on D2Q9 (Sec. III B/C) or on the D2Q5 lattice of
 // Appendix B (its five velocities are the first five of Eq. 11); a layout
