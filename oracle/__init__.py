@@ -51,7 +51,7 @@ class OracleParams(ctypes.Structure):
         ("k_f", ctypes.c_double), ("k_m", ctypes.c_double), ("L", ctypes.c_double),
         ("s", ctypes.c_double * Q), ("zeta", ctypes.c_double * Q), ("eta", ctypes.c_double * Q),
         ("qt", ctypes.c_int), ("varpi", ctypes.c_double), ("wall_type", ctypes.c_int * 4),
-        ("wall_T", ctypes.c_double * 4),
+        ("wall_T", ctypes.c_double * 4), ("bounce_back", ctypes.c_int),
     ]
 
 
@@ -136,6 +136,7 @@ def make_struct(lp: dict, window=None) -> OracleParams:
     for w in range(4):
         s.wall_type[w] = int(wt[w])
         s.wall_T[w] = float(wT[w])
+    s.bounce_back = int(lp.get("solid_treatment", 0))
     return s
 
 

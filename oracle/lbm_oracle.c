@@ -42,6 +42,12 @@
  * models of Sec. V A (every rate 1/tau) and other zeta_e values (Sec. V D).
  * Each wall is isothermal at a given temperature or adiabatic; at a corner
  * an isothermal vertical wall wins, then an isothermal horizontal wall.
+ *
+ * Solid treatment: the volumetric scheme of Eq. (20), or the bounce-back
+ * alternative compared in Sec. V B: a node with f_l < 0.5 (the interface
+ * is f_l = 0.5) is solid, its flow populations are reflected
+ * (f*_i = f+_{-i}) and its velocity is zero; other nodes collide their
+ * unblended f+ with the force of Eq. (3).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -81,6 +87,8 @@ static const double M5[Q5][Q5] = {
 
 enum { W_NONE = -1, W_LEFT = 0, W_RIGHT = 1, W_BOTTOM = 2, W_TOP = 3 };
 enum { WALL_ISOTHERMAL = 1, WALL_ADIABATIC = 2 };
+/* Opposite direction of each D2Q9 velocity. */
+static const int OPP[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 typedef struct {
     /* geometry: a window [gx0, gx0+nx) x [gy0, gy0+ny) of an NX x NY cavity */
@@ -102,6 +110,7 @@ typedef struct {
     double varpi;       /* D2Q5 weight parameter, Eq. (B2) */
     int wall_type[4];   /* left, right, bottom, top: isothermal or adiabatic */
     double wall_T[4];   /* temperature of the isothermal walls */
+    int bounce_back;    /* 0: volumetric scheme (Eq. 20); 1: bounce-back (Sec. V B) */
 } oracle_params;
 
 typedef struct {
@@ -313,10 +322,12 @@ static void node_macros(const oracle_params *p, const double *fp, const double *
     double rho = 0.0;
     for (int i = 0; i < Q; ++i) rho += fp[i];
     m->rho = rho;
-    /* Eq. (20): the solid part is the equilibrium at the solid velocity 0. */
+    /* Eq. (20): the solid part is the equilibrium at the solid velocity 0.
+     * The bounce-back alternative (Sec. V B) has no blend. */
     double f_solid[Q];
     oracle_feq(rho, 0.0, 0.0, p->phi, f_solid);
-    for (int i = 0; i < Q; ++i) m->fb[i] = m->f_l * fp[i] + (1.0 - m->f_l) * f_solid[i];
+    for (int i = 0; i < Q; ++i)
+        m->fb[i] = p->bounce_back ? fp[i] : m->f_l * fp[i] + (1.0 - m->f_l) * f_solid[i];
     /* Eq. (7): G = -g beta (T_f - T0) f_l with gravity pointing along -axis. */
     double G = p->gbeta * (m->T_f - p->T0) * m->f_l;
     m->Gx = p->gravity_axis == 0 ? G : 0.0;
@@ -337,6 +348,11 @@ static void node_macros(const oracle_params *p, const double *fp, const double *
     double den = l0 + sqrt(l0 * l0 + l1 * vmag);
     m->ux = vx / den;
     m->uy = vy / den;
+    /* bounce-back: a node below the interface value f_l = 0.5 is solid, at rest */
+    if (p->bounce_back && m->f_l < 0.5) {
+        m->ux = 0.0;
+        m->uy = 0.0;
+    }
 }
 
 void oracle_node_macros(const oracle_params *p, const double *fp, const double *g, const double *h,
@@ -428,6 +444,9 @@ static void collide_node(const oracle_params *p, const double Minv[Q][Q],
     /* Eq. (14). */
     for (int k = 0; k < Q; ++k) ms[k] = m[k] - p->s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * p->s[k]) * S[k];
     matvec(Minv, ms, fo); /* f* = M^-1 m*, Eq. (15) */
+    /* Sec. V B alternative: a solid node reflects what arrived */
+    if (p->bounce_back && mc.f_l < 0.5)
+        for (int i = 0; i < Q; ++i) fo[i] = fp[OPP[i]];
 
     /* ---- interstitial sources, Eqs. (36), (47), Remark III ---- */
     double srf = p->h_v * (mc.T_m - mc.T_f) / (phi * p->rho_l);

@@ -19,7 +19,9 @@ paper's definitions:
   zeta_e = 2 - zeta_alpha), MRT or BGK thermal collisions (Sec. V A), an
   optional fixed zeta_e (Sec. V D);
 * walls: isothermal or adiabatic, each of the four; by default the cavity
-  of Sec. IV B (hot left, cold right, adiabatic top and bottom).
+  of Sec. IV B (hot left, cold right, adiabatic top and bottom);
+* solid phase: the volumetric scheme of Eq. (20), or the bounce-back
+  alternative of Sec. V B.
 """
 from __future__ import annotations
 
@@ -149,6 +151,9 @@ def lattice_params(p: dict) -> dict:
     if collision not in (0, 1):
         raise ValueError("thermal_collision must be 0 (MRT) or 1 (BGK)")
     zeta_e_given = float(p.get("zeta_e", 0.0))
+    solid_treatment = int(p.get("solid_treatment", 0))
+    if solid_treatment not in (0, 1):
+        raise ValueError("solid_treatment must be 0 (volumetric, Eq. 20) or 1 (bounce-back, Sec. V B)")
 
     # Eq. (26) / Sec. III C: s_v^-1 = 0.5 + nu_e / c_s^2.
     s_v = 1.0 / (0.5 + 3.0 * nu_e)
@@ -198,6 +203,7 @@ def lattice_params(p: dict) -> dict:
         tau_v=1.0 / s_v, tau_g=1.0 / zeta_a, tau_h=1.0 / eta_a,
         s=s, zeta=zeta, eta=eta, qt=qt, varpi=varpi, cs2T=cs2T,
         wall_type=wall_type, wall_T=wall_T, thermal_collision=collision,
+        solid_treatment=solid_treatment,
     )
 
 

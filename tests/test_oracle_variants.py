@@ -212,3 +212,31 @@ def test_wall_mapping():
     with pytest.raises(ValueError):
         _lp(wall_type=(3, 0, 0, 0))
     assert _lp(L_char=100.0)["L"] == 100.0
+
+
+def test_bounce_back_solid_node_reflects():
+    # Sec. V B alternative: a node below f_l = 0.5 returns every flow
+    # population along the opposite link; a liquid node collides as usual.
+    lp = _lp(solid_treatment=1, Ra=1e8)
+    r = np.random.default_rng(21)
+    fplus = oracle.feq(1.0, 0.01, -0.02, lp["phi"]) + 1e-4 * r.standard_normal(9)
+    opp = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+    for i in range(9):
+        assert EX[opp[i]] == -EX[i] and EY[opp[i]] == -EY[i]
+    Hs = oracle.enthalpy_of_T(lp, -0.5)
+    g = oracle.geq(Hs, -0.5, 0.0, 0.0, lp["phi"], lp["c_fref"], lp["c_pl"])
+    h = oracle.heq(-0.5, lp["c_pm"], lp["c_mref"])
+    m = oracle.node_macros(lp, fplus, g, h)
+    assert m["f_l"] == 0.0 and m["ux"] == 0.0 and m["uy"] == 0.0
+    fo, _, _, _ = oracle.collide_node(lp, fplus, g, h, 0.0, 0.0)
+    np.testing.assert_array_equal(fo, fplus[opp])
+    # the same node in the volumetric scheme is the rest equilibrium instead
+    fv, _, _, _ = oracle.collide_node(_lp(Ra=1e8), fplus, g, h, 0.0, 0.0)
+    np.testing.assert_allclose(fv, W * fplus.sum(), rtol=0, atol=2e-16)
+    # a liquid node is unaffected by the switch
+    Hl = oracle.enthalpy_of_T(lp, 0.6)
+    gl = oracle.geq(Hl, 0.6, 0.0, 0.0, lp["phi"], lp["c_fref"], lp["c_pl"])
+    hl = oracle.heq(0.6, lp["c_pm"], lp["c_mref"])
+    a, _, _, _ = oracle.collide_node(lp, fplus, gl, hl, 0.0, 0.0)
+    b, _, _, _ = oracle.collide_node(_lp(Ra=1e8), fplus, gl, hl, 0.0, 0.0)
+    np.testing.assert_array_equal(a, b)

@@ -312,3 +312,68 @@ def test_wall_nodes_carry_their_wall_values(qt):
         # corner the isothermal top wall
         assert f["T_pcm"][0, 0] == 1.0 or abs(f["T_pcm"][0, 0] - 1.0) < 1e-13
         assert abs(f["T_pcm"][ny - 1, nx - 1] - 0.1) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Bounce-back alternative to the volumetric scheme (Sec. V B)
+# ---------------------------------------------------------------------------
+
+def _bb_channel(ny, k=2, target_u=1e-3):
+    """Porous channel, periodic in x, force along x, with k+1 solid rows
+    along each wall (T at the solidus, f_l = 0) and liquid between (T just
+    above the liquidus, so the two phases barely conduct).  nu_e = 3/16
+    makes (1/s_v - 1/2)(1/s_q - 1/2) = 3/16, for which the MRT bounce-back
+    wall sits exactly halfway between a solid and a fluid node."""
+    nu = 0.1875
+    p = make_params(nx=4, ny=ny, bc_x=1, gravity_axis=0, porosity=0.9, Ra=1.0, Pr=nu / 1e-4, Da=0.05,
+                    Ste=1.0, k_ratio=1.0, cap_ratio=1.0, Nu_i=0.0, F_phi=0.0, k_f=1e-4,
+                    T_hot=1.0, T_cold=-1.0, T_init=1e-6, T_solidus=0.0, T_liquidus=1e-7,
+                    solid_treatment=1)
+    lp = lattice_params(p)
+    gb = target_u * lp["nu_f"] / lp["K"]
+    p["Ra"] = gb * (lp["T_hot"] - lp["T_cold"]) * lp["L"] ** 3 / (lp["nu_f"] * lp["alpha_f"])
+    lp = lattice_params(p)
+    T = np.full((ny, 4), 1e-6)
+    T[:k + 1] = 0.0
+    T[ny - 1 - k:] = 0.0
+    o = oracle.Oracle(p)
+    o.set_initial(T, T)
+    Hf = ny - 2 * k - 2
+    rate = lp["nu_e"] * (math.pi / Hf) ** 2 + lp["phi"] * lp["nu_f"] / lp["K"]
+    o.step(int(40.0 / rate))
+    f = o.fields()
+    u = f["ux"][:, 1]
+    # Brinkman closed form between walls at y = k + 1/2 and y = ny - 1 - k - 1/2
+    ya, yb = k + 0.5, ny - 1.5 - k
+    r = math.sqrt(lp["phi"] * lp["nu_f"] / (lp["K"] * lp["nu_e"]))
+    uinf = lp["gbeta"] * (1e-6 - lp["T0"]) * lp["K"] / lp["nu_f"]
+    y = np.arange(ny, dtype=float)
+    ue = uinf * (1 - np.cosh(r * (y - 0.5 * (ya + yb))) / np.cosh(r * (yb - ya) / 2))
+    fluid = slice(k + 1, ny - 1 - k)
+    assert np.all(f["f_l"][:k + 1] < 0.5) and np.all(f["f_l"][fluid] == 1.0)
+    assert np.all(u[:k + 1] == 0.0) and np.all(u[ny - 1 - k:] == 0.0)
+    return np.abs(u[fluid] - ue[fluid]).max() / np.abs(ue[fluid]).max()
+
+
+def test_bounce_back_channel_halfway_wall():
+    e21, e37 = _bb_channel(21), _bb_channel(37)
+    assert e21 < 1.5e-3 and e37 < 4e-4, (e21, e37)
+    assert e21 / e37 > 3.0
+
+
+def test_bounce_back_cavity_balance_and_rest():
+    p, _, seed, _ = case_c1()
+    p = dict(p, solid_treatment=1)
+    Tf, Tm = initial_temperatures(p, seed)
+    o = oracle.Oracle(p)
+    o.set_initial(Tf, Tm)
+    o.step(1500)
+    d = o.diagnostics()
+    f = o.fields()
+    solid = f["f_l"] < 0.5
+    assert solid.sum() > 1000 and (~solid).sum() > 300
+    assert np.all(f["ux"][solid] == 0.0) and np.all(f["uy"][solid] == 0.0)
+    assert np.hypot(f["ux"], f["uy"]).max() > 1e-5
+    # reflection permutes populations: mass and energy balances stay exact
+    assert abs(d["energy_residual"]) <= 1e-12 * abs(d["E_int"])
+    assert abs(d["mass_residual"]) <= 1e-12 * abs(d["M_int"])
