@@ -129,6 +129,11 @@ typedef struct lbm_params {
     double wall_T[4];          /* temperatures of walls of type 1             */
     double L_char;             /* > 0: characteristic length for Ra, Da, d_p,
                                   Fo and Nu; <= 0: nx - 1 (periodic: ny - 1)  */
+    int32_t solid_treatment;   /* 0: volumetric scheme, Eq. (20); 1: the
+                                  bounce-back alternative of Sec. V B: a node
+                                  with f_l < 0.5 reflects its flow populations
+                                  and is at rest, other nodes collide their
+                                  unblended f+                                */
 } lbm_params;
 
 /* Derived lattice constants of one cavity (read-only view). */
@@ -144,6 +149,7 @@ typedef struct lbm_lattice {
     double q_thermal;                /* thermal velocities: 9 or 5 */
     double varpi;                    /* D2Q5 weight parameter (0 on D2Q9) */
     double wall_type[4], wall_T[4];  /* resolved: 1 isothermal, 2 adiabatic */
+    double solid_treatment;          /* 0 volumetric, 1 bounce-back */
 } lbm_lattice;
 
 /* Diagnostics of one cavity at the current step (all FP64).

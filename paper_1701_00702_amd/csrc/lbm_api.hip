@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -55,6 +56,7 @@ struct Lattice {
     double T_hot, T_cold, T_init;
     int wall_type[4];       // resolved: 1 isothermal, 2 adiabatic
     double wall_T[4];
+    int solid;              // 0 volumetric (Eq. 20), 1 bounce-back (Sec. V B)
     double zeta_a, eta_a;
     double s[9], zeta[9], eta[9];
     int scale_exp[3];
@@ -107,6 +109,9 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     }
     if (p.thermal_collision == 1 && p.zeta_e > 0)
         return fail(LBM_EINVAL, "zeta_e cannot be set for BGK thermal collisions");
+    if (p.solid_treatment != 0 && p.solid_treatment != 1)
+        return fail(LBM_EINVAL, "solid_treatment must be 0 (volumetric, Eq. 20) or 1 (bounce-back, Sec. V B)");
+    l.solid = p.solid_treatment;
     for (int w = 0; w < 4; ++w)
         if (p.wall_type[w] < 0 || p.wall_type[w] > 2)
             return fail(LBM_EINVAL, "wall_type[%d] = %d: 0 default, 1 isothermal, 2 adiabatic", w, p.wall_type[w]);
@@ -313,6 +318,7 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
         c.T_wall[w] = (R)l.wall_T[w];
         c.wall_iso[w] = l.wall_type[w] == 1 ? 1 : 0;
     }
+    c.bounce_back = l.solid;
     for (int f = 0; f < 3; ++f) {
         c.scale[f] = (R)std::ldexp(1.0, l.scale_exp[f]);
         c.inv_scale[f] = (R)std::ldexp(1.0, -l.scale_exp[f]);
@@ -334,6 +340,15 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Copy of a parameter struct with its trailing padding cleared, so that
+// checkpoints compare parameters byte for byte.
+lbm_params normalized(const lbm_params &p) {
+    lbm_params q = p;
+    const size_t end = offsetof(lbm_params, solid_treatment) + sizeof(q.solid_treatment);
+    std::memset((char *)&q + end, 0, sizeof(q) - end);
+    return q;
+}
 
 int storage_of(lbm_precision p, int qt = 9) {
     if (qt == 5) {
@@ -689,7 +704,7 @@ lbm_status create_common(const lbm_params *p, int n, lbm_precision prec, void *w
     h->prec = prec;
     h->st = h->pl.st;
     h->n = n;
-    h->params.assign(p, p + n);
+    for (int c = 0; c < n; ++c) h->params.push_back(normalized(p[c]));
     h->stream = (hipStream_t)stream;
     if (ext) {
         if (!ws) {
@@ -926,6 +941,7 @@ void fill_lattice(const Lattice &l, lbm_lattice *out) {
         out->wall_type[w] = l.wall_type[w];
         out->wall_T[w] = l.wall_T[w];
     }
+    out->solid_treatment = l.solid;
 }
 }  // namespace
 

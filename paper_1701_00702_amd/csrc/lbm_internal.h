@@ -52,6 +52,7 @@ struct CavityConst {
     // bottom, top): isothermal (1) or adiabatic (0) and its temperature
     R T_ref, T_wall[4], varpi;
     int32_t wall_iso[4];
+    int32_t bounce_back;  // solid phase: 0 volumetric (Eq. 20), 1 bounce-back (Sec. V B)
     // storage scale per field (populations are stored as (X - X_ref) * scale)
     R scale[3], inv_scale[3];
     // PCM enthalpy field

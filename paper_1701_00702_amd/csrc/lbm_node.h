@@ -403,10 +403,13 @@ LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[
     // Eq. (21)
     m.drho = sum9(qf);
     m.rho = R(1) + m.drho;
-    // Eq. (20): f = f_l f+ + (1 - f_l) w rho, written on offsets from w rho_0.
-    const R sol = (R(1) - m.fl) * m.drho;
+    // Eq. (20): f = f_l f+ + (1 - f_l) w rho, written on offsets from w rho_0
+    // (the bounce-back alternative of Sec. V B keeps f+ unblended).
+    if (!c.bounce_back) {
+        const R sol = (R(1) - m.fl) * m.drho;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) qf[i] = m.fl * qf[i] + w_of<R>(i) * sol;
+        for (int i = 0; i < 9; ++i) qf[i] = m.fl * qf[i] + w_of<R>(i) * sol;
+    }
     // Eq. (7): buoyancy along +axis (gravity along -axis).
     const R G = c.gbeta * (m.Tf - c.T0) * m.fl;
     m.Gx = c.gaxis == 0 ? G : R(0);
@@ -421,11 +424,27 @@ LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[
     const R inv_den = R(1) / (c.l0 + sqrt(c.l0sq + c.l1 * vmag));
     m.ux = vx * inv_den;
     m.uy = vy * inv_den;
+    // bounce-back: below the interface value f_l = 0.5 a node is solid, at rest
+    if (c.bounce_back && m.fl < R(0.5)) {
+        m.ux = R(0);
+        m.uy = R(0);
+    }
 }
 
-// Flow collision, Eqs. (14), (16)-(19), on the blended offsets.
+// Flow collision, Eqs. (14), (16)-(19), on the blended offsets; with the
+// bounce-back alternative (Sec. V B) a solid node instead returns every
+// population along the opposite link (the reference w_i rho_0 is symmetric,
+// so the offsets swap the same way).
 template <typename R>
 LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R q[9]) {
+    if (c.bounce_back && m.fl < R(0.5)) {
+        R t;
+        t = q[1]; q[1] = q[3]; q[3] = t;
+        t = q[2]; q[2] = q[4]; q[4] = t;
+        t = q[5]; q[5] = q[7]; q[7] = t;
+        t = q[6]; q[6] = q[8]; q[8] = t;
+        return;
+    }
     R d[9];
     to_moments(q, d);
     const R ux = m.ux, uy = m.uy, rho = m.rho;

@@ -54,7 +54,7 @@ class lbm_params(ctypes.Structure):
         ("thermal_lattice", ctypes.c_int32), ("thermal_collision", ctypes.c_int32),
         ("varpi", ctypes.c_double), ("zeta_e", ctypes.c_double),
         ("wall_type", ctypes.c_int32 * 4), ("wall_T", ctypes.c_double * 4),
-        ("L_char", ctypes.c_double),
+        ("L_char", ctypes.c_double), ("solid_treatment", ctypes.c_int32),
     ]
 
 
@@ -66,7 +66,7 @@ class lbm_lattice(ctypes.Structure):
                [(n, ctypes.c_double) for n in ("H_fs", "H_fl", "T_ref", "H_ref")] + \
                [("scale_exp", ctypes.c_double * 3), ("q_thermal", ctypes.c_double),
                 ("varpi", ctypes.c_double), ("wall_type", ctypes.c_double * 4),
-                ("wall_T", ctypes.c_double * 4)]
+                ("wall_T", ctypes.c_double * 4), ("solid_treatment", ctypes.c_double)]
 
 
 DIAG_NAMES = ["step", "Fo", "liquid_fraction", "Nu_hot", "Nu_hot_pcm", "Nu_cold",

@@ -58,7 +58,7 @@ def test_host_mapping_matches_paper_and_checker():
                                   dict(thermal_collision=1), dict(thermal_lattice=5, thermal_collision=1),
                                   dict(zeta_e=1.2), dict(thermal_lattice=5, zeta_e=0.6),
                                   dict(wall_type=(1, 2, 1, 0), wall_T=(-1.0, 0.0, 0.5, 0.0)),
-                                  dict(L_char=40.0)])
+                                  dict(L_char=40.0), dict(solid_treatment=1)])
 def test_host_mapping_of_variants_matches_checker(over):
     from paper_1701_00702_amd import lbm
     p = dict(W.case_c1()[0], **over)
@@ -69,6 +69,7 @@ def test_host_mapping_of_variants_matches_checker(over):
     for k in ("s", "zeta", "eta", "wall_T"):
         assert a[k] == pytest.approx(b[k], rel=1e-14), k
     assert a["wall_type"] == b["wall_type"] and a["q_thermal"] == b["qt"]
+    assert a["solid_treatment"] == b["solid_treatment"]
 
 
 def test_corner_case_maps_like_the_checker():
@@ -87,7 +88,7 @@ def test_host_validation_rejects_bad_sets():
            dict(base, bc_x=2), dict(base, thermal_lattice=7), dict(base, thermal_collision=2),
            dict(base, thermal_lattice=5, varpi=1.5), dict(base, thermal_collision=1, zeta_e=1.0),
            dict(base, wall_type=(3, 0, 0, 0)),
-           dict(base, bc_x=1, wall_type=(1, 0, 0, 0))]
+           dict(base, bc_x=1, wall_type=(1, 0, 0, 0)), dict(base, solid_treatment=2)]
     for q in bad:
         with pytest.raises(lbm.LbmError) as e:
             lbm.lbm_lattice_of(q, "f32")

@@ -209,3 +209,46 @@ def test_d2q5_launch_shapes_batches_and_checkpoints_bitwise(lbm):
     assert np.array_equal(a.state(), e.state())
     for s in (a, c, e):
         s.close()
+
+
+@pytest.mark.parametrize("qt", [9, 5])
+def test_bounce_back_parity(lbm, qt):
+    # the Sec. V B alternative on the 64^2 cavity: FP64 to the parity bar,
+    # FP32 to 1e-4; solid nodes (f_l < 0.5) at rest exactly
+    p, seed = _c1(solid_treatment=1, thermal_lattice=qt)
+    g, gd, r, rd = run_pair(lbm, p, 2000, seed)
+    e = field_errors(g, r, p)
+    de = diag_errors(gd, rd)
+    assert max(e.values()) < 1e-10, e
+    assert max(de.values()) < 1e-10, de
+    solid = g["f_l"] < 0.5
+    assert solid.sum() > 1000 and np.all(g["ux"][solid] == 0.0) and np.all(g["uy"][solid] == 0.0)
+    g32, gd32, _, _ = run_pair(lbm, p, 2000, seed, precision="f32")
+    e32 = field_errors(g32, r, p)
+    assert max(e32.values()) < 1e-4, e32
+
+
+def test_bounce_back_channel_parity(lbm):
+    # solid layers along both walls of a periodic porous channel
+    import math
+    ny, k = 37, 2
+    p = W.make_params(nx=4, ny=ny, bc_x=1, gravity_axis=0, porosity=0.9, Ra=2e3, Pr=1875.0, Da=0.05,
+                      Ste=1.0, k_ratio=1.0, cap_ratio=1.0, Nu_i=0.0, F_phi=0.0, k_f=1e-4,
+                      T_hot=1.0, T_cold=-1.0, T_init=1e-6, T_solidus=0.0, T_liquidus=1e-7,
+                      solid_treatment=1)
+    T = np.full((ny, 4), 1e-6)
+    T[:k + 1] = 0.0
+    T[ny - 1 - k:] = 0.0
+    s = lbm.Solver(p, "f64")
+    s.set_initial(0, T, T)
+    s.step(3000)
+    g = s.fields()
+    s.close()
+    o = oracle.Oracle(p)
+    o.set_initial(T, T)
+    o.step(3000)
+    r = o.fields()
+    assert np.abs(r["ux"]).max() > 1e-6
+    e = field_errors(g, r, p)
+    assert max(e.values()) < 1e-10, e
+    assert np.all(g["ux"][:k + 1] == 0.0)
