@@ -1,7 +1,9 @@
 """Throughput of the fused three-field MRT step on one MI355X.
 
-Prints one JSON line.  A step is one launch of the fused kernel over every
-node of the workload (default: the 8192 x 8192 cavity, Ra = 1e7, Da = 1e-5,
+Prints one JSON line.  A step advances every node of the workload by one
+time step; the library's default launch does two steps per launch through
+LDS tiles (FP32/FP64 storage), bit-identical to two one-step launches, and
+the one-step kernel is timed beside it.  Workload (default: the 8192 x 8192 cavity, Ra = 1e7, Da = 1e-5,
 phi = 0.9, Ste = 0.5, lambda = 1000, FP32 storage, 67.1 M nodes, 15 GB of
 double-buffered populations).  Inputs are resident in HBM before timing;
 the timed region is bracketed by HIP events on the stream the kernels run
@@ -66,11 +68,13 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_from_profile(sha: str, workload_name: str, precision: str, thermal_lattice: int = 9):
+def traffic_from_profile(sha: str, workload_name: str, precision: str, thermal_lattice: int = 9,
+                         steps_per_launch: int = 1):
     """HBM bytes per launch measured with rocprofv3 counters, if the summary
     in profiles/ was taken on the current kernel source."""
     tag = f"{workload_name}_d2q5_{precision}" if thermal_lattice == 5 else f"{workload_name}_{precision}"
-    path = os.path.join(ROOT, "profiles", f"traffic_step_kernel_{tag}.md")
+    kernel = "step2_kernel" if steps_per_launch == 2 else "step_kernel"
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{tag}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -145,6 +149,8 @@ def main():
     ap.add_argument("--npt", type=int, default=1)
     ap.add_argument("--xcd", type=int, default=1)
     ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--steps-per-launch", type=int, default=0, choices=[0, 1, 2],
+                    help="0: the library's default (two steps per launch through LDS where available)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--forms", action="store_true", help="also time the 16-bit and batched forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -186,30 +192,50 @@ def main():
     if args.autotune:
         launch = lbm.lbm_autotune(s.h, 5, os.path.join(ROOT, "gpurun_out", "autotune_cache.txt"))
     else:
-        lbm.lbm_set_launch(s.h, args.block, args.npt, args.xcd, args.persistent)
+        lbm.lbm_set_launch(s.h, args.block, args.npt, args.xcd, args.persistent,
+                           steps_per_launch=args.steps_per_launch or None)
         launch = lbm.lbm_get_launch(s.h)
     nodes = sum(p["nx"] * p["ny"] for p in params)
     ms = time_steps(lbm, torch, s, stream, args.steps, args.warmup)
     d = s.diagnostics(0, allow_nonfinite=True)
     ms_step = ms / args.steps
     mlups = nodes / (ms_step * 1e-3) / 1e6
+    # A launch reads and writes the state once, whether it advances one step
+    # or two (through LDS); the roofline is per launch.
+    spl = launch["steps_per_launch"]
     alg = bytes_per_node(prec, qt) * nodes
-    achieved = alg / (ms_step * 1e-3) / 1e9
+    launch_ms = ms_step * spl
+    achieved = alg / (launch_ms * 1e-3) / 1e9
     sha = kernel_sha()
-    traffic = traffic_from_profile(sha, args.workload, prec, qt)
+    traffic = traffic_from_profile(sha, args.workload, prec, qt, spl)
+    single = None
+    if spl == 2:
+        # the one-step kernel on the same state, for reference
+        lbm.lbm_set_launch(s.h, launch["block"], launch["nodes_per_thread"], launch["xcd_remap"],
+                           launch["persistent"], steps_per_launch=1)
+        t1 = time_steps(lbm, torch, s, stream, 100, 10) / 100
+        single = {"MLUPS": nodes / (t1 * 1e-3) / 1e6, "ms_per_step": t1,
+                  "achieved_GBps": alg / (t1 * 1e-3) / 1e9,
+                  "frac": alg / (t1 * 1e-3) / 1e9 / PEAK_HBM_GBPS}
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
         "config": {"workload": desc, "nodes": nodes, "storage": prec, "thermal_lattice": qt, "launch": launch,
-                   "seed": seed, "step_kernel": "lbm::step_kernel (fused pull-stream + NEE walls + 3 MRT collisions)"},
+                   "seed": seed,
+                   "step_kernel": ("lbm::step2_kernel (two fused steps per launch through LDS tiles)"
+                                   if launch["steps_per_launch"] == 2 else
+                                   "lbm::step_kernel (fused pull-stream + NEE walls + 3 MRT collisions)")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS,
                      "traffic": None if traffic is None else traffic,
-                     "algorithmic_bytes_per_launch": alg, "kernel_sha": sha},
+                     "algorithmic_bytes_per_launch": alg, "steps_per_launch": spl,
+                     "launch_ms": launch_ms, "kernel_sha": sha},
         "check": {"nonfinite": d["nonfinite"], "liquid_fraction": d["liquid_fraction"],
                   "energy_residual_rel": d["energy_residual"] / max(abs(d["E_int"]), 1e-300)},
     }
+    if single is not None:
+        out["one_step_kernel"] = single
     s.close()
     del ws
     torch.cuda.empty_cache()
@@ -227,12 +253,14 @@ def main():
             s2, ws2 = make_solver(lbm, torch, ps, pr, stream)
             T_pcm, T_mf = W.initial_temperatures(ps[0], sd)
             s2.set_initial(0, T_pcm, T_mf)
-            lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent)
+            lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent,
+                               steps_per_launch=args.steps_per_launch or None)
             n2 = ps[0]["nx"] * ps[0]["ny"]
             t = time_steps(lbm, torch, s2, stream, 100, 10) / 100
             name = f"{wl}_d2q5_{pr}" if q == 5 else f"{wl}_{pr}"
-            forms[name] = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t,
-                           "alg_GBps": bytes_per_node(pr, q) * n2 / (t * 1e-3) / 1e9}
+            sp2 = lbm.lbm_get_launch(s2.h)["steps_per_launch"]
+            forms[name] = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t, "steps_per_launch": sp2,
+                           "alg_GBps_per_launch": bytes_per_node(pr, q) * n2 / (t * sp2 * 1e-3) / 1e9}
             s2.close()
             del ws2
             torch.cuda.empty_cache()
@@ -240,7 +268,8 @@ def main():
         s2, ws2 = make_solver(lbm, torch, ps, "f32", stream)
         for c, q in enumerate(ps):
             s2.set_initial(c, *W.initial_temperatures(q, sd + c))
-        lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent)
+        lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent,
+                           steps_per_launch=args.steps_per_launch or None)
         n2 = sum(q["nx"] * q["ny"] for q in ps)
         t1 = time_steps(lbm, torch, s2, stream, 200, 10) / 200
         t2 = time_steps(lbm, torch, s2, stream, 20, 2, looped=True) / 20

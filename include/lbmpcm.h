@@ -171,13 +171,18 @@ typedef struct lbm_diag {
     double nonfinite;                 /* nodes holding a non-finite population  */
 } lbm_diag;
 
-/* Launch shape of the step kernel.  Every shape gives bit-identical results. */
+/* Launch shape of the step kernels.  Every shape gives bit-identical results. */
 typedef struct lbm_launch_config {
     int32_t block;            /* threads per workgroup: 64, 128, 256 or 512      */
     int32_t nodes_per_thread; /* 1, 2 or 4 consecutive-by-block nodes per thread */
     int32_t xcd_remap;        /* 1: consecutive tiles share an XCD (and its L2)  */
     int32_t persistent;       /* 0: one tile per workgroup; >0: that many
                                  workgroups per CU loop over all tiles           */
+    int32_t steps_per_launch; /* 1: one step per launch; 2: two steps per launch
+                                 through LDS (2-D tiles with a one-node ring,
+                                 the state crosses HBM once per two steps;
+                                 LBM_F64 and LBM_F32 only, the default there).
+                                 block and nodes_per_thread then do not apply. */
 } lbm_launch_config;
 
 /* Create a single-cavity solver.  Maps the groups to lattice units (Eq. 54,

@@ -391,6 +391,36 @@ int plane_groups(int st, PlaneGroup g[2]) {
     return 0;
 }
 
+// Splits [0, n) into runs of at most t (t >= 3, n >= 4) such that no run
+// starts at n - 1: a last run of one would leave a wall node whose partner
+// pulls from outside the two-step kernel's LDS region.
+void split_runs(int n, int t, std::vector<std::pair<int, int>> &out) {
+    out.clear();
+    int start = 0;
+    while (start < n) {
+        int w = std::min(t, n - start);
+        if (n - (start + w) == 1) w -= 1;
+        out.push_back({start, w});
+        start += w;
+    }
+}
+
+// Tiles of the two-step kernel for one cavity.
+void cavity_tiles2(int cav, int nx, int ny, int tw, int th, std::vector<Tile2> &tiles) {
+    std::vector<std::pair<int, int>> xs, ys;
+    split_runs(nx, tw, xs);
+    split_runs(ny, th, ys);
+    for (const auto &yr : ys)
+        for (const auto &xr : xs) tiles.push_back(Tile2{cav, xr.first, yr.first, xr.second, yr.second});
+}
+
+int64_t count_tiles2(int nx, int ny, int tw, int th) {
+    std::vector<std::pair<int, int>> xs, ys;
+    split_runs(nx, tw, xs);
+    split_runs(ny, th, ys);
+    return (int64_t)xs.size() * (int64_t)ys.size();
+}
+
 // Memory plan shared by lbm_workspace_bytes and the create calls.
 struct Plan {
     int st = -1;  // storage form (precision and thermal lattice)
@@ -398,6 +428,8 @@ struct Plan {
     std::vector<int64_t> node0, acc0;
     int64_t nodes = 0, stride = 0, slots = 0, max_nodes = 0;
     int max_tiles = 0;
+    int64_t tiles2 = 0;  // tiles of the two-step kernel (0: not available for this storage)
+    size_t off_tiles2 = 0;
     size_t off_pop[2], off_sr[2], off_acc, off_accs, off_cav, off_tiles, off_fields, off_part,
         off_out, total;
 };
@@ -454,6 +486,14 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     off = align256(off + (size_t)n * std::max(sizeof(CavityConst<double>), sizeof(CavityConst<float>)));
     pl.off_tiles = off;
     off = align256(off + (size_t)pl.max_tiles * sizeof(Tile));
+    if (step2_supported(st)) {
+        int tw, th;
+        step2_tile(st, &tw, &th);
+        for (int c = 0; c < n; ++c) pl.tiles2 += count_tiles2(p[c].nx, p[c].ny, tw, th);
+        if (pl.tiles2 >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
+        pl.off_tiles2 = off;
+        off = align256(off + (size_t)pl.tiles2 * sizeof(Tile2));
+    }
     pl.off_fields = off;
     off = align256(off + (size_t)6 * pl.max_nodes * sizeof(double));
     pl.off_part = off;
@@ -486,12 +526,14 @@ struct lbm_handle {
     int cur = 0;
     int64_t step = 0;
     std::vector<double> E0, M0;
-    lbm_launch_config lc{512, 1, 1, 0};
+    lbm_launch_config lc{512, 1, 1, 0, 1};
     std::vector<Tile> tiles;             // host copy, sorted by cavity: interior, then ring
     std::vector<int> cav_tile0, cav_ntiles;
-    int graph_chunk = 32;
+    int graph_chunk = 32;  // launches per captured graph
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipGraph_t gsrc[2] = {nullptr, nullptr};
+    hipGraphExec_t graph2[2] = {nullptr, nullptr};  // two-step launches
+    hipGraph_t gsrc2[2] = {nullptr, nullptr};
 
     void *pop(int b) { return ws + pl.off_pop[b]; }
     void *sr(int b) { return ws + pl.off_sr[b]; }
@@ -499,6 +541,7 @@ struct lbm_handle {
     double *acc_scratch() { return (double *)(ws + pl.off_accs); }
     void *cav() { return ws + pl.off_cav; }
     Tile *dtiles() { return (Tile *)(ws + pl.off_tiles); }
+    Tile2 *dtiles2() { return (Tile2 *)(ws + pl.off_tiles2); }
     double *fields() { return (double *)(ws + pl.off_fields); }
     double *partials() { return (double *)(ws + pl.off_part); }
     double *dout() { return (double *)(ws + pl.off_out); }
@@ -510,9 +553,24 @@ void drop_graphs(lbm_handle *h) {
     for (int b = 0; b < 2; ++b) {
         if (h->graph[b]) (void)hipGraphExecDestroy(h->graph[b]);
         if (h->gsrc[b]) (void)hipGraphDestroy(h->gsrc[b]);
-        h->graph[b] = nullptr;
-        h->gsrc[b] = nullptr;
+        if (h->graph2[b]) (void)hipGraphExecDestroy(h->graph2[b]);
+        if (h->gsrc2[b]) (void)hipGraphDestroy(h->gsrc2[b]);
+        h->graph[b] = h->graph2[b] = nullptr;
+        h->gsrc[b] = h->gsrc2[b] = nullptr;
     }
+}
+
+// Tile table of the two-step kernel (fixed per storage form).
+lbm_status build_tiles2(lbm_handle *h) {
+    if (!h->pl.tiles2) return LBM_OK;
+    int tw, th;
+    step2_tile(h->st, &tw, &th);
+    std::vector<Tile2> t;
+    for (int c = 0; c < h->n; ++c) cavity_tiles2(c, h->params[c].nx, h->params[c].ny, tw, th, t);
+    if ((int64_t)t.size() != h->pl.tiles2) return fail(LBM_EINVAL, "two-step tile table mismatch");
+    HIP_TRY(hipMemcpyAsync(h->dtiles2(), t.data(), t.size() * sizeof(Tile2), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
 }
 
 lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
@@ -538,10 +596,29 @@ lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
     return LBM_OK;
 }
 
-bool valid_launch(const lbm_launch_config &lc) {
+bool valid_launch(const lbm_launch_config &lc, int storage) {
     const bool b = lc.block == 64 || lc.block == 128 || lc.block == 256 || lc.block == 512;
     const bool n = lc.nodes_per_thread == 1 || lc.nodes_per_thread == 2 || lc.nodes_per_thread == 4;
-    return b && n && (lc.xcd_remap == 0 || lc.xcd_remap == 1) && lc.persistent >= 0 && lc.persistent <= 64;
+    const bool t = lc.steps_per_launch == 1 || (lc.steps_per_launch == 2 && step2_supported(storage));
+    return b && n && t && (lc.xcd_remap == 0 || lc.xcd_remap == 1) && lc.persistent >= 0 && lc.persistent <= 64;
+}
+
+Step2Launch step2_args(lbm_handle *h, int src_buf, double *acc, const lbm_launch_config &lc) {
+    Step2Launch L;
+    L.storage = h->st;
+    const int nt = (int)h->pl.tiles2;
+    L.grid = lc.persistent > 0 ? std::min(nt, h->n_cu * lc.persistent) : nt;
+    L.xcd_remap = lc.xcd_remap;
+    L.src = h->pop(src_buf);
+    L.dst = h->pop(1 - src_buf);
+    L.plane_stride = h->pl.stride;
+    L.sr_src = h->sr(src_buf);
+    L.sr_dst = h->sr(1 - src_buf);
+    L.acc = acc;
+    L.cav = h->cav();
+    L.tiles = h->dtiles2();
+    L.ntiles = nt;
+    return L;
 }
 
 StepLaunch step_args(lbm_handle *h, int pull, int src_buf, double *acc, int tile0, int ntiles,
@@ -571,13 +648,19 @@ lbm_status launch_one(lbm_handle *h, hipStream_t s, int pull, int src_buf) {
     return LBM_OK;
 }
 
-lbm_status build_graph(lbm_handle *h, int parity) {
+lbm_status build_graph(lbm_handle *h, int parity, bool two) {
     if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     int b = parity;
     for (int k = 0; k < h->graph_chunk; ++k) {
-        StepLaunch L = step_args(h, 1, b, h->acc(), 0, (int)h->tiles.size(), h->lc);
-        hipError_t e = launch_step(L, h->cap);
+        hipError_t e;
+        if (two) {
+            Step2Launch L = step2_args(h, b, h->acc(), h->lc);
+            e = launch_step2(L, h->cap);
+        } else {
+            StepLaunch L = step_args(h, 1, b, h->acc(), 0, (int)h->tiles.size(), h->lc);
+            e = launch_step(L, h->cap);
+        }
         if (e != hipSuccess) {
             hipGraph_t g;
             (void)hipStreamEndCapture(h->cap, &g);
@@ -586,8 +669,10 @@ lbm_status build_graph(lbm_handle *h, int parity) {
         }
         b ^= 1;
     }
-    HIP_TRY(hipStreamEndCapture(h->cap, &h->gsrc[parity]));
-    HIP_TRY(hipGraphInstantiate(&h->graph[parity], h->gsrc[parity], nullptr, nullptr, 0));
+    hipGraph_t *src = two ? &h->gsrc2[parity] : &h->gsrc[parity];
+    hipGraphExec_t *ex = two ? &h->graph2[parity] : &h->graph[parity];
+    HIP_TRY(hipStreamEndCapture(h->cap, src));
+    HIP_TRY(hipGraphInstantiate(ex, *src, nullptr, nullptr, 0));
     return LBM_OK;
 }
 
@@ -680,7 +765,10 @@ lbm_status setup(lbm_handle *h) {
         HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     }
+    h->lc.steps_per_launch = step2_supported(h->st) ? 2 : 1;
     lbm_status s = build_tiles(h, h->lc);
+    if (s != LBM_OK) return s;
+    s = build_tiles2(h);
     if (s != LBM_OK) return s;
     h->E0.assign(h->n, 0.0);
     h->M0.assign(h->n, 0.0);
@@ -814,9 +902,27 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
         h->step += 1;
         n -= 1;
     }
+    if (h->lc.steps_per_launch == 2) {
+        // pairs of steps, one launch each (a launch swaps the buffers once)
+        while (n >= 2 * (int64_t)h->graph_chunk && h->graph_chunk > 0) {
+            if (!h->graph2[h->cur]) {
+                lbm_status s = build_graph(h, h->cur, true);
+                if (s != LBM_OK) return s;
+            }
+            HIP_TRY(hipGraphLaunch(h->graph2[h->cur], h->stream));
+            h->step += 2 * (int64_t)h->graph_chunk;
+            n -= 2 * (int64_t)h->graph_chunk;
+        }
+        for (; n >= 2; n -= 2) {
+            Step2Launch L = step2_args(h, h->cur, h->acc(), h->lc);
+            HIP_TRY(launch_step2(L, h->stream));
+            h->cur ^= 1;
+            h->step += 2;
+        }
+    }
     while (n >= h->graph_chunk && h->graph_chunk > 0) {
         if (!h->graph[h->cur]) {
-            lbm_status s = build_graph(h, h->cur);
+            lbm_status s = build_graph(h, h->cur, false);
             if (s != LBM_OK) return s;
         }
         HIP_TRY(hipGraphLaunch(h->graph[h->cur], h->stream));
@@ -970,9 +1076,9 @@ extern "C" lbm_status lbm_get_launch(const lbm_handle *h, lbm_launch_config *out
 
 extern "C" lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg) {
     if (!h || !cfg) return fail(LBM_EINVAL, "NULL argument");
-    if (!valid_launch(*cfg))
-        return fail(LBM_EINVAL, "unsupported launch shape block=%d npt=%d xcd=%d persistent=%d", cfg->block,
-                    cfg->nodes_per_thread, cfg->xcd_remap, cfg->persistent);
+    if (!valid_launch(*cfg, h->st))
+        return fail(LBM_EINVAL, "unsupported launch shape block=%d npt=%d xcd=%d persistent=%d steps=%d",
+                    cfg->block, cfg->nodes_per_thread, cfg->xcd_remap, cfg->persistent, cfg->steps_per_launch);
     HIP_TRY(hipStreamSynchronize(h->stream));
     lbm_status s = build_tiles(h, *cfg);
     if (s != LBM_OK) return s;
@@ -1005,9 +1111,9 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
         if (f) {
             char k[256];
             lbm_launch_config lc;
-            while (fscanf(f, "%255s %d %d %d %d", k, &lc.block, &lc.nodes_per_thread, &lc.xcd_remap,
-                          &lc.persistent) == 5) {
-                if (key == k && valid_launch(lc)) {
+            while (fscanf(f, "%255s %d %d %d %d %d", k, &lc.block, &lc.nodes_per_thread, &lc.xcd_remap,
+                          &lc.persistent, &lc.steps_per_launch) == 6) {
+                if (key == k && valid_launch(lc, h->st)) {
                     fclose(f);
                     lbm_status s = lbm_set_launch(h, &lc);
                     if (s == LBM_OK && chosen) *chosen = lc;
@@ -1027,27 +1133,56 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
     lbm_launch_config best = h->lc;
     float best_ms = 1e30f;
     const lbm_launch_config saved = h->lc;
+    // Every trial reads the live buffer and writes only the other buffer and
+    // scratch tallies; times are per step.
+    auto trial = [&](const lbm_launch_config &lc, float *ms_per_step) -> lbm_status {
+        if (lc.steps_per_launch == 2) {
+            Step2Launch L = step2_args(h, h->cur, h->acc_scratch(), lc);
+            HIP_TRY(launch_step2(L, h->stream));
+            HIP_TRY(hipEventRecord(e0, h->stream));
+            for (int k = 0; k < steps; ++k) HIP_TRY(launch_step2(L, h->stream));
+        } else {
+            lbm_status s = build_tiles(h, lc);
+            if (s != LBM_OK) return s;
+            StepLaunch L = step_args(h, 1, h->cur, h->acc_scratch(), 0, (int)h->tiles.size(), lc);
+            HIP_TRY(launch_step(L, h->stream));
+            HIP_TRY(hipEventRecord(e0, h->stream));
+            for (int k = 0; k < steps; ++k) HIP_TRY(launch_step(L, h->stream));
+        }
+        HIP_TRY(hipEventRecord(e1, h->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *ms_per_step = ms / (float)(steps * lc.steps_per_launch);
+        return LBM_OK;
+    };
     for (int b : blocks)
         for (int np : npts)
             for (int xr : xcds)
                 for (int pp : pers) {
-                    lbm_launch_config lc{b, np, xr, pp};
-                    lbm_status s = build_tiles(h, lc);
+                    lbm_launch_config lc{b, np, xr, pp, 1};
+                    float ms;
+                    lbm_status s = trial(lc, &ms);
                     if (s != LBM_OK) return s;
-                    // reads the live buffer, writes only the other buffer and scratch tallies
-                    StepLaunch L = step_args(h, 1, h->cur, h->acc_scratch(), 0, (int)h->tiles.size(), lc);
-                    HIP_TRY(launch_step(L, h->stream));
-                    HIP_TRY(hipEventRecord(e0, h->stream));
-                    for (int k = 0; k < steps; ++k) HIP_TRY(launch_step(L, h->stream));
-                    HIP_TRY(hipEventRecord(e1, h->stream));
-                    HIP_TRY(hipEventSynchronize(e1));
-                    float ms = 0;
-                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
                     if (ms < best_ms) {
                         best_ms = ms;
                         best = lc;
                     }
                 }
+    if (step2_supported(h->st)) {
+        const lbm_launch_config one = best;
+        for (int xr : xcds)
+            for (int pp : pers) {
+                lbm_launch_config lc{one.block, one.nodes_per_thread, xr, pp, 2};
+                float ms;
+                lbm_status s = trial(lc, &ms);
+                if (s != LBM_OK) return s;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = lc;
+                }
+            }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)saved;
@@ -1059,8 +1194,8 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %d %d\n", key.c_str(), best.block, best.nodes_per_thread, best.xcd_remap,
-                    best.persistent);
+            fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), best.block, best.nodes_per_thread, best.xcd_remap,
+                    best.persistent, best.steps_per_launch);
             fclose(f);
         }
     }

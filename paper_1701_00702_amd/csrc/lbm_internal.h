@@ -89,6 +89,26 @@ struct StepLaunch {
     int ntiles;
 };
 
+// A tile of the two-steps-per-launch kernel: w x h nodes of one cavity at
+// (x0, y0); no tile starts on the last column or row of its cavity.
+struct Tile2 {
+    int32_t cav, x0, y0, w, h;
+};
+
+struct Step2Launch {
+    int storage;
+    int grid, xcd_remap;
+    const void *src;
+    void *dst;
+    int64_t plane_stride;
+    const void *sr_src;
+    void *sr_dst;
+    double *acc;
+    const void *cav;
+    const Tile2 *tiles;
+    int ntiles;
+};
+
 struct MacroLaunch {
     int storage;
     int raw;  // 1: populations are post-streaming already (step 0)
@@ -136,6 +156,9 @@ struct InitLaunch {
 };
 
 hipError_t launch_step(const StepLaunch &L, hipStream_t s);
+hipError_t launch_step2(const Step2Launch &L, hipStream_t s);
+bool step2_supported(int storage);
+void step2_tile(int storage, int *tw, int *th);  // tile shape of the two-step kernel
 hipError_t launch_macro(const MacroLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_init(const InitLaunch &L, int nx, int ny, hipStream_t s);

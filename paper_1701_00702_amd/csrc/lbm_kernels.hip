@@ -142,6 +142,107 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Two steps per launch through LDS (plain FP32 and FP64 storage).  One
+// workgroup per tile: the first update covers the tile and its one-node
+// ring into LDS, a barrier, then the second update covers the tile into the
+// destination buffer.  Tile shapes fill at most 64 KiB of LDS; the FP32
+// defaults (measured) let three or four workgroups share a CU, whose waves
+// overlap one tile's loads with another's arithmetic.
+// ---------------------------------------------------------------------------
+template <int ST>
+struct Step2Tile;
+// Tile shapes are build options (LBM_S2_*) for tuning; the defaults below.
+#ifndef LBM_S2_F32_TW
+#define LBM_S2_F32_TW 32
+#define LBM_S2_F32_TH 12
+#endif
+#ifndef LBM_S2_F32Q5_TW
+#define LBM_S2_F32Q5_TW 64
+#define LBM_S2_F32Q5_TH 5
+#endif
+constexpr int round64(int n) { return (n + 63) / 64 * 64; }
+template <>
+struct Step2Tile<ST_F32> {  // 27 x 4 + 4 = 112 B per slot (default 34 x 14 slots: 3 per CU)
+    static constexpr int TW = LBM_S2_F32_TW, TH = LBM_S2_F32_TH, NT = round64((TW + 2) * (TH + 2));
+};
+template <>
+struct Step2Tile<ST5_F32> {  // 19 x 4 + 4 = 80 B per slot (default 66 x 7 slots: 4 per CU)
+    static constexpr int TW = LBM_S2_F32Q5_TW, TH = LBM_S2_F32Q5_TH, NT = round64((TW + 2) * (TH + 2));
+};
+template <>
+struct Step2Tile<ST_F64> {  // 27 x 8 + 8 = 224 B per slot, 18 x 16 slots
+    static constexpr int TW = 16, TH = 14, NT = 320;
+};
+template <>
+struct Step2Tile<ST5_F64> {  // 19 x 8 + 8 = 160 B per slot, 18 x 22 slots
+    static constexpr int TW = 16, TH = 20, NT = 448;
+};
+
+template <class Lay, typename R, typename RH, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void step2_kernel(const void *__restrict__ src, void *__restrict__ dst,
+                                                   int64_t stride, const R *__restrict__ sr_src,
+                                                   R *__restrict__ sr_dst, double *__restrict__ acc,
+                                                   const CavityConst<R> *__restrict__ cav,
+                                                   const Tile2 *__restrict__ tiles, int ntiles, int xcd_remap) {
+    using Sh = Step2Shape<Lay, TW, TH>;
+    static_assert(Sh::NPOP * Sh::NSLOT * sizeof(typename Lay::T) + Sh::NSLOT * sizeof(R) <= 65536,
+                  "tile exceeds 64 KiB of LDS");
+    static_assert(NT >= Sh::NSLOT && NT % 64 == 0, "one thread per slot of the first update");
+    __shared__ typename Lay::T lds_q[Sh::NPOP * Sh::NSLOT];
+    __shared__ R lds_sr[Sh::NSLOT];
+    const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
+    for (int t = b; t < ntiles; t += gridDim.x) {
+        const Tile2 tl = tiles[t];
+        const CavityConst<R> &c = cav[tl.cav];
+        const int n1 = (TW + 2) * (tl.h + 2);
+        for (int s = (int)threadIdx.x; s < n1; s += NT)
+            step2_phase1<Lay, R, RH, TW, TH>(c, tl, src, stride, sr_src, acc, lds_q, lds_sr, s);
+        __syncthreads();
+        const int n2 = TW * tl.h;
+        for (int n = (int)threadIdx.x; n < n2; n += NT)
+            step2_phase2<Lay, R, RH, TW, TH>(c, tl, dst, stride, sr_dst, acc, lds_q, lds_sr, n);
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
+template <int ST>
+static hipError_t launch_step2_s(const Step2Launch &L, hipStream_t s) {
+    using Lay = typename LayoutOf<ST>::L;
+    using R = typename LayoutOf<ST>::R;
+    using RH = typename LayoutOf<ST>::RH;
+    using Tl = Step2Tile<ST>;
+    hipLaunchKernelGGL((step2_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT>), dim3(L.grid), dim3(Tl::NT), 0, s,
+                       L.src, L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                       (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
+    return hipGetLastError();
+}
+
+bool step2_supported(int storage) {
+    return storage == ST_F32 || storage == ST5_F32 || storage == ST_F64 || storage == ST5_F64;
+}
+
+void step2_tile(int storage, int *tw, int *th) {
+    switch (storage) {
+        case ST_F32: *tw = Step2Tile<ST_F32>::TW; *th = Step2Tile<ST_F32>::TH; return;
+        case ST5_F32: *tw = Step2Tile<ST5_F32>::TW; *th = Step2Tile<ST5_F32>::TH; return;
+        case ST_F64: *tw = Step2Tile<ST_F64>::TW; *th = Step2Tile<ST_F64>::TH; return;
+        case ST5_F64: *tw = Step2Tile<ST5_F64>::TW; *th = Step2Tile<ST5_F64>::TH; return;
+        default: *tw = *th = 0;
+    }
+}
+
+hipError_t launch_step2(const Step2Launch &L, hipStream_t s) {
+    if (L.grid < 1 || L.ntiles < 1) return hipErrorInvalidValue;
+    switch (L.storage) {
+        case ST_F32: return launch_step2_s<ST_F32>(L, s);
+        case ST5_F32: return launch_step2_s<ST5_F32>(L, s);
+        case ST_F64: return launch_step2_s<ST_F64>(L, s);
+        case ST5_F64: return launch_step2_s<ST5_F64>(L, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Macroscopic fields and per-block diagnostics of one cavity.
 // ---------------------------------------------------------------------------
 constexpr int MB = 256;  // threads per block of the diagnostics kernels

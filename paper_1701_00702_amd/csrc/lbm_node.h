@@ -27,6 +27,8 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #include "lbm_internal.h"
 
@@ -47,6 +49,29 @@ template <typename R>
 __host__ __device__ constexpr R w_of(int i) {
     return i == 0 ? R(4) / R(9) : (i <= 4 ? R(1) / R(9) : R(1) / R(36));
 }
+
+// Reciprocal and square root of the velocity solve and the force: correctly
+// rounded in FP64; in FP32 the hardware instructions (about 1 ulp), a tenth
+// of the instructions of the correctly rounded sequences.  The FP32 forms
+// are held to 1e-4 of the FP64 checker, far above that rounding.
+template <typename R>
+LBM_HD R rcp_of(R x) {
+    return R(1) / x;
+}
+template <typename R>
+LBM_HD R sqrt_of(R x) {
+    return sqrt(x);
+}
+#if defined(__HIP_DEVICE_COMPILE__)
+template <>
+LBM_HD float rcp_of<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);
+}
+template <>
+LBM_HD float sqrt_of<float>(float x) {
+    return __builtin_amdgcn_sqrtf(x);
+}
+#endif
 
 // Enthalpy-field constants in the enthalpy arithmetic type.
 template <typename RH>
@@ -417,11 +442,11 @@ LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[
     // Eq. (24), then the explicit root Eq. (23) with Eq. (25).
     const R jx = (qf[1] - qf[3]) + ((qf[5] - qf[6]) - (qf[7] - qf[8]));
     const R jy = (qf[2] - qf[4]) + ((qf[5] + qf[6]) - (qf[7] + qf[8]));
-    const R inv_rho = R(1) / m.rho;
+    const R inv_rho = rcp_of(m.rho);
     const R vx = jx * inv_rho + R(0.5) * c.phi * m.Gx;
     const R vy = jy * inv_rho + R(0.5) * c.phi * m.Gy;
-    const R vmag = sqrt(vx * vx + vy * vy);
-    const R inv_den = R(1) / (c.l0 + sqrt(c.l0sq + c.l1 * vmag));
+    const R vmag = sqrt_of(vx * vx + vy * vy);
+    const R inv_den = rcp_of(c.l0 + sqrt_of(c.l0sq + c.l1 * vmag));
     m.ux = vx * inv_den;
     m.uy = vy * inv_den;
     // bounce-back: below the interface value f_l = 0.5 a node is solid, at rest
@@ -449,7 +474,7 @@ LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R q[9]) {
     to_moments(q, d);
     const R ux = m.ux, uy = m.uy, rho = m.rho;
     const R uu = ux * ux + uy * uy;
-    const R umag = sqrt(uu);
+    const R umag = sqrt_of(uu);
     // Eq. (3).
     const R Fx = -c.drag_lin * ux - c.drag_quad * umag * ux + c.phi * m.Gx;
     const R Fy = -c.drag_lin * uy - c.drag_quad * umag * uy + c.phi * m.Gy;
@@ -718,25 +743,20 @@ LBM_HD void link_content(const CavityConst<R> &c, int i, const R qf[9], const RH
     m = (double)w_of<double>(i) + (double)qf[i];
 }
 
-// One node's full time step.  KIND selects which of the interior and wall
-// code paths this instantiation carries (the caller guarantees the node is
-// of that kind).
-template <class Lay, typename R, typename RH, bool PULL, int KIND = NODE_ANY>
-LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
-                      const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
-                      int x, int y) {
+// The update of one node from its gathered (post-streaming) offsets: wall
+// tallies (only when the node's step is counted here, `tally`), wall
+// reconstruction, macroscopic values, the three collisions and the
+// interstitial sources.  On return q* hold the post-collision offsets and
+// m, th the values the split layout stores as bases; the result is the
+// new PCM source Sr_f.
+template <int QT, typename R, typename RH, bool PULL>
+LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, R qf[9], RH qg[9], R qh[9],
+                      R sr_prev, bool tally, double *__restrict__ acc, Thermo<RH> &th, Macro<R> &m) {
     const int nx = c.nx, ny = c.ny;
-    const NodeGeom g = geometry_of<R, KIND>(c, x, y, PULL);
-    R qf[9], qh[9];
-    RH qg[9];
-    gather<Lay, R, RH, PULL>(c, src, stride, g, x, y, qf, qg, qh);
-    const int64_t k = c.node0 + (int64_t)y * nx + x;
-    const R sr_prev = sr_src[k];
-
     // Wall tallies: an interior node next to a wall owns one slot per wall it
     // touches (x: the vertical wall, y: the horizontal one).
     double xE = 0.0, xM = 0.0, yE = 0.0, yM = 0.0;
-    if (PULL && (g.near_x || g.near_y)) {
+    if (PULL && tally && (g.near_x || g.near_y)) {
         // inflow: populations pulled from wall nodes (post-collision of the
         // previous step)
 #pragma unroll
@@ -746,7 +766,7 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
             const bool ony = (py == 0 || py == ny - 1);
             if (onx || ony) {
                 double e, mm;
-                link_content<Lay::QT>(c, i, qf, qg, qh, e, mm);
+                link_content<QT>(c, i, qf, qg, qh, e, mm);
                 if (onx) {
                     xE += e;
                     xM += mm;
@@ -758,11 +778,9 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
         }
     }
 
-    if (PULL && g.wall) reconstruct_wall<Lay::QT>(c, x, y, qf, qg, qh);
+    if (PULL && g.wall) reconstruct_wall<QT>(c, x, y, qf, qg, qh);
 
-    Thermo<RH> th;
-    Macro<R> m;
-    macros<Lay::QT>(c, qf, qg, qh, th, m);
+    macros<QT>(c, qf, qg, qh, th, m);
     collide_flow(c, m, qf);
     // Eqs. (36), (47) with the backward difference of Remark III.
     const RH srf = (RH)c.hv_f * ((RH)m.Tm - th.Tf);
@@ -770,7 +788,7 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
     const R srm_prev = -c.sr_ratio * sr_prev;
     const RH S_pcm = srf + RH(0.5) * (srf - (RH)sr_prev);
     const R S_metal = srm + R(0.5) * (srm - srm_prev);
-    if (Lay::QT == 9) {
+    if (QT == 9) {
         collide_pcm(c, th, m, S_pcm, qg);
         collide_metal(c, m, S_metal, qh);
     } else {
@@ -778,7 +796,7 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
         collide_metal5(c, m, S_metal, qh);
     }
 
-    if (g.near_x || g.near_y) {
+    if (tally && (g.near_x || g.near_y)) {
         // outflow: post-collision populations aimed at wall nodes
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
@@ -787,7 +805,7 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
             const bool ony = (ty == 0 || ty == ny - 1);
             if (onx || ony) {
                 double e, mm;
-                link_content<Lay::QT>(c, i, qf, qg, qh, e, mm);
+                link_content<QT>(c, i, qf, qg, qh, e, mm);
                 if (onx) {
                     xE -= e;
                     xM -= mm;
@@ -808,7 +826,139 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
             acc[2 * slot + 1] += yM;
         }
     }
+    return srf;
+}
 
+// One node's full time step.  KIND selects which of the interior and wall
+// code paths this instantiation carries (the caller guarantees the node is
+// of that kind).
+template <class Lay, typename R, typename RH, bool PULL, int KIND = NODE_ANY>
+LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
+                      const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
+                      int x, int y) {
+    const NodeGeom g = geometry_of<R, KIND>(c, x, y, PULL);
+    R qf[9], qh[9];
+    RH qg[9];
+    gather<Lay, R, RH, PULL>(c, src, stride, g, x, y, qf, qg, qh);
+    const int64_t k = c.node0 + (int64_t)y * c.nx + x;
+    Thermo<RH> th;
+    Macro<R> m;
+    const RH srf = update_node<Lay::QT, R, RH, PULL>(c, g, x, y, qf, qg, qh, sr_src[k], true, acc, th, m);
+    const ThermalConst<RH> &t = thermal<RH>(c);
+    Lay::template store<R>(dst, stride, 0, qf, m.drho, k, c);
+    Lay::template store<RH>(dst, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);
+    Lay::template store<R>(dst, stride, 2, qh, c.c_mref * m.dTm, k, c);
+    sr_dst[k] = (R)srf;
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per sweep through LDS.  A tile of w x h nodes (w <= TW, h <= TH)
+// at (x0, y0) first advances the tile and a one-node ring around it (the
+// region R1, (w+2) x (h+2) slots, unwrapped coordinates) from the global
+// state into LDS, then advances the tile from LDS to the global state: the
+// same two updates as two single steps, with the intermediate populations
+// kept in their storage type, so the result is bit-identical.  The state
+// crosses HBM once per two steps.  A wall node of the tile pulls through its
+// partner from at most one node outside the tile, so R1 covers the second
+// update as long as no tile starts on the last column or row of a cavity
+// (the host's tiling guarantees it).  Only the tile's own nodes write wall
+// tallies.  Plain layouts only: the LDS holds each population as stored.
+// ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LBM_HOST_CHECK(cond) ((void)0)
+#else
+#define LBM_HOST_CHECK(cond)                                                              \
+    do {                                                                                  \
+        if (!(cond)) {                                                                    \
+            fprintf(stderr, "lbm: check failed: %s (%s:%d)\n", #cond, __FILE__, __LINE__); \
+            abort();                                                                      \
+        }                                                                                 \
+    } while (0)
+#endif
+
+template <class Lay, int TW, int TH>
+struct Step2Shape {
+    static constexpr int QT = Lay::QT;
+    static constexpr int NPOP = 9 + 2 * QT;
+    static constexpr int NSLOT = (TW + 2) * (TH + 2);  // LDS plane stride
+    using T = typename Lay::T;
+};
+
+// First update: slot s of R1 (row-major with the fixed pitch TW + 2, so the
+// decode divides by a constant; columns beyond w + 2 idle).  Reads the
+// global state, writes the slot's post-collision populations and Sr_f to LDS.
+template <class Lay, typename R, typename RH, int TW, int TH>
+LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *src, int64_t stride,
+                         const R *__restrict__ sr_src, double *__restrict__ acc,
+                         typename Lay::T *lds_q, R *lds_sr, int s) {
+    using Sh = Step2Shape<Lay, TW, TH>;
+    constexpr int LW = TW + 2;
+    LBM_HOST_CHECK(s >= 0 && s < LW * (tl.h + 2) && s < Sh::NSLOT);
+    const int lx = s % LW, ly = s / LW;
+    if (lx >= tl.w + 2) return;
+    const int x = tl.x0 - 1 + lx, y = tl.y0 - 1 + ly;  // unwrapped
+    if (y < 0 || y >= c.ny) return;
+    int xx = x;
+    if (c.periodic) xx = x < 0 ? x + c.nx : (x >= c.nx ? x - c.nx : x);
+    else if (x < 0 || x >= c.nx) return;
+    LBM_HOST_CHECK(xx >= 0 && xx < c.nx);
+    const bool owned = x >= tl.x0 && x < tl.x0 + tl.w && y >= tl.y0 && y < tl.y0 + tl.h;
+    const NodeGeom g = geometry(c, xx, y, true);
+    R qf[9], qh[9];
+    RH qg[9];
+    gather<Lay, R, RH, true>(c, src, stride, g, xx, y, qf, qg, qh);
+    const int64_t k = c.node0 + (int64_t)y * c.nx + xx;
+    Thermo<RH> th;
+    Macro<R> m;
+    const RH srf = update_node<Sh::QT, R, RH, true>(c, g, xx, y, qf, qg, qh, sr_src[k], owned, acc, th, m);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        lds_q[i * Sh::NSLOT + s] = (typename Lay::T)qf[i];
+        if (i < Sh::QT) {
+            lds_q[(9 + i) * Sh::NSLOT + s] = (typename Lay::T)qg[i];
+            lds_q[(9 + Sh::QT + i) * Sh::NSLOT + s] = (typename Lay::T)qh[i];
+        }
+    }
+    lds_sr[s] = (R)srf;
+}
+
+// Second update: node n of the tile (row-major with pitch TW; columns beyond
+// w idle).  Pulls from LDS, writes the global state.
+template <class Lay, typename R, typename RH, int TW, int TH>
+LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, int64_t stride,
+                         R *__restrict__ sr_dst, double *__restrict__ acc, const typename Lay::T *lds_q,
+                         const R *lds_sr, int n) {
+    using Sh = Step2Shape<Lay, TW, TH>;
+    constexpr int LW = TW + 2;
+    LBM_HOST_CHECK(n >= 0 && n < TW * tl.h);
+    if (n % TW >= tl.w) return;
+    const int x = tl.x0 + n % TW, y = tl.y0 + n / TW;
+    LBM_HOST_CHECK(x >= 0 && x < c.nx && y >= 0 && y < c.ny);
+    const NodeGeom g = geometry(c, x, y, true);
+    R qf[9], qh[9];
+    RH qg[9];
+    // pull from the LDS slots of the neighbours of the node (or of its wall
+    // partner), in unwrapped coordinates relative to R1's corner
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int lx = g.sx - ex_of(i) - (tl.x0 - 1), ly = g.sy - ey_of(i) - (tl.y0 - 1);
+        LBM_HOST_CHECK(lx >= 0 && lx < LW && ly >= 0 && ly < tl.h + 2);
+        const int sl = ly * LW + lx;
+        LBM_HOST_CHECK(sl < Sh::NSLOT);
+        qf[i] = (R)lds_q[i * Sh::NSLOT + sl];
+        if (i < Sh::QT) {
+            qg[i] = (RH)lds_q[(9 + i) * Sh::NSLOT + sl];
+            qh[i] = (R)lds_q[(9 + Sh::QT + i) * Sh::NSLOT + sl];
+        } else {
+            qg[i] = RH(0);
+            qh[i] = R(0);
+        }
+    }
+    const int self = (y - (tl.y0 - 1)) * LW + (x - (tl.x0 - 1));
+    const int64_t k = c.node0 + (int64_t)y * c.nx + x;
+    Thermo<RH> th;
+    Macro<R> m;
+    const RH srf = update_node<Sh::QT, R, RH, true>(c, g, x, y, qf, qg, qh, lds_sr[self], true, acc, th, m);
     const ThermalConst<RH> &t = thermal<RH>(c);
     Lay::template store<R>(dst, stride, 0, qf, m.drho, k, c);
     Lay::template store<RH>(dst, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);

@@ -87,9 +87,11 @@ def test_fp64_c1_parity(lbm):
     assert gd["step"] == 2000
 
 
-@pytest.mark.parametrize("launch", [dict(block=64, nodes_per_thread=1, xcd_remap=0, persistent=0),
-                                    dict(block=128, nodes_per_thread=2, xcd_remap=1, persistent=0),
-                                    dict(block=256, nodes_per_thread=4, xcd_remap=1, persistent=2)])
+@pytest.mark.parametrize("launch", [dict(block=64, nodes_per_thread=1, xcd_remap=0, persistent=0, steps_per_launch=1),
+                                    dict(block=128, nodes_per_thread=2, xcd_remap=1, persistent=0, steps_per_launch=1),
+                                    dict(block=256, nodes_per_thread=4, xcd_remap=1, persistent=2, steps_per_launch=1),
+                                    dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=2),
+                                    dict(block=256, nodes_per_thread=1, xcd_remap=0, persistent=2, steps_per_launch=2)])
 def test_fp64_ragged_tiles(lbm, launch):
     # 67 x 45 nodes: several tiles per row and a ragged tail for every shape
     p = W.scaled_cavity(W.case_c1()[0], 67, 45)
@@ -154,12 +156,14 @@ def test_launch_shapes_bitwise_and_deterministic(lbm):
     ref = None
     # rows of 300 nodes span several tiles for every shape, including the
     # first (non-pulling) step
-    for launch in (dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0),
-                   dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0),
-                   dict(block=128, nodes_per_thread=2, xcd_remap=0, persistent=4),
-                   dict(block=64, nodes_per_thread=4, xcd_remap=1, persistent=0),
-                   dict(block=64, nodes_per_thread=1, xcd_remap=0, persistent=0),
-                   dict(block=512, nodes_per_thread=4, xcd_remap=1, persistent=1)):
+    for launch in (dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=1),
+                   dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=1),
+                   dict(block=128, nodes_per_thread=2, xcd_remap=0, persistent=4, steps_per_launch=1),
+                   dict(block=64, nodes_per_thread=4, xcd_remap=1, persistent=0, steps_per_launch=1),
+                   dict(block=64, nodes_per_thread=1, xcd_remap=0, persistent=0, steps_per_launch=1),
+                   dict(block=512, nodes_per_thread=4, xcd_remap=1, persistent=1, steps_per_launch=1),
+                   dict(block=512, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=2),
+                   dict(block=512, nodes_per_thread=1, xcd_remap=0, persistent=3, steps_per_launch=2)):
         s = lbm.Solver(p, "f32")
         lbm.lbm_set_launch(s.h, **launch)
         s.set_initial(0, T_pcm, T_mf)

@@ -172,9 +172,10 @@ def test_d2q5_launch_shapes_batches_and_checkpoints_bitwise(lbm):
     p = dict(W.scaled_cavity(W.case_c2()[0], 300, 130), thermal_lattice=5)
     T_pcm, T_mf = W.initial_temperatures(p, 1)
     ref = None
-    for launch in (dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0),
-                   dict(block=128, nodes_per_thread=2, xcd_remap=0, persistent=4),
-                   dict(block=512, nodes_per_thread=4, xcd_remap=1, persistent=1)):
+    for launch in (dict(block=256, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=1),
+                   dict(block=128, nodes_per_thread=2, xcd_remap=0, persistent=4, steps_per_launch=1),
+                   dict(block=512, nodes_per_thread=4, xcd_remap=1, persistent=1, steps_per_launch=1),
+                   dict(block=512, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=2)):
         s = lbm.Solver(p, "f32")
         lbm.lbm_set_launch(s.h, **launch)
         s.set_initial(0, T_pcm, T_mf)
