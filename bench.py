@@ -62,6 +62,16 @@ def workload(name: str):
     if name == "c4":
         p, _, seed, prec = W.case_c4()
         return [p], seed, prec, "cavity 4096x4096 Ra=1e6 Da=1e-4 phi=0.9 Ste=1 lambda=100 Nu_i=5"
+    if name.startswith("bat"):
+        # k identical n x n cavities in one batch (bat<k>x<n>)
+        k, n = (int(v) for v in name[3:].split("x"))
+        p = W.scaled_cavity(W.case_c3()[0], n)
+        return [dict(p) for _ in range(k)], 0, "f32", f"{k} cavities {n}x{n}, physics of the 8192x8192 case"
+    if name.startswith("sq"):
+        # square cavity of the 8192^2 physics at another size (sq<n>)
+        n = int(name[2:])
+        p = W.scaled_cavity(W.case_c3()[0], n)
+        return [p], 0, "f32", f"cavity {n}x{n}, physics of the 8192x8192 case"
     if name == "c5":
         ps, _, seed, prec = W.case_c5()
         return ps, seed, prec, "256 cavities, sides log-U[64,512] (seed 7), 24198641 nodes"
@@ -141,7 +151,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c3",
+                    help="c2, c3 (default), c4, c5, sq<n> for an n x n cavity, bat<k>x<n> for k of them")
     ap.add_argument("--precision", default=None, choices=[None] + list(BYTES_PER_NODE))
     ap.add_argument("--thermal-lattice", type=int, default=9, choices=[9, 5],
                     help="9: D2Q9 thermal fields (the paper's main method); 5: D2Q5 (Appendix B)")
