@@ -170,6 +170,14 @@ struct Step2Tile<ST5_F32> {  // 19 x 4 + 4 = 80 B per slot (default 66 x 7 slots
     static constexpr int TW = LBM_S2_F32Q5_TW, TH = LBM_S2_F32Q5_TH, NT = round64((TW + 2) * (TH + 2));
 };
 template <>
+struct Step2Tile<ST_F32H> {  // 26 x 4 + 8 + 4 = 116 B per slot, 34 x 13 slots: 3 per CU
+    static constexpr int TW = 32, TH = 11, NT = 448;
+};
+template <>
+struct Step2Tile<ST5_F32H> {  // 18 x 4 + 8 + 4 = 84 B per slot, 66 x 7 slots: 4 per CU
+    static constexpr int TW = 64, TH = 5, NT = 512;
+};
+template <>
 struct Step2Tile<ST_F64> {  // 27 x 8 + 8 = 224 B per slot, 18 x 16 slots
     static constexpr int TW = 16, TH = 14, NT = 320;
 };
@@ -185,10 +193,9 @@ __global__ __launch_bounds__(NT) void step2_kernel(const void *__restrict__ src,
                                                    const CavityConst<R> *__restrict__ cav,
                                                    const Tile2 *__restrict__ tiles, int ntiles, int xcd_remap) {
     using Sh = Step2Shape<Lay, TW, TH>;
-    static_assert(Sh::NPOP * Sh::NSLOT * sizeof(typename Lay::T) + Sh::NSLOT * sizeof(R) <= 65536,
-                  "tile exceeds 64 KiB of LDS");
+    static_assert(Sh::LDS_BYTES + Sh::NSLOT * sizeof(R) <= 65536, "tile exceeds 64 KiB of LDS");
     static_assert(NT >= Sh::NSLOT && NT % 64 == 0, "one thread per slot of the first update");
-    __shared__ typename Lay::T lds_q[Sh::NPOP * Sh::NSLOT];
+    __shared__ __align__(16) unsigned char lds_q[Sh::LDS_BYTES];
     __shared__ R lds_sr[Sh::NSLOT];
     const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
     for (int t = b; t < ntiles; t += gridDim.x) {
@@ -218,7 +225,8 @@ static hipError_t launch_step2_s(const Step2Launch &L, hipStream_t s) {
 }
 
 bool step2_supported(int storage) {
-    return storage == ST_F32 || storage == ST5_F32 || storage == ST_F64 || storage == ST5_F64;
+    return storage == ST_F32 || storage == ST5_F32 || storage == ST_F64 || storage == ST5_F64 ||
+           storage == ST_F32H || storage == ST5_F32H;
 }
 
 void step2_tile(int storage, int *tw, int *th) {
@@ -227,6 +235,8 @@ void step2_tile(int storage, int *tw, int *th) {
         case ST5_F32: *tw = Step2Tile<ST5_F32>::TW; *th = Step2Tile<ST5_F32>::TH; return;
         case ST_F64: *tw = Step2Tile<ST_F64>::TW; *th = Step2Tile<ST_F64>::TH; return;
         case ST5_F64: *tw = Step2Tile<ST5_F64>::TW; *th = Step2Tile<ST5_F64>::TH; return;
+        case ST_F32H: *tw = Step2Tile<ST_F32H>::TW; *th = Step2Tile<ST_F32H>::TH; return;
+        case ST5_F32H: *tw = Step2Tile<ST5_F32H>::TW; *th = Step2Tile<ST5_F32H>::TH; return;
         default: *tw = *th = 0;
     }
 }
@@ -238,6 +248,8 @@ hipError_t launch_step2(const Step2Launch &L, hipStream_t s) {
         case ST5_F32: return launch_step2_s<ST5_F32>(L, s);
         case ST_F64: return launch_step2_s<ST_F64>(L, s);
         case ST5_F64: return launch_step2_s<ST5_F64>(L, s);
+        case ST_F32H: return launch_step2_s<ST_F32H>(L, s);
+        case ST5_F32H: return launch_step2_s<ST5_F32H>(L, s);
         default: return hipErrorInvalidValue;
     }
 }

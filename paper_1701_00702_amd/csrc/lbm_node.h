@@ -862,7 +862,8 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
 // partner from at most one node outside the tile, so R1 covers the second
 // update as long as no tile starts on the last column or row of a cavity
 // (the host's tiling guarantees it).  Only the tile's own nodes write wall
-// tallies.  Plain layouts only: the LDS holds each population as stored.
+// tallies.  Plain layouts and the FP32 layout with the FP64 rest enthalpy
+// population: the LDS holds each population in the type it is stored in.
 // ---------------------------------------------------------------------------
 #if defined(__HIP_DEVICE_COMPILE__)
 #define LBM_HOST_CHECK(cond) ((void)0)
@@ -876,12 +877,52 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64
     } while (0)
 #endif
 
+// How a layout keeps its populations in LDS for the two-step kernel: in
+// the element type it stores them in, so that the second update sees the
+// same values as a one-step launch would load.  NSLOT is the plane stride.
+template <class Lay>
+struct LdsCodec;
+template <class E, bool SCALED, int QT_>
+struct LdsCodec<Plain<E, SCALED, QT_>> {
+    static_assert(!SCALED, "16-bit forms have no two-step kernel");
+    using T = typename E::T;
+    static constexpr int QT = QT_;
+    static constexpr size_t bytes(int nslot) { return (size_t)(9 + 2 * QT) * nslot * sizeof(T); }
+    LBM_HD static int plane(int f, int i) { return f == 0 ? i : 9 + (f - 1) * QT + i; }
+    template <typename V>
+    LBM_HD static void put(void *lds, int nslot, int f, int i, int slot, V v) {
+        ((T *)lds)[plane(f, i) * nslot + slot] = (T)v;
+    }
+    template <typename V>
+    LBM_HD static V get(const void *lds, int nslot, int f, int i, int slot) {
+        return (V)((const T *)lds)[plane(f, i) * nslot + slot];
+    }
+};
+template <int QT_>
+struct LdsCodec<PlainH64<QT_>> {
+    static constexpr int QT = QT_;
+    static constexpr int NF32 = PlainH64<QT_>::NF32;
+    // FP32 planes, then the FP64 rest enthalpy plane (8-byte aligned)
+    static constexpr size_t f64_offset(int nslot) { return ((size_t)NF32 * nslot * 4 + 7) & ~(size_t)7; }
+    static constexpr size_t bytes(int nslot) { return f64_offset(nslot) + (size_t)nslot * 8; }
+    template <typename V>
+    LBM_HD static void put(void *lds, int nslot, int f, int i, int slot, V v) {
+        if (f == 1 && i == 0) ((double *)((char *)lds + f64_offset(nslot)))[slot] = (double)v;
+        else ((float *)lds)[PlainH64<QT_>::plane(f, i) * nslot + slot] = (float)v;
+    }
+    template <typename V>
+    LBM_HD static V get(const void *lds, int nslot, int f, int i, int slot) {
+        if (f == 1 && i == 0) return (V)((const double *)((const char *)lds + f64_offset(nslot)))[slot];
+        return (V)((const float *)lds)[PlainH64<QT_>::plane(f, i) * nslot + slot];
+    }
+};
+
 template <class Lay, int TW, int TH>
 struct Step2Shape {
     static constexpr int QT = Lay::QT;
-    static constexpr int NPOP = 9 + 2 * QT;
     static constexpr int NSLOT = (TW + 2) * (TH + 2);  // LDS plane stride
-    using T = typename Lay::T;
+    using Codec = LdsCodec<Lay>;
+    static constexpr size_t LDS_BYTES = Codec::bytes(NSLOT);
 };
 
 // First update: slot s of R1 (row-major with the fixed pitch TW + 2, so the
@@ -889,8 +930,8 @@ struct Step2Shape {
 // global state, writes the slot's post-collision populations and Sr_f to LDS.
 template <class Lay, typename R, typename RH, int TW, int TH>
 LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *src, int64_t stride,
-                         const R *__restrict__ sr_src, double *__restrict__ acc,
-                         typename Lay::T *lds_q, R *lds_sr, int s) {
+                         const R *__restrict__ sr_src, double *__restrict__ acc, void *lds_q, R *lds_sr,
+                         int s) {
     using Sh = Step2Shape<Lay, TW, TH>;
     constexpr int LW = TW + 2;
     LBM_HOST_CHECK(s >= 0 && s < LW * (tl.h + 2) && s < Sh::NSLOT);
@@ -911,12 +952,13 @@ LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *s
     Thermo<RH> th;
     Macro<R> m;
     const RH srf = update_node<Sh::QT, R, RH, true>(c, g, xx, y, qf, qg, qh, sr_src[k], owned, acc, th, m);
+    using Cd = typename Sh::Codec;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        lds_q[i * Sh::NSLOT + s] = (typename Lay::T)qf[i];
+        Cd::put(lds_q, Sh::NSLOT, 0, i, s, qf[i]);
         if (i < Sh::QT) {
-            lds_q[(9 + i) * Sh::NSLOT + s] = (typename Lay::T)qg[i];
-            lds_q[(9 + Sh::QT + i) * Sh::NSLOT + s] = (typename Lay::T)qh[i];
+            Cd::put(lds_q, Sh::NSLOT, 1, i, s, qg[i]);
+            Cd::put(lds_q, Sh::NSLOT, 2, i, s, qh[i]);
         }
     }
     lds_sr[s] = (R)srf;
@@ -926,7 +968,7 @@ LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *s
 // w idle).  Pulls from LDS, writes the global state.
 template <class Lay, typename R, typename RH, int TW, int TH>
 LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, int64_t stride,
-                         R *__restrict__ sr_dst, double *__restrict__ acc, const typename Lay::T *lds_q,
+                         R *__restrict__ sr_dst, double *__restrict__ acc, const void *lds_q,
                          const R *lds_sr, int n) {
     using Sh = Step2Shape<Lay, TW, TH>;
     constexpr int LW = TW + 2;
@@ -945,10 +987,11 @@ LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, in
         LBM_HOST_CHECK(lx >= 0 && lx < LW && ly >= 0 && ly < tl.h + 2);
         const int sl = ly * LW + lx;
         LBM_HOST_CHECK(sl < Sh::NSLOT);
-        qf[i] = (R)lds_q[i * Sh::NSLOT + sl];
+        using Cd = typename Sh::Codec;
+        qf[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 0, i, sl);
         if (i < Sh::QT) {
-            qg[i] = (RH)lds_q[(9 + i) * Sh::NSLOT + sl];
-            qh[i] = (R)lds_q[(9 + Sh::QT + i) * Sh::NSLOT + sl];
+            qg[i] = Cd::template get<RH>(lds_q, Sh::NSLOT, 1, i, sl);
+            qh[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 2, i, sl);
         } else {
             qg[i] = RH(0);
             qh[i] = R(0);

@@ -3,8 +3,8 @@ per two steps through LDS tiles, and the result must be the same map as
 two single steps, bit for bit (populations, sources, FP64 wall tallies and
 diagnostics), on every geometry the single-step path handles: walls and
 corners, periodic channels, ragged and batched cavities, mixed wall types,
-the bounce-back alternative, both thermal lattices, FP32 and FP64, odd step
-counts and graph replays.
+the bounce-back alternative, both thermal lattices, FP32, FP64 and FP32 with
+the FP64 rest enthalpy population, odd step counts and graph replays.
 """
 import numpy as np
 import pytest
@@ -57,7 +57,7 @@ def _run(lbm, ps, prec, steps, spl, chunks):
 
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("qt", [9, 5])
-@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("prec", ["f32", "f64", "f32h64"])
 def test_two_step_is_bitwise_two_single_steps(lbm, case, qt, prec):
     ps = [dict(q, thermal_lattice=qt) for q in CASES[case]()]
     steps = 131      # first (raw) step, graph replays of 32 launches, odd remainder
