@@ -68,10 +68,11 @@ def workload(name: str):
         p = W.scaled_cavity(W.case_c3()[0], n)
         return [dict(p) for _ in range(k)], 0, "f32", f"{k} cavities {n}x{n}, physics of the 8192x8192 case"
     if name.startswith("sq"):
-        # square cavity of the 8192^2 physics at another size (sq<n>)
-        n = int(name[2:])
-        p = W.scaled_cavity(W.case_c3()[0], n)
-        return [p], 0, "f32", f"cavity {n}x{n}, physics of the 8192x8192 case"
+        # cavity of the 8192^2 physics at another size (sq<n> square, sq<nx>x<ny>)
+        dims = [int(v) for v in name[2:].split("x")]
+        nx, ny = dims[0], dims[-1]
+        p = W.scaled_cavity(W.case_c3()[0], nx, ny)
+        return [p], 0, "f32", f"cavity {nx}x{ny}, physics of the 8192x8192 case"
     if name == "c5":
         ps, _, seed, prec = W.case_c5()
         return ps, seed, prec, "256 cavities, sides log-U[64,512] (seed 7), 24198641 nodes"
@@ -152,7 +153,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3",
-                    help="c2, c3 (default), c4, c5, sq<n> for an n x n cavity, bat<k>x<n> for k of them")
+                    help="c2, c3 (default), c4, c5, sq<n> for an n x n cavity (sq<nx>x<ny>), bat<k>x<n> for k of them")
     ap.add_argument("--precision", default=None, choices=[None] + list(BYTES_PER_NODE))
     ap.add_argument("--thermal-lattice", type=int, default=9, choices=[9, 5],
                     help="9: D2Q9 thermal fields (the paper's main method); 5: D2Q5 (Appendix B)")

@@ -87,7 +87,8 @@ typedef enum {
  * dx = dt = 1, c_s^2 = 1/3, rho_l = rho_s = 1, c_pl = c_ps = c_pm = 1
  * (Sec. IV parameter list).  Optional fields use the stated sentinel. */
 typedef struct lbm_params {
-    int32_t nx, ny;       /* nodes including the wall nodes, each >= 4          */
+    int32_t nx, ny;       /* nodes including the wall nodes, each >= 4;
+                             nx <= 4194304, nx * ny <= 2^31                  */
     int32_t bc_x;         /* 0: cavity (hot wall x=0, cold wall x=nx-1);
                              1: periodic in x, walls only at y=0 and y=ny-1      */
     int32_t gravity_axis; /* 1: gravity along -y; 0: along -x                    */
@@ -226,10 +227,13 @@ lbm_status lbm_set_initial(lbm_handle *h, int32_t cavity, const double *T_pcm0,
                            const double *T_mf0);
 
 /* Advance every cavity by n >= 0 steps (asynchronous).  Each step is one
- * launch of the fused kernel: streaming, wall reconstruction (Eq. 52),
+ * launch of the fused kernel (or one launch per two steps, see
+ * lbm_launch_config): streaming, wall reconstruction (Eq. 52),
  * enthalpy/temperature/liquid fraction (Eqs. 37-39, 48), volumetric blend
  * (Eq. 20), velocity (Eqs. 23-25), the three moment-space collisions
- * (Eqs. 14, 32, 43) and the wall energy/mass flux tallies. */
+ * (Eqs. 14, 32, 43) and the wall energy/mass flux tallies.  Runs of 32
+ * launches go out as HIP graphs, captured when the handle is created and
+ * on every lbm_set_launch, so a call spends no host time on capture. */
 lbm_status lbm_step(lbm_handle *h, int64_t n);
 
 /* Batched handles only: the same n steps as one launch per cavity per step

@@ -79,6 +79,9 @@ double char_length(const lbm_params &p) {
 
 lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     if (p.nx < 4 || p.ny < 4) return fail(LBM_EINVAL, "grid %dx%d: each side needs >= 4 nodes", p.nx, p.ny);
+    // the step kernels address a tile's rows by 32-bit byte offsets from its
+    // first row: a few dozen rows of 8-byte elements must stay below 2^31
+    if (p.nx > LBM_MAX_NX) return fail(LBM_EINVAL, "grid %dx%d: rows longer than %d nodes", p.nx, p.ny, LBM_MAX_NX);
     if ((int64_t)p.nx * p.ny > (int64_t)1 << 31)
         return fail(LBM_EINVAL, "cavity of %dx%d nodes exceeds 2^31 nodes", p.nx, p.ny);
     if (p.bc_x != 0 && p.bc_x != 1) return fail(LBM_EINVAL, "bc_x must be 0 or 1");
@@ -422,6 +425,11 @@ int64_t count_tiles2(int nx, int ny, int tw, int th) {
     return (int64_t)xs.size() * (int64_t)ys.size();
 }
 
+// Nodes added to every population plane beyond the 128-node rounding.
+#ifndef LBM_PLANE_PAD
+#define LBM_PLANE_PAD 0
+#endif
+
 // Memory plan shared by lbm_workspace_bytes and the create calls.
 struct Plan {
     int st = -1;  // storage form (precision and thermal lattice)
@@ -461,15 +469,14 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
         pl.slots += 2 * ((int64_t)p[c].nx + p[c].ny);
         pl.max_nodes = std::max(pl.max_nodes, nn);
         // interior rows and the wall ring, in tiles of at least 64 nodes
-        const int64_t ring = 2 * (int64_t)p[c].nx;
-        tiles += ((int64_t)p[c].nx * (p[c].ny - 2) + 63) / 64 + 1 + (ring + 63) / 64;
+        tiles += ((int64_t)p[c].nx * (p[c].ny - 2) + 63) / 64 + 1 + 2 * (((int64_t)p[c].nx + 63) / 64);
     }
     if (pl.nodes >= ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "more than 2^31 nodes in total");
     if (tiles >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
     pl.max_tiles = (int)tiles;
     pl.st = storage_of(prec, qt0);
     const int st = pl.st;
-    pl.stride = (pl.nodes + 127) & ~(int64_t)127;
+    pl.stride = ((pl.nodes + 127) & ~(int64_t)127) + LBM_PLANE_PAD;
     size_t off = 0;
     for (int b = 0; b < 2; ++b) {
         pl.off_pop[b] = off;
@@ -582,12 +589,14 @@ lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
     for (int c = 0; c < h->n; ++c) {
         h->cav_tile0[c] = (int)h->tiles.size();
         const int nx = h->params[c].nx, ny = h->params[c].ny;
-        const int ring = 2 * nx;  // bottom and top rows
         // interior tiles start on 64-node boundaries of the cavity (which is
         // 64-aligned in the packed index); lanes on row 0 idle
         for (int k0 = (nx / 64) * 64; k0 < nx * (ny - 1); k0 += tw)
             h->tiles.push_back(Tile{c, TILE_INTERIOR, k0, std::min(nx * (ny - 1), k0 + tw)});
-        for (int r0 = 0; r0 < ring; r0 += tw) h->tiles.push_back(Tile{c, TILE_WALL, r0, std::min(ring, r0 + tw)});
+        // wall tiles hold nodes of one row (the bottom or the top)
+        for (int row = 0; row < 2; ++row)
+            for (int r0 = row * nx; r0 < (row + 1) * nx; r0 += tw)
+                h->tiles.push_back(Tile{c, TILE_WALL, r0, std::min((row + 1) * nx, r0 + tw)});
         h->cav_ntiles[c] = (int)h->tiles.size() - h->cav_tile0[c];
     }
     if ((int)h->tiles.size() > h->pl.max_tiles) return fail(LBM_EINVAL, "tile table overflow");
@@ -597,10 +606,11 @@ lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
     return LBM_OK;
 }
 
-bool valid_launch(const lbm_launch_config &lc, int storage) {
+// two_step: the plan has the two-step kernel's tiles
+bool valid_launch(const lbm_launch_config &lc, bool two_step) {
     const bool b = lc.block == 64 || lc.block == 128 || lc.block == 256 || lc.block == 512;
     const bool n = lc.nodes_per_thread == 1 || lc.nodes_per_thread == 2 || lc.nodes_per_thread == 4;
-    const bool t = lc.steps_per_launch == 1 || (lc.steps_per_launch == 2 && step2_supported(storage));
+    const bool t = lc.steps_per_launch == 1 || (lc.steps_per_launch == 2 && two_step);
     return b && n && t && (lc.xcd_remap == 0 || lc.xcd_remap == 1) && lc.persistent >= 0 && lc.persistent <= 64;
 }
 
@@ -674,6 +684,19 @@ lbm_status build_graph(lbm_handle *h, int parity, bool two) {
     hipGraphExec_t *ex = two ? &h->graph2[parity] : &h->graph[parity];
     HIP_TRY(hipStreamEndCapture(h->cap, src));
     HIP_TRY(hipGraphInstantiate(ex, *src, nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+// Capture both parities' graphs of the current launch mode now (creation and
+// every change of launch shape), so that no lbm_step spends host time on
+// capture and instantiation while the device waits.
+lbm_status prepare_graphs(lbm_handle *h) {
+    const bool two = h->lc.steps_per_launch == 2;
+    for (int parity = 0; parity < 2; ++parity) {
+        if (two ? h->graph2[parity] : h->graph[parity]) continue;
+        lbm_status s = build_graph(h, parity, two);
+        if (s != LBM_OK) return s;
+    }
     return LBM_OK;
 }
 
@@ -772,7 +795,7 @@ lbm_status setup(lbm_handle *h) {
     // aligned or at least 1024 nodes wide.  Batches of narrow, unaligned
     // cavities (a tile row then writes partial cache lines shared with its
     // neighbour) stay at one step per launch.
-    bool two = step2_supported(h->st) && h->st != ST_F64;
+    bool two = h->pl.tiles2 > 0 && h->st != ST_F64;
     for (int c = 0; c < h->n; ++c)
         if (!(h->params[c].nx % 32 == 0 || h->params[c].nx >= 1024)) two = false;
     h->lc.steps_per_launch = two ? 2 : 1;
@@ -786,7 +809,7 @@ lbm_status setup(lbm_handle *h) {
         s = init_cavity(h, c, nullptr, nullptr);
         if (s != LBM_OK) return s;
     }
-    return LBM_OK;
+    return prepare_graphs(h);
 }
 
 lbm_status create_common(const lbm_params *p, int n, lbm_precision prec, void *ws, uint64_t ws_bytes,
@@ -1086,7 +1109,7 @@ extern "C" lbm_status lbm_get_launch(const lbm_handle *h, lbm_launch_config *out
 
 extern "C" lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg) {
     if (!h || !cfg) return fail(LBM_EINVAL, "NULL argument");
-    if (!valid_launch(*cfg, h->st))
+    if (!valid_launch(*cfg, h->pl.tiles2 > 0))
         return fail(LBM_EINVAL, "unsupported launch shape block=%d npt=%d xcd=%d persistent=%d steps=%d",
                     cfg->block, cfg->nodes_per_thread, cfg->xcd_remap, cfg->persistent, cfg->steps_per_launch);
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1094,7 +1117,7 @@ extern "C" lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg
     if (s != LBM_OK) return s;
     h->lc = *cfg;
     drop_graphs(h);
-    return LBM_OK;
+    return prepare_graphs(h);
 }
 
 namespace {
@@ -1123,7 +1146,7 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
             lbm_launch_config lc;
             while (fscanf(f, "%255s %d %d %d %d %d", k, &lc.block, &lc.nodes_per_thread, &lc.xcd_remap,
                           &lc.persistent, &lc.steps_per_launch) == 6) {
-                if (key == k && valid_launch(lc, h->st)) {
+                if (key == k && valid_launch(lc, h->pl.tiles2 > 0)) {
                     fclose(f);
                     lbm_status s = lbm_set_launch(h, &lc);
                     if (s == LBM_OK && chosen) *chosen = lc;
@@ -1179,7 +1202,7 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
                         best = lc;
                     }
                 }
-    if (step2_supported(h->st)) {
+    if (h->pl.tiles2 > 0) {
         const lbm_launch_config one = best;
         for (int xr : xcds)
             for (int pp : pers) {

@@ -16,6 +16,11 @@ enum Storage {
 
 enum Wall { W_LEFT = 0, W_RIGHT = 1, W_BOTTOM = 2, W_TOP = 3 };
 
+// Longest cavity row.  The step kernels address the rows a tile touches
+// (at most 2048 + 3 nx nodes, or TH + 4 rows of the two-step tiles) by
+// 32-bit byte offsets of up to 8-byte elements from the tile's first row.
+#define LBM_MAX_NX 4194304
+
 // Constants of the PCM enthalpy field, kept in both arithmetic types (the
 // mixed storage form runs this field in FP64 and the others in FP32).
 template <typename T>
@@ -67,8 +72,8 @@ struct CavityConst {
 // A tile is a run [k0, k1) of one cavity's nodes.  Row tiles (kind 0)
 // index the rows 1..ny-2 linearly, k = y * nx + x, and start on 64-node
 // boundaries (lanes of row 0 idle); the wall columns are part of their
-// rows.  Wall tiles (kind 1) index the bottom and top rows, r in [0, 2 nx).
-// Tiles never straddle cavities.
+// rows.  Wall tiles (kind 1) index the bottom and top rows, r in [0, 2 nx),
+// each tile within one of the two.  Tiles never straddle cavities.
 enum { TILE_INTERIOR = 0, TILE_WALL = 1 };
 struct Tile {
     int32_t cav, kind, k0, k1;

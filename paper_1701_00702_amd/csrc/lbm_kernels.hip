@@ -72,7 +72,49 @@ __device__ __forceinline__ int remap_block(int b, int grid, int xcd_remap) {
     return (b & 7) * per + (b >> 3);
 }
 
+// The tile of one workgroup.  Accesses are 32-bit offsets from a row the
+// workgroup shares: for interior tiles the row before their first one (the
+// pulls reach one row either side), for wall tiles (one row each) the first
+// of the three rows their wall partners pull from.  Both kinds share one
+// instantiation of the node update (decided per node), so the kernel holds
+// a single copy of the global accesses.
 template <class Lay, typename R, typename RH, bool PULL, int NPT>
+__device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__restrict__ dst, int64_t stride,
+                                          const R *__restrict__ sr_src, R *__restrict__ sr_dst,
+                                          double *__restrict__ acc, const CavityConst<R> *__restrict__ cav,
+                                          const Tile &tl) {
+    const CavityConst<R> &c = cav[tl.cav];
+    const bool wall = tl.kind != TILE_INTERIOR;
+    int yb;
+    if (wall) {
+        yb = tl.k0 < c.nx ? 0 : c.ny - 3;
+    } else {
+        const int y0 = tl.k0 / c.nx;
+        yb = y0 >= 1 ? y0 - 1 : 0;
+    }
+    const RowOrigin org{c.node0 + (int64_t)yb * c.nx, yb, c.nx};
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int k = tl.k0 + (int)threadIdx.x + j * (int)blockDim.x;
+        if (k < tl.k1) {
+            int x, y;
+            if (wall) {
+                ring_node(c, k, x, y);
+            } else {
+                y = k / c.nx;
+                x = k - y * c.nx;
+            }
+            // interior tiles cover whole rows: the wall columns ride along
+            // (each stored cache line then has one writer); lanes on row 0 idle
+            if (wall || y >= 1)
+                step_node_at<Lay, R, RH, PULL, NODE_ANY>(c, src, dst, stride, sr_src, sr_dst, acc, x, y, org);
+        }
+    }
+}
+
+// One tile per workgroup, or (LOOP) a grid-stride walk over the tiles for
+// the persistent launch.
+template <class Lay, typename R, typename RH, bool PULL, int NPT, bool LOOP>
 __global__ __launch_bounds__(512) void step_kernel(const void *__restrict__ src, void *__restrict__ dst,
                                                    int64_t stride, const R *__restrict__ sr_src,
                                                    R *__restrict__ sr_dst, double *__restrict__ acc,
@@ -80,32 +122,12 @@ __global__ __launch_bounds__(512) void step_kernel(const void *__restrict__ src,
                                                    const Tile *__restrict__ tiles, int ntiles,
                                                    int xcd_remap) {
     const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
-    for (int t = b; t < ntiles; t += gridDim.x) {
-        const Tile tl = tiles[t];
-        const CavityConst<R> &c = cav[tl.cav];
-        if (tl.kind == TILE_INTERIOR) {
-#pragma unroll
-            for (int j = 0; j < NPT; ++j) {
-                const int k = tl.k0 + (int)threadIdx.x + j * (int)blockDim.x;
-                if (k < tl.k1) {
-                    const int y = k / c.nx, x = k - y * c.nx;
-                    // whole rows: the wall columns ride along (each stored
-                    // cache line then has one writer)
-                    if (y >= 1) step_node<Lay, R, RH, PULL, NODE_ANY>(c, src, dst, stride, sr_src, sr_dst, acc, x, y);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < NPT; ++j) {
-                const int r = tl.k0 + (int)threadIdx.x + j * (int)blockDim.x;
-                if (r < tl.k1) {
-                    int x, y;
-                    ring_node(c, r, x, y);
-                    step_node<Lay, R, RH, PULL, NODE_WALL>(c, src, dst, stride, sr_src, sr_dst, acc, x, y);
-                }
-            }
-        }
+    if (!LOOP) {
+        if (b < ntiles) step_tile<Lay, R, RH, PULL, NPT>(src, dst, stride, sr_src, sr_dst, acc, cav, tiles[b]);
+        return;
     }
+    for (int t = b; t < ntiles; t += gridDim.x)
+        step_tile<Lay, R, RH, PULL, NPT>(src, dst, stride, sr_src, sr_dst, acc, cav, tiles[t]);
 }
 
 template <int ST, bool PULL, int NPT>
@@ -113,9 +135,14 @@ static hipError_t launch_step_t(const StepLaunch &L, hipStream_t s) {
     using Lay = typename LayoutOf<ST>::L;
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
-    hipLaunchKernelGGL((step_kernel<Lay, R, RH, PULL, NPT>), dim3(L.grid), dim3(L.block), 0, s, L.src, L.dst,
-                       L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
-                       (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
+    if (L.grid >= L.ntiles)
+        hipLaunchKernelGGL((step_kernel<Lay, R, RH, PULL, NPT, false>), dim3(L.grid), dim3(L.block), 0, s, L.src,
+                           L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                           (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
+    else
+        hipLaunchKernelGGL((step_kernel<Lay, R, RH, PULL, NPT, true>), dim3(L.grid), dim3(L.block), 0, s, L.src,
+                           L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                           (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     return hipGetLastError();
 }
 
@@ -186,7 +213,25 @@ struct Step2Tile<ST5_F64> {  // 19 x 8 + 8 = 160 B per slot, 18 x 22 slots
     static constexpr int TW = 16, TH = 20, NT = 448;
 };
 
+// One tile per workgroup, or (LOOP) a grid-stride walk over the tiles for
+// the persistent launch.  Without the loop nothing in the tile's code is
+// loop-invariant, so the compiler does not keep the 27 plane addresses live
+// across iterations (they would spill to vector registers).
 template <class Lay, typename R, typename RH, int TW, int TH, int NT>
+__device__ __forceinline__ void step2_advance(const void *__restrict__ src, void *__restrict__ dst,
+                                              int64_t stride, const R *__restrict__ sr_src,
+                                              R *__restrict__ sr_dst, double *__restrict__ acc,
+                                              const CavityConst<R> *__restrict__ cav, const Tile2 &tl,
+                                              void *lds_q, R *lds_sr) {
+    const CavityConst<R> &c = cav[tl.cav];
+    // NT >= NSLOT: each thread advances at most one slot per update
+    const int s = (int)threadIdx.x;
+    if (s < (TW + 2) * (tl.h + 2)) step2_phase1<Lay, R, RH, TW, TH>(c, tl, src, stride, sr_src, acc, lds_q, lds_sr, s);
+    __syncthreads();
+    if (s < TW * tl.h) step2_phase2<Lay, R, RH, TW, TH>(c, tl, dst, stride, sr_dst, acc, lds_q, lds_sr, s);
+}
+
+template <class Lay, typename R, typename RH, int TW, int TH, int NT, bool LOOP>
 __global__ __launch_bounds__(NT) void step2_kernel(const void *__restrict__ src, void *__restrict__ dst,
                                                    int64_t stride, const R *__restrict__ sr_src,
                                                    R *__restrict__ sr_dst, double *__restrict__ acc,
@@ -198,16 +243,13 @@ __global__ __launch_bounds__(NT) void step2_kernel(const void *__restrict__ src,
     __shared__ __align__(16) unsigned char lds_q[Sh::LDS_BYTES];
     __shared__ R lds_sr[Sh::NSLOT];
     const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
+    if (!LOOP) {
+        if (b < ntiles)
+            step2_advance<Lay, R, RH, TW, TH, NT>(src, dst, stride, sr_src, sr_dst, acc, cav, tiles[b], lds_q, lds_sr);
+        return;
+    }
     for (int t = b; t < ntiles; t += gridDim.x) {
-        const Tile2 tl = tiles[t];
-        const CavityConst<R> &c = cav[tl.cav];
-        const int n1 = (TW + 2) * (tl.h + 2);
-        for (int s = (int)threadIdx.x; s < n1; s += NT)
-            step2_phase1<Lay, R, RH, TW, TH>(c, tl, src, stride, sr_src, acc, lds_q, lds_sr, s);
-        __syncthreads();
-        const int n2 = TW * tl.h;
-        for (int n = (int)threadIdx.x; n < n2; n += NT)
-            step2_phase2<Lay, R, RH, TW, TH>(c, tl, dst, stride, sr_dst, acc, lds_q, lds_sr, n);
+        step2_advance<Lay, R, RH, TW, TH, NT>(src, dst, stride, sr_src, sr_dst, acc, cav, tiles[t], lds_q, lds_sr);
         __syncthreads();  // the next tile reuses the LDS
     }
 }
@@ -218,9 +260,14 @@ static hipError_t launch_step2_s(const Step2Launch &L, hipStream_t s) {
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
     using Tl = Step2Tile<ST>;
-    hipLaunchKernelGGL((step2_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT>), dim3(L.grid), dim3(Tl::NT), 0, s,
-                       L.src, L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
-                       (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
+    if (L.grid >= L.ntiles)
+        hipLaunchKernelGGL((step2_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, false>), dim3(L.grid), dim3(Tl::NT),
+                           0, s, L.src, L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                           (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
+    else
+        hipLaunchKernelGGL((step2_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, true>), dim3(L.grid), dim3(Tl::NT),
+                           0, s, L.src, L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                           (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     return hipGetLastError();
 }
 

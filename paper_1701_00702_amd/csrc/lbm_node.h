@@ -30,6 +30,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "lbm_internal.h"
 
 #define LBM_HD __host__ __device__ __forceinline__
@@ -72,6 +74,19 @@ LBM_HD float sqrt_of<float>(float x) {
     return __builtin_amdgcn_sqrtf(x);
 }
 #endif
+
+// Fused multiply-add, rounded once.  The library is built without automatic
+// contraction, so each fusion is written out here and every instantiation
+// of the update rounds the same way.  With a power-of-two factor the fused
+// form gives the same bits as the separate product and sum.
+template <typename R>
+LBM_HD R fma_of(R a, R b, R c) {
+    return fma(a, b, c);
+}
+template <>
+LBM_HD float fma_of<float>(float a, float b, float c) {
+    return fmaf(a, b, c);
+}
 
 // Enthalpy-field constants in the enthalpy arithmetic type.
 template <typename RH>
@@ -119,6 +134,51 @@ LBM_HD void st_stream(T *p, T v) {
 #endif
 }
 
+// A node's place in a population plane: a packed node index (int64_t), or
+// an origin k0 that is the same for the whole wavefront plus a 32-bit
+// offset rel (NodeRef).  With the second form the address of each plane at
+// the origin is held in scalar registers (the empty asm keeps the compiler
+// from regrouping the sum into a per-lane 64-bit base plus plane offsets)
+// and an access is that scalar base plus a 32-bit vector offset; the
+// caller keeps rel times the element size below 2^31.
+struct NodeRef {
+    int64_t k0;
+    uint32_t rel;
+};
+template <typename T>
+LBM_HD T *at(T *plane, int64_t k) {
+    return plane + k;
+}
+template <typename T>
+LBM_HD T *at(T *plane, NodeRef r) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    T *b = plane + r.k0;
+#if defined(__HIP_DEVICE_COMPILE__)
+    __attribute__((address_space(1))) T *gb = (__attribute__((address_space(1))) T *)b;  // global memory
+    asm("" : "+s"(gb));
+    b = (T *)gb;
+#endif
+    return (T *)((B *)b + r.rel * (uint32_t)sizeof(T));
+}
+// The address of a store of v to plane p (of stride elements) from base:
+// as at(), with the plane's scalar base formed from a copy of the stride
+// that depends on v.  The bases are then computed next to the stores, not
+// shared with the loads' and held in scalar registers across the update.
+template <typename T, typename V>
+LBM_HD T *at_store(T *base, int p, int64_t stride, int64_t k, V v) {
+    (void)v;
+    return base + (int64_t)p * stride + k;
+}
+template <typename T, typename V>
+LBM_HD T *at_store(T *base, int p, int64_t stride, NodeRef r, V v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm("" : "+s"(stride) : "v"(v));
+#else
+    (void)v;
+#endif
+    return at(base + (int64_t)p * stride, r);
+}
+
 struct E64 {
     using T = double;
     LBM_HD static double dec(double v) { return v; }
@@ -161,21 +221,23 @@ struct Plain {
     static constexpr int QT = QT_;
     static constexpr int bytes_per_node = (9 + 2 * QT) * (int)sizeof(T);
     LBM_HD static int plane(int f, int i) { return f == 0 ? i : 9 + (f - 1) * QT + i; }
-    template <typename V, typename R>
-    LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
-        const T *p = (const T *)base + (int64_t)plane(f, i) * stride + k;
+    template <typename V, typename R, typename K>
+    LBM_HD static V load(const void *base, int64_t stride, int f, int i, K k, const CavityConst<R> &c) {
+        const T *p = at((const T *)base + (int64_t)plane(f, i) * stride, k);
         const V v = (V)E::dec(ld_stream(p));
         return SCALED ? v * (V)c.inv_scale[f] : v;
     }
-    template <typename V, typename R>
-    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, int64_t k,
+    template <typename V, typename R, typename K>
+    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, K k,
                              const CavityConst<R> &c) {
         (void)beta;
-        T *p = (T *)base + (int64_t)plane(f, 0) * stride + k;
         const int n = f == 0 ? 9 : QT;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            if (i < n) st_stream(p + (int64_t)i * stride, E::enc((C)(SCALED ? q[i] * (V)c.scale[f] : q[i])));
+            if (i < n) {
+                const T e = E::enc((C)(SCALED ? q[i] * (V)c.scale[f] : q[i]));
+                st_stream(at_store((T *)base, plane(f, i), stride, k, e), e);
+            }
     }
 };
 
@@ -188,14 +250,14 @@ struct PlainH64 {
     static constexpr int NF32 = 8 + 2 * QT;
     static constexpr int bytes_per_node = NF32 * 4 + 8;
     LBM_HD static int plane(int f, int i) { return f == 0 ? i : (f == 1 ? 8 + i : 8 + QT + i); }
-    template <typename V, typename R>
-    LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
+    template <typename V, typename R, typename K>
+    LBM_HD static V load(const void *base, int64_t stride, int f, int i, K k, const CavityConst<R> &c) {
         (void)c;
-        if (f == 1 && i == 0) return (V)ld_stream((const double *)((const float *)base + NF32 * stride) + k);
-        return (V)ld_stream((const float *)base + (int64_t)plane(f, i) * stride + k);
+        if (f == 1 && i == 0) return (V)ld_stream(at((const double *)((const float *)base + NF32 * stride), k));
+        return (V)ld_stream(at((const float *)base + (int64_t)plane(f, i) * stride, k));
     }
-    template <typename V, typename R>
-    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, int64_t k,
+    template <typename V, typename R, typename K>
+    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, K k,
                              const CavityConst<R> &c) {
         (void)beta;
         (void)c;
@@ -203,8 +265,13 @@ struct PlainH64 {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             if (i >= n) continue;
-            if (f == 1 && i == 0) st_stream((double *)((float *)base + NF32 * stride) + k, (double)q[0]);
-            else st_stream((float *)base + (int64_t)plane(f, i) * stride + k, (float)q[i]);
+            if (f == 1 && i == 0) {
+                const double e = (double)q[0];
+                st_stream(at_store((double *)((float *)base + NF32 * stride), 0, stride, k, e), e);
+            } else {
+                const float e = (float)q[i];
+                st_stream(at_store((float *)base, plane(f, i), stride, k, e), e);
+            }
         }
     }
 };
@@ -221,26 +288,28 @@ struct PlainH64 {
 struct Split16 {
     static constexpr int QT = 9;
     static constexpr int bytes_per_node = 6 * 4 + 24 * 2;
-    template <typename V, typename R>
-    LBM_HD static V load(const void *base, int64_t stride, int f, int i, int64_t k, const CavityConst<R> &c) {
+    template <typename V, typename R, typename K>
+    LBM_HD static V load(const void *base, int64_t stride, int f, int i, K k, const CavityConst<R> &c) {
         const float *P = (const float *)base;
-        if (i == 0) return (V)ld_stream(P + (int64_t)(2 * f) * stride + k);
-        const V beta = (V)ld_stream(P + (int64_t)(2 * f + 1) * stride + k);
+        if (i == 0) return (V)ld_stream(at(P + (int64_t)(2 * f) * stride, k));
+        const V beta = (V)ld_stream(at(P + (int64_t)(2 * f + 1) * stride, k));
         const uint16_t *Qp = (const uint16_t *)(P + 6 * stride);
-        const V r = (V)E16::dec(ld_stream(Qp + (int64_t)(8 * f + i - 1) * stride + k));
+        const V r = (V)E16::dec(ld_stream(at(Qp + (int64_t)(8 * f + i - 1) * stride, k)));
         return w_of<V>(i) * beta + r * (V)c.inv_scale[f];
     }
-    template <typename V, typename R>
-    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, int64_t k,
+    template <typename V, typename R, typename K>
+    LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, K k,
                              const CavityConst<R> &c) {
         float *P = (float *)base;
-        st_stream(P + (int64_t)(2 * f) * stride + k, (float)q[0]);
-        st_stream(P + (int64_t)(2 * f + 1) * stride + k, (float)beta);
+        const float e0 = (float)q[0], eb = (float)beta;
+        st_stream(at_store(P, 2 * f, stride, k, e0), e0);
+        st_stream(at_store(P, 2 * f + 1, stride, k, eb), eb);
         uint16_t *Qp = (uint16_t *)(P + 6 * stride);
 #pragma unroll
-        for (int i = 1; i < 9; ++i)
-            st_stream(Qp + (int64_t)(8 * f + i - 1) * stride + k,
-                      E16::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f])));
+        for (int i = 1; i < 9; ++i) {
+            const uint16_t e = E16::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f]));
+            st_stream(at_store(Qp, 8 * f + i - 1, stride, k, e), e);
+        }
     }
 };
 
@@ -311,14 +380,14 @@ LBM_HD void to_moments(const R q[9], R d[9]) {
     const R s14 = (q[1] + q[2]) + (q[3] + q[4]);
     const R s58 = (q[5] + q[6]) + (q[7] + q[8]);
     d[0] = q[0] + s14 + s58;
-    d[1] = -R(4) * q[0] - s14 + R(2) * s58;
-    d[2] = R(4) * q[0] - R(2) * s14 + s58;
+    d[1] = fma_of(R(2), s58, fma_of(R(-4), q[0], -s14));
+    d[2] = fma_of(R(-2), s14, R(4) * q[0]) + s58;
     const R dxd = (q[5] - q[6]) - (q[7] - q[8]);
     const R dyd = (q[5] + q[6]) - (q[7] + q[8]);
     d[3] = (q[1] - q[3]) + dxd;
-    d[4] = R(2) * (q[3] - q[1]) + dxd;
+    d[4] = fma_of(R(2), q[3] - q[1], dxd);
     d[5] = (q[2] - q[4]) + dyd;
-    d[6] = R(2) * (q[4] - q[2]) + dyd;
+    d[6] = fma_of(R(2), q[4] - q[2], dyd);
     d[7] = (q[1] + q[3]) - (q[2] + q[4]);
     d[8] = (q[5] + q[7]) - (q[6] + q[8]);
 }
@@ -334,11 +403,11 @@ LBM_HD void from_moments(const R d[9], R q[9]) {
     const R a6 = d[6] * (R(1) / R(12));
     const R a7 = d[7] * R(0.25);
     const R a8 = d[8] * R(0.25);
-    const R axis = a0 - a1 - R(2) * a2;
-    const R diag = a0 + R(2) * a1 + a2;
-    const R xa = a3 - R(2) * a4, ya = a5 - R(2) * a6;
+    const R axis = fma_of(R(-2), a2, a0 - a1);
+    const R diag = fma_of(R(2), a1, a0) + a2;
+    const R xa = fma_of(R(-2), a4, a3), ya = fma_of(R(-2), a6, a5);
     const R xd = a3 + a4, yd = a5 + a6;
-    q[0] = a0 - R(4) * a1 + R(4) * a2;
+    q[0] = fma_of(R(4), a2, fma_of(R(-4), a1, a0));
     q[1] = axis + xa + a7;
     q[2] = axis + ya - a7;
     q[3] = axis - xa + a7;
@@ -393,7 +462,7 @@ struct Thermo {  // PCM enthalpy field, Eqs. (37)-(39)
 };
 template <typename R>
 struct Macro {  // everything the flow and metal collisions need
-    R Tf, fl, dTm, Tm, drho, rho, ux, uy, Gx, Gy;
+    R Tf, fl, dTm, Tm, drho, rho, ux, uy, umag, Gx, Gy;
 };
 
 // Eqs. (38)-(39), branches in the order the paper lists them.
@@ -433,7 +502,7 @@ LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[
     if (!c.bounce_back) {
         const R sol = (R(1) - m.fl) * m.drho;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) qf[i] = m.fl * qf[i] + w_of<R>(i) * sol;
+        for (int i = 0; i < 9; ++i) qf[i] = fma_of(m.fl, qf[i], w_of<R>(i) * sol);
     }
     // Eq. (7): buoyancy along +axis (gravity along -axis).
     const R G = c.gbeta * (m.Tf - c.T0) * m.fl;
@@ -443,16 +512,18 @@ LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[
     const R jx = (qf[1] - qf[3]) + ((qf[5] - qf[6]) - (qf[7] - qf[8]));
     const R jy = (qf[2] - qf[4]) + ((qf[5] + qf[6]) - (qf[7] + qf[8]));
     const R inv_rho = rcp_of(m.rho);
-    const R vx = jx * inv_rho + R(0.5) * c.phi * m.Gx;
-    const R vy = jy * inv_rho + R(0.5) * c.phi * m.Gy;
-    const R vmag = sqrt_of(vx * vx + vy * vy);
-    const R inv_den = rcp_of(c.l0 + sqrt_of(c.l0sq + c.l1 * vmag));
+    const R vx = fma_of(jx, inv_rho, R(0.5) * c.phi * m.Gx);
+    const R vy = fma_of(jy, inv_rho, R(0.5) * c.phi * m.Gy);
+    const R vmag = sqrt_of(fma_of(vx, vx, vy * vy));
+    const R inv_den = rcp_of(c.l0 + sqrt_of(fma_of(c.l1, vmag, c.l0sq)));
     m.ux = vx * inv_den;
     m.uy = vy * inv_den;
+    m.umag = vmag * inv_den;  // |u| of Eq. (3)
     // bounce-back: below the interface value f_l = 0.5 a node is solid, at rest
     if (c.bounce_back && m.fl < R(0.5)) {
         m.ux = R(0);
         m.uy = R(0);
+        m.umag = R(0);
     }
 }
 
@@ -473,11 +544,11 @@ LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R q[9]) {
     R d[9];
     to_moments(q, d);
     const R ux = m.ux, uy = m.uy, rho = m.rho;
-    const R uu = ux * ux + uy * uy;
-    const R umag = sqrt_of(uu);
-    // Eq. (3).
-    const R Fx = -c.drag_lin * ux - c.drag_quad * umag * ux + c.phi * m.Gx;
-    const R Fy = -c.drag_lin * uy - c.drag_quad * umag * uy + c.phi * m.Gy;
+    const R uu = fma_of(ux, ux, uy * uy);
+    // Eq. (3): F = -(drag_lin + drag_quad |u|) u + phi G
+    const R drag = fma_of(c.drag_quad, m.umag, c.drag_lin);
+    const R Fx = fma_of(-drag, ux, c.phi * m.Gx);
+    const R Fy = fma_of(-drag, uy, c.phi * m.Gy);
     const R rip = rho * c.inv_phi;
     R eq[9], S[9];
     eq[1] = -R(2) * m.drho + R(3) * rip * uu;
@@ -499,7 +570,7 @@ LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R q[9]) {
     S[8] = rip * (ux * Fy + uy * Fx);
     d[0] = m.drho;
 #pragma unroll
-    for (int k = 1; k < 9; ++k) d[k] = d[k] - c.s[k] * (d[k] - eq[k]) + c.s_half[k] * S[k];
+    for (int k = 1; k < 9; ++k) d[k] = fma_of(c.s_half[k], S[k], fma_of(-c.s[k], d[k] - eq[k], d[k]));
     from_moments(d, q);
 }
 
@@ -523,9 +594,9 @@ LBM_HD void collide_pcm(const CavityConst<R> &c, const Thermo<RH> &th, const Mac
     eq[7] = RH(0);
     eq[8] = RH(0);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = d[k] - t.zeta[k] * (d[k] - eq[k]);
+    for (int k = 0; k < 9; ++k) d[k] = fma_of(-t.zeta[k], d[k] - eq[k], d[k]);
     d[0] += S_pcm;
-    d[1] -= RH(2) * S_pcm;
+    d[1] = fma_of(RH(-2), S_pcm, d[1]);
     d[2] += S_pcm;
     from_moments(d, q);
 }
@@ -542,9 +613,9 @@ LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal,
 #pragma unroll
     for (int k = 3; k < 9; ++k) eq[k] = R(0);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = d[k] - c.eta[k] * (d[k] - eq[k]);
+    for (int k = 0; k < 9; ++k) d[k] = fma_of(-c.eta[k], d[k] - eq[k], d[k]);
     d[0] += S_metal;
-    d[1] -= R(2) * S_metal;
+    d[1] = fma_of(R(-2), S_metal, d[1]);
     d[2] += S_metal;
     from_moments(d, q);
 }
@@ -565,9 +636,9 @@ LBM_HD void collide_pcm5(const CavityConst<R> &c, const Thermo<RH> &th, const Ma
     eq[3] = t.varpi * t.c_fref * (th.Tf - t.T_ref);
     eq[4] = RH(0);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) d[k] = d[k] - t.zeta[k] * (d[k] - eq[k]);
+    for (int k = 0; k < 5; ++k) d[k] = fma_of(-t.zeta[k], d[k] - eq[k], d[k]);
     d[0] += S_pcm;
-    d[3] += t.varpi * S_pcm;
+    d[3] = fma_of(t.varpi, S_pcm, d[3]);
     from_moments5(d, q);
 }
 
@@ -583,9 +654,9 @@ LBM_HD void collide_metal5(const CavityConst<R> &c, const Macro<R> &m, R S_metal
     eq[3] = c.varpi * c.c_mref * m.dTm;
     eq[4] = R(0);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) d[k] = d[k] - c.eta[k] * (d[k] - eq[k]);
+    for (int k = 0; k < 5; ++k) d[k] = fma_of(-c.eta[k], d[k] - eq[k], d[k]);
     d[0] += S_metal;
-    d[3] += c.varpi * S_metal;
+    d[3] = fma_of(c.varpi, S_metal, d[3]);
     from_moments5(d, q);
 }
 
@@ -708,21 +779,36 @@ LBM_HD void ring_node(const CavityConst<R> &c, int r, int &x, int &y) {
     }
 }
 
+// Where node (x, y) of a cavity sits in the planes: its packed index, or
+// (RowOrigin) an offset from the start of row yb, whose packed index k0 is
+// uniform across the workgroup; rows yb .. yb + span of the cavity must fit
+// the 32-bit offset (checked on the host).
+struct PackedIndex {
+    int64_t node0;
+    int nx;
+    LBM_HD int64_t operator()(int x, int y) const { return node0 + (int64_t)y * nx + x; }
+};
+struct RowOrigin {
+    int64_t k0;
+    int yb, nx;
+    LBM_HD NodeRef operator()(int x, int y) const { return NodeRef{k0, (uint32_t)((y - yb) * nx + x)}; }
+};
+
 // Offsets of the node's post-streaming populations: pulled from the
 // neighbours (Eqs. 15, 33, 44), or read in place for the initial state.
-template <class Lay, typename R, typename RH, bool PULL>
-LBM_HD void gather(const CavityConst<R> &c, const void *src, int64_t stride, const NodeGeom &g, int x,
-                   int y, R qf[9], RH qg[9], R qh[9]) {
+template <class Lay, typename R, typename RH, bool PULL, class A>
+LBM_HD void gather_at(const CavityConst<R> &c, const void *src, int64_t stride, const NodeGeom &g, int x,
+                      int y, A addr, R qf[9], RH qg[9], R qh[9]) {
     const int nx = c.nx;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        int idx = y * nx + x;
+        int px = x, py = y;
         if (PULL) {
-            int px = g.sx - ex_of(i);
+            px = g.sx - ex_of(i);
             if (c.periodic) px = px < 0 ? px + nx : (px >= nx ? px - nx : px);
-            idx = (g.sy - ey_of(i)) * nx + px;
+            py = g.sy - ey_of(i);
         }
-        const int64_t k = c.node0 + idx;
+        const auto k = addr(px, py);
         qf[i] = Lay::template load<R>(src, stride, 0, i, k, c);
         if (i < Lay::QT) {
             qg[i] = Lay::template load<RH>(src, stride, 1, i, k, c);
@@ -732,6 +818,12 @@ LBM_HD void gather(const CavityConst<R> &c, const void *src, int64_t stride, con
             qh[i] = R(0);
         }
     }
+}
+
+template <class Lay, typename R, typename RH, bool PULL>
+LBM_HD void gather(const CavityConst<R> &c, const void *src, int64_t stride, const NodeGeom &g, int x,
+                   int y, R qf[9], RH qg[9], R qh[9]) {
+    gather_at<Lay, R, RH, PULL>(c, src, stride, g, x, y, PackedIndex{c.node0, c.nx}, qf, qg, qh);
 }
 
 // Energy and mass carried by direction i of the given offsets (FP64);
@@ -831,24 +923,32 @@ LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, 
 
 // One node's full time step.  KIND selects which of the interior and wall
 // code paths this instantiation carries (the caller guarantees the node is
-// of that kind).
-template <class Lay, typename R, typename RH, bool PULL, int KIND = NODE_ANY>
-LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
-                      const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
-                      int x, int y) {
+// of that kind); addr places the node and its neighbours in the planes.
+template <class Lay, typename R, typename RH, bool PULL, int KIND, class A>
+LBM_HD void step_node_at(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
+                         const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
+                         int x, int y, A addr) {
     const NodeGeom g = geometry_of<R, KIND>(c, x, y, PULL);
     R qf[9], qh[9];
     RH qg[9];
-    gather<Lay, R, RH, PULL>(c, src, stride, g, x, y, qf, qg, qh);
-    const int64_t k = c.node0 + (int64_t)y * c.nx + x;
+    gather_at<Lay, R, RH, PULL>(c, src, stride, g, x, y, addr, qf, qg, qh);
+    const auto k = addr(x, y);
     Thermo<RH> th;
     Macro<R> m;
-    const RH srf = update_node<Lay::QT, R, RH, PULL>(c, g, x, y, qf, qg, qh, sr_src[k], true, acc, th, m);
+    const RH srf = update_node<Lay::QT, R, RH, PULL>(c, g, x, y, qf, qg, qh, *at(sr_src, k), true, acc, th, m);
     const ThermalConst<RH> &t = thermal<RH>(c);
     Lay::template store<R>(dst, stride, 0, qf, m.drho, k, c);
     Lay::template store<RH>(dst, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);
     Lay::template store<R>(dst, stride, 2, qh, c.c_mref * m.dTm, k, c);
-    sr_dst[k] = (R)srf;
+    *at(sr_dst, k) = (R)srf;
+}
+
+template <class Lay, typename R, typename RH, bool PULL, int KIND = NODE_ANY>
+LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
+                      const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
+                      int x, int y) {
+    step_node_at<Lay, R, RH, PULL, KIND>(c, src, dst, stride, sr_src, sr_dst, acc, x, y,
+                                         PackedIndex{c.node0, c.nx});
 }
 
 // ---------------------------------------------------------------------------
@@ -925,6 +1025,15 @@ struct Step2Shape {
     static constexpr size_t LDS_BYTES = Codec::bytes(NSLOT);
 };
 
+// Global accesses of a tile go through 32-bit offsets from the first row
+// either update touches, y0 - 2 (the ring's pulls), clipped to the cavity:
+// at most TH + 4 rows (the host enables the kernel only where they fit).
+template <typename R>
+LBM_HD RowOrigin tile_origin(const CavityConst<R> &c, const Tile2 &tl) {
+    const int yb = tl.y0 >= 2 ? tl.y0 - 2 : 0;
+    return RowOrigin{c.node0 + (int64_t)yb * c.nx, yb, c.nx};
+}
+
 // First update: slot s of R1 (row-major with the fixed pitch TW + 2, so the
 // decode divides by a constant; columns beyond w + 2 idle).  Reads the
 // global state, writes the slot's post-collision populations and Sr_f to LDS.
@@ -945,13 +1054,15 @@ LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *s
     LBM_HOST_CHECK(xx >= 0 && xx < c.nx);
     const bool owned = x >= tl.x0 && x < tl.x0 + tl.w && y >= tl.y0 && y < tl.y0 + tl.h;
     const NodeGeom g = geometry(c, xx, y, true);
+    const RowOrigin org = tile_origin(c, tl);
+    LBM_HOST_CHECK(g.sy - 1 >= org.yb && g.sy + 1 < org.yb + TH + 4);
     R qf[9], qh[9];
     RH qg[9];
-    gather<Lay, R, RH, true>(c, src, stride, g, xx, y, qf, qg, qh);
-    const int64_t k = c.node0 + (int64_t)y * c.nx + xx;
+    gather_at<Lay, R, RH, true>(c, src, stride, g, xx, y, org, qf, qg, qh);
     Thermo<RH> th;
     Macro<R> m;
-    const RH srf = update_node<Sh::QT, R, RH, true>(c, g, xx, y, qf, qg, qh, sr_src[k], owned, acc, th, m);
+    const R sr_prev = *at(sr_src, org(xx, y));
+    const RH srf = update_node<Sh::QT, R, RH, true>(c, g, xx, y, qf, qg, qh, sr_prev, owned, acc, th, m);
     using Cd = typename Sh::Codec;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -998,7 +1109,7 @@ LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, in
         }
     }
     const int self = (y - (tl.y0 - 1)) * LW + (x - (tl.x0 - 1));
-    const int64_t k = c.node0 + (int64_t)y * c.nx + x;
+    const NodeRef k = tile_origin(c, tl)(x, y);
     Thermo<RH> th;
     Macro<R> m;
     const RH srf = update_node<Sh::QT, R, RH, true>(c, g, x, y, qf, qg, qh, lds_sr[self], true, acc, th, m);
@@ -1006,7 +1117,7 @@ LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, in
     Lay::template store<R>(dst, stride, 0, qf, m.drho, k, c);
     Lay::template store<RH>(dst, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);
     Lay::template store<R>(dst, stride, 2, qh, c.c_mref * m.dTm, k, c);
-    sr_dst[k] = (R)srf;
+    *at(sr_dst, k) = (R)srf;
 }
 
 // Macroscopic fields of one node (post-streaming state) plus its
