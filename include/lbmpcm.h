@@ -88,7 +88,7 @@ typedef enum {
  * (Sec. IV parameter list).  Optional fields use the stated sentinel. */
 typedef struct lbm_params {
     int32_t nx, ny;       /* nodes including the wall nodes, each >= 4;
-                             nx <= 4194304, nx * ny <= 2^31                  */
+                             nx <= 262144, nx * ny <= 2^31                   */
     int32_t bc_x;         /* 0: cavity (hot wall x=0, cold wall x=nx-1);
                              1: periodic in x, walls only at y=0 and y=ny-1      */
     int32_t gravity_axis; /* 1: gravity along -y; 0: along -x                    */

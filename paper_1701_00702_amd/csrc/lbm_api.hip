@@ -281,8 +281,33 @@ ThermalConst<T> make_thermal(const Lattice &l) {
     return t;
 }
 
+// Banded placement of one cavity's populations in a state buffer.
+struct Bands {
+    int rows;       // rows per band
+    int64_t nodes;  // plane stride within a band (rows * nx, rounded up)
+    int64_t bytes;  // bytes of one band's block
+    int64_t off;    // byte offset of the cavity's first block
+    int count;      // number of bands
+};
+
+// Rows per band: about LBM_BAND_BYTES of state per block, at least enough
+// rows for any step-kernel tile to span at most two bands, at most the
+// cavity.  The plane stride is a multiple of 128 nodes, so every plane of
+// every block starts 256-byte aligned.
+Bands bands_of(int nx, int ny, int bpn, int64_t off) {
+    Bands b;
+    int64_t rows = LBM_BAND_BYTES / ((int64_t)bpn * nx);
+    rows = std::max<int64_t>(rows, std::max<int64_t>(LBM_MIN_BAND_ROWS, (2048 + nx - 1) / nx + 4));
+    b.rows = (int)std::min<int64_t>(rows, ny);
+    b.nodes = ((int64_t)b.rows * nx + 127) & ~(int64_t)127;
+    b.bytes = (int64_t)bpn * b.nodes;
+    b.off = off;
+    b.count = (ny + b.rows - 1) / b.rows;
+    return b;
+}
+
 template <typename R>
-CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
+CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0, const Bands &bd) {
     CavityConst<R> c;
     std::memset(&c, 0, sizeof(c));
     c.nx = l.nx;
@@ -291,6 +316,10 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0) {
     c.gaxis = l.gaxis;
     c.node0 = node0;
     c.acc0 = acc0;
+    c.band_rows = bd.rows;
+    c.band_nodes = bd.nodes;
+    c.band_bytes = bd.bytes;
+    c.pop_off = bd.off;
     c.phi = (R)l.phi;
     c.inv_phi = (R)(1.0 / l.phi);
     c.inv_cpm = (R)(1.0 / l.c_pm);
@@ -425,16 +454,14 @@ int64_t count_tiles2(int nx, int ny, int tw, int th) {
     return (int64_t)xs.size() * (int64_t)ys.size();
 }
 
-// Nodes added to every population plane beyond the 128-node rounding.
-#ifndef LBM_PLANE_PAD
-#define LBM_PLANE_PAD 0
-#endif
-
 // Memory plan shared by lbm_workspace_bytes and the create calls.
 struct Plan {
     int st = -1;  // storage form (precision and thermal lattice)
     std::vector<Lattice> lat;
     std::vector<int64_t> node0, acc0;
+    std::vector<Bands> bands;  // population blocks of each cavity
+    int64_t pop_bytes = 0;     // one state buffer
+    // nodes: packed index range of the flat per-node arrays (stride each)
     int64_t nodes = 0, stride = 0, slots = 0, max_nodes = 0;
     int max_tiles = 0;
     int64_t tiles2 = 0;  // tiles of the two-step kernel (0: not available for this storage)
@@ -476,11 +503,19 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     pl.max_tiles = (int)tiles;
     pl.st = storage_of(prec, qt0);
     const int st = pl.st;
-    pl.stride = ((pl.nodes + 127) & ~(int64_t)127) + LBM_PLANE_PAD;
+    pl.stride = (pl.nodes + 127) & ~(int64_t)127;
+    for (int c = 0; c < n; ++c) {
+        const Bands b = bands_of(p[c].nx, p[c].ny, bytes_per_node(st), pl.pop_bytes);
+        // the step kernels' 32-bit offsets within two consecutive blocks
+        if (b.nodes * (bytes_per_node(st) + 8) >= ((int64_t)1 << 31))
+            return fail(LBM_EINVAL, "cavity %d: rows of %d nodes are too long", c, p[c].nx);
+        pl.bands.push_back(b);
+        pl.pop_bytes += b.bytes * b.count;
+    }
     size_t off = 0;
     for (int b = 0; b < 2; ++b) {
         pl.off_pop[b] = off;
-        off = align256(off + (size_t)bytes_per_node(st) * pl.stride);
+        off = align256(off + (size_t)pl.pop_bytes);
     }
     for (int b = 0; b < 2; ++b) {
         pl.off_sr[b] = off;
@@ -622,7 +657,6 @@ Step2Launch step2_args(lbm_handle *h, int src_buf, double *acc, const lbm_launch
     L.xcd_remap = lc.xcd_remap;
     L.src = h->pop(src_buf);
     L.dst = h->pop(1 - src_buf);
-    L.plane_stride = h->pl.stride;
     L.sr_src = h->sr(src_buf);
     L.sr_dst = h->sr(1 - src_buf);
     L.acc = acc;
@@ -643,7 +677,6 @@ StepLaunch step_args(lbm_handle *h, int pull, int src_buf, double *acc, int tile
     L.pull = pull;
     L.src = h->pop(src_buf);
     L.dst = h->pop(1 - src_buf);
-    L.plane_stride = h->pl.stride;
     L.sr_src = h->sr(src_buf);
     L.sr_dst = h->sr(1 - src_buf);
     L.acc = acc;
@@ -709,7 +742,6 @@ lbm_status run_macro(lbm_handle *h, int c, bool with_diag) {
     M.raw = h->step == 0 ? 1 : 0;
     M.cav_index = c;
     M.src = h->pop(h->cur);
-    M.plane_stride = h->pl.stride;
     M.cav = h->cav();
     M.fields = h->fields();
     M.partials = h->partials();
@@ -756,7 +788,6 @@ lbm_status init_cavity(lbm_handle *h, int c, const double *T_pcm, const double *
     I.cav_index = c;
     I.cav = h->cav();
     I.dst = h->pop(h->cur);
-    I.plane_stride = h->pl.stride;
     I.sr = h->sr(h->cur);
     I.T_pcm = T_pcm ? dT : nullptr;
     I.T_mf = T_mf ? dT + nn : nullptr;
@@ -780,12 +811,14 @@ lbm_status setup(lbm_handle *h) {
     // cavity table in the kernels' arithmetic type (FP64 forms: double)
     if (real_size(h->st) == 8) {
         std::vector<CavityConst<double>> t;
-        for (int c = 0; c < h->n; ++c) t.push_back(make_const<double>(h->pl.lat[c], h->pl.node0[c], h->pl.acc0[c]));
+        for (int c = 0; c < h->n; ++c)
+            t.push_back(make_const<double>(h->pl.lat[c], h->pl.node0[c], h->pl.acc0[c], h->pl.bands[c]));
         HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     } else {
         std::vector<CavityConst<float>> t;
-        for (int c = 0; c < h->n; ++c) t.push_back(make_const<float>(h->pl.lat[c], h->pl.node0[c], h->pl.acc0[c]));
+        for (int c = 0; c < h->n; ++c)
+            t.push_back(make_const<float>(h->pl.lat[c], h->pl.node0[c], h->pl.acc0[c], h->pl.bands[c]));
         HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     }
@@ -1252,7 +1285,7 @@ extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
     if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
     HIP_TRY(hipStreamSynchronize(h->stream));
     const size_t rs = real_size(h->st);
-    std::vector<char> buf((size_t)bytes_per_node(h->st) * h->pl.stride);
+    std::vector<char> buf((size_t)h->pl.pop_bytes);
     HIP_TRY(hipMemcpy(buf.data(), h->pop(h->cur), buf.size(), hipMemcpyDeviceToHost));
     std::vector<char> sr((size_t)h->pl.stride * rs);
     HIP_TRY(hipMemcpy(sr.data(), h->sr(h->cur), sr.size(), hipMemcpyDeviceToHost));
@@ -1297,7 +1330,7 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
     std::vector<lbm_params> ps(h->n);
     std::vector<double> E0(h->n), M0(h->n);
     const size_t rs = real_size(h->st);
-    std::vector<char> buf((size_t)bytes_per_node(h->st) * h->pl.stride), sr((size_t)h->pl.stride * rs);
+    std::vector<char> buf((size_t)h->pl.pop_bytes), sr((size_t)h->pl.stride * rs);
     std::vector<double> acc((size_t)h->pl.slots * 2);
     bool ok = fread(ps.data(), sizeof(lbm_params), h->n, f) == (size_t)h->n;
     ok = ok && fread(E0.data(), sizeof(double), h->n, f) == (size_t)h->n;
@@ -1329,16 +1362,23 @@ extern "C" lbm_status lbm_copy_state(lbm_handle *h, int32_t c, void *host, uint6
     HIP_TRY(hipStreamSynchronize(h->stream));
     PlaneGroup grp[2];
     const int ng = plane_groups(h->st, grp);
-    const char *src = (const char *)h->pop(h->cur);
+    const Bands &bd = h->pl.bands[c];
+    const int nx = h->params[c].nx, ny = h->params[c].ny;
+    const char *blocks = (const char *)h->pop(h->cur) + bd.off;
     char *dst = (char *)host;
+    size_t group_off = 0;  // byte offset of the plane group within a block
     for (int q = 0; q < ng; ++q) {
+        const size_t eb = grp[q].bytes;
         for (int p = 0; p < grp[q].planes; ++p) {
-            const size_t eb = grp[q].bytes;
-            HIP_TRY(hipMemcpy(dst, src + ((size_t)p * h->pl.stride + h->pl.node0[c]) * eb, nn * eb,
-                              hipMemcpyDeviceToHost));
-            dst += nn * eb;
+            // each band's rows of the plane are contiguous in its block
+            for (int b = 0; b < bd.count; ++b) {
+                const int rows = std::min(bd.rows, ny - b * bd.rows);
+                const char *src = blocks + (size_t)b * bd.bytes + group_off + (size_t)p * bd.nodes * eb;
+                HIP_TRY(hipMemcpy(dst, src, (size_t)rows * nx * eb, hipMemcpyDeviceToHost));
+                dst += (size_t)rows * nx * eb;
+            }
         }
-        src += (size_t)grp[q].planes * h->pl.stride * grp[q].bytes;
+        group_off += (size_t)grp[q].planes * bd.nodes * eb;
     }
     return LBM_OK;
 }
@@ -1352,32 +1392,36 @@ extern "C" lbm_status lbm_debug_poke(lbm_handle *h, int32_t c, int32_t x, int32_
     if (x < 0 || x >= p.nx || y < 0 || y >= p.ny || field < 0 || field > 2 || dir < 0 ||
         dir > (field == 0 ? 8 : qt - 1))
         return fail(LBM_EINVAL, "poke index out of range");
-    const int64_t node = h->pl.node0[c] + (int64_t)y * p.nx + x;
-    char *base = (char *)h->pop(h->cur);
+    // the node's band block, its index within the band, the plane stride
+    const Bands &bd = h->pl.bands[c];
+    const int b = y / bd.rows;
+    const int64_t node = (int64_t)(y - b * bd.rows) * p.nx + x;
+    const size_t S = (size_t)bd.nodes;
+    char *base = (char *)h->pop(h->cur) + bd.off + (size_t)b * bd.bytes;
     char *ptr;
     int elem;
     if (h->st == ST_F32H || h->st == ST5_F32H) {
         const int nf32 = 8 + 2 * qt;
         if (field == 1 && dir == 0) {
-            ptr = base + (size_t)nf32 * h->pl.stride * 4 + (size_t)node * 8;
+            ptr = base + (size_t)nf32 * S * 4 + (size_t)node * 8;
             elem = 8;
         } else {
             const int plane = field == 0 ? dir : (field == 1 ? 8 + dir : 8 + qt + dir);
-            ptr = base + ((size_t)plane * h->pl.stride + node) * 4;
+            ptr = base + ((size_t)plane * S + node) * 4;
             elem = 4;
         }
     } else if (h->st == ST_F16S) {
         if (dir == 0) {
-            ptr = base + ((size_t)(2 * field) * h->pl.stride + node) * 4;
+            ptr = base + ((size_t)(2 * field) * S + node) * 4;
             elem = 4;
         } else {
-            ptr = base + (size_t)6 * h->pl.stride * 4 + ((size_t)(8 * field + dir - 1) * h->pl.stride + node) * 2;
+            ptr = base + (size_t)6 * S * 4 + ((size_t)(8 * field + dir - 1) * S + node) * 2;
             elem = 2;
         }
     } else {
         const int eb = bytes_per_node(h->st) / (9 + 2 * qt);
         const int plane = field == 0 ? dir : 9 + (field - 1) * qt + dir;
-        ptr = base + ((size_t)plane * h->pl.stride + node) * eb;
+        ptr = base + ((size_t)plane * S + node) * eb;
         elem = h->st == ST_BF16 ? 3 : eb;
     }
     HIP_TRY(launch_poke(elem, ptr, value, h->stream));

@@ -16,10 +16,15 @@ enum Storage {
 
 enum Wall { W_LEFT = 0, W_RIGHT = 1, W_BOTTOM = 2, W_TOP = 3 };
 
-// Longest cavity row.  The step kernels address the rows a tile touches
-// (at most 2048 + 3 nx nodes, or TH + 4 rows of the two-step tiles) by
-// 32-bit byte offsets of up to 8-byte elements from the tile's first row.
-#define LBM_MAX_NX 4194304
+// Longest cavity row.  A band (below) holds at least LBM_MIN_BAND_ROWS rows,
+// and the step kernels address a tile's rows by 32-bit byte offsets within
+// two consecutive bands: band_nodes * (bytes per node + 8) < 2^31.
+#define LBM_MAX_NX 262144
+#define LBM_MIN_BAND_ROWS 32
+// Target size of one band of a state buffer (bytes); a build option.
+#ifndef LBM_BAND_BYTES
+#define LBM_BAND_BYTES (256ll << 20)
+#endif
 
 // Constants of the PCM enthalpy field, kept in both arithmetic types (the
 // mixed storage form runs this field in FP64 and the others in FP32).
@@ -41,10 +46,20 @@ struct ThermalConst {
 // its tile through scalar loads.
 template <typename R>
 struct CavityConst {
-    // geometry of the cavity inside the packed node index
+    // geometry of the cavity inside the packed node index (the flat
+    // per-node arrays of the interstitial source)
     int32_t nx, ny, periodic, gaxis;
     int64_t node0;  // first packed node of this cavity
     int64_t acc0;   // first wall-tally slot of this cavity (2*(nx+ny) slots)
+    // Populations are stored by bands: rows [b * band_rows, (b + 1) *
+    // band_rows) of the cavity form band b, a block of band_bytes holding
+    // every population plane of those rows (node (x, y) at index
+    // (y - b * band_rows) * nx + x of a plane, plane stride band_nodes).  The
+    // cavity's blocks follow each other from byte pop_off of a state buffer.
+    // Kept to a few hundred MiB, a block keeps the planes a tile reads and
+    // writes close together in the address space.
+    int32_t band_rows;
+    int64_t band_nodes, band_bytes, pop_off;
     // materials
     R phi, inv_phi, inv_cpm, c_pm, c_mref;
     // relaxation rates in moment order and the forcing factors 1 - s/2
@@ -83,9 +98,8 @@ struct StepLaunch {
     int storage;
     int block, npt, xcd_remap, grid;  // grid: number of workgroups (>= 1)
     int pull;                         // 0: first step, populations are post-streaming already
-    const void *src;                  // population planes of plane_stride nodes each
+    const void *src;                  // state buffers (banded population blocks)
     void *dst;
-    int64_t plane_stride;
     const void *sr_src;
     void *sr_dst;
     double *acc;                      // wall tallies: [slot][2] (energy, mass)
@@ -105,7 +119,6 @@ struct Step2Launch {
     int grid, xcd_remap;
     const void *src;
     void *dst;
-    int64_t plane_stride;
     const void *sr_src;
     void *sr_dst;
     double *acc;
@@ -119,7 +132,6 @@ struct MacroLaunch {
     int raw;  // 1: populations are post-streaming already (step 0)
     int cav_index;
     const void *src;
-    int64_t plane_stride;
     const void *cav;     // CavityConst<R>[]
     double *fields;      // 6 planes of nx*ny doubles: ux, uy, T_f, T_m, f_l, rho
     double *partials;    // [nblocks][NPART]
@@ -154,7 +166,6 @@ struct InitLaunch {
     int cav_index;
     const void *cav;
     void *dst;
-    int64_t plane_stride;
     void *sr;
     const double *T_pcm;  // device, may be null
     const double *T_mf;   // device, may be null

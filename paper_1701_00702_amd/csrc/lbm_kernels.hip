@@ -72,14 +72,16 @@ __device__ __forceinline__ int remap_block(int b, int grid, int xcd_remap) {
     return (b & 7) * per + (b >> 3);
 }
 
-// The tile of one workgroup.  Accesses are 32-bit offsets from a row the
-// workgroup shares: for interior tiles the row before their first one (the
-// pulls reach one row either side), for wall tiles (one row each) the first
-// of the three rows their wall partners pull from.  Both kinds share one
-// instantiation of the node update (decided per node), so the kernel holds
-// a single copy of the global accesses.
+// The tile of one workgroup.  Accesses are 32-bit offsets from the block of
+// the band of a row the workgroup shares: for interior tiles the row before
+// their first one (the pulls reach one row either side; a tile of at most
+// 2048 nodes then spans at most 2048 / nx + 3 <= LBM_MIN_BAND_ROWS rows),
+// for wall tiles (one row each) the first of the three rows their wall
+// partners pull from.  Both kinds share one instantiation of the node
+// update (decided per node), so the kernel holds a single copy of the
+// global accesses.
 template <class Lay, typename R, typename RH, bool PULL, int NPT>
-__device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__restrict__ dst, int64_t stride,
+__device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__restrict__ dst,
                                           const R *__restrict__ sr_src, R *__restrict__ sr_dst,
                                           double *__restrict__ acc, const CavityConst<R> *__restrict__ cav,
                                           const Tile &tl) {
@@ -92,7 +94,10 @@ __device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__
         const int y0 = tl.k0 / c.nx;
         yb = y0 >= 1 ? y0 - 1 : 0;
     }
-    const RowOrigin org{c.node0 + (int64_t)yb * c.nx, yb, c.nx};
+    const BandOrigin org = band_origin(c, yb);
+    const int ba = yb / c.band_rows;
+    const void *sblk = band_block(c, src, ba);
+    void *dblk = band_block(c, dst, ba);
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
         const int k = tl.k0 + (int)threadIdx.x + j * (int)blockDim.x;
@@ -107,7 +112,7 @@ __device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__
             // interior tiles cover whole rows: the wall columns ride along
             // (each stored cache line then has one writer); lanes on row 0 idle
             if (wall || y >= 1)
-                step_node_at<Lay, R, RH, PULL, NODE_ANY>(c, src, dst, stride, sr_src, sr_dst, acc, x, y, org);
+                step_node_at<Lay, R, RH, PULL, NODE_ANY>(c, sblk, dblk, sr_src, sr_dst, acc, x, y, org);
         }
     }
 }
@@ -116,18 +121,18 @@ __device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__
 // the persistent launch.
 template <class Lay, typename R, typename RH, bool PULL, int NPT, bool LOOP>
 __global__ __launch_bounds__(512) void step_kernel(const void *__restrict__ src, void *__restrict__ dst,
-                                                   int64_t stride, const R *__restrict__ sr_src,
+                                                   const R *__restrict__ sr_src,
                                                    R *__restrict__ sr_dst, double *__restrict__ acc,
                                                    const CavityConst<R> *__restrict__ cav,
                                                    const Tile *__restrict__ tiles, int ntiles,
                                                    int xcd_remap) {
     const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
     if (!LOOP) {
-        if (b < ntiles) step_tile<Lay, R, RH, PULL, NPT>(src, dst, stride, sr_src, sr_dst, acc, cav, tiles[b]);
+        if (b < ntiles) step_tile<Lay, R, RH, PULL, NPT>(src, dst, sr_src, sr_dst, acc, cav, tiles[b]);
         return;
     }
     for (int t = b; t < ntiles; t += gridDim.x)
-        step_tile<Lay, R, RH, PULL, NPT>(src, dst, stride, sr_src, sr_dst, acc, cav, tiles[t]);
+        step_tile<Lay, R, RH, PULL, NPT>(src, dst, sr_src, sr_dst, acc, cav, tiles[t]);
 }
 
 template <int ST, bool PULL, int NPT>
@@ -137,11 +142,11 @@ static hipError_t launch_step_t(const StepLaunch &L, hipStream_t s) {
     using RH = typename LayoutOf<ST>::RH;
     if (L.grid >= L.ntiles)
         hipLaunchKernelGGL((step_kernel<Lay, R, RH, PULL, NPT, false>), dim3(L.grid), dim3(L.block), 0, s, L.src,
-                           L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                           L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     else
         hipLaunchKernelGGL((step_kernel<Lay, R, RH, PULL, NPT, true>), dim3(L.grid), dim3(L.block), 0, s, L.src,
-                           L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                           L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     return hipGetLastError();
 }
@@ -219,21 +224,21 @@ struct Step2Tile<ST5_F64> {  // 19 x 8 + 8 = 160 B per slot, 18 x 22 slots
 // across iterations (they would spill to vector registers).
 template <class Lay, typename R, typename RH, int TW, int TH, int NT>
 __device__ __forceinline__ void step2_advance(const void *__restrict__ src, void *__restrict__ dst,
-                                              int64_t stride, const R *__restrict__ sr_src,
+                                              const R *__restrict__ sr_src,
                                               R *__restrict__ sr_dst, double *__restrict__ acc,
                                               const CavityConst<R> *__restrict__ cav, const Tile2 &tl,
                                               void *lds_q, R *lds_sr) {
     const CavityConst<R> &c = cav[tl.cav];
     // NT >= NSLOT: each thread advances at most one slot per update
     const int s = (int)threadIdx.x;
-    if (s < (TW + 2) * (tl.h + 2)) step2_phase1<Lay, R, RH, TW, TH>(c, tl, src, stride, sr_src, acc, lds_q, lds_sr, s);
+    if (s < (TW + 2) * (tl.h + 2)) step2_phase1<Lay, R, RH, TW, TH>(c, tl, src, sr_src, acc, lds_q, lds_sr, s);
     __syncthreads();
-    if (s < TW * tl.h) step2_phase2<Lay, R, RH, TW, TH>(c, tl, dst, stride, sr_dst, acc, lds_q, lds_sr, s);
+    if (s < TW * tl.h) step2_phase2<Lay, R, RH, TW, TH>(c, tl, dst, sr_dst, acc, lds_q, lds_sr, s);
 }
 
 template <class Lay, typename R, typename RH, int TW, int TH, int NT, bool LOOP>
 __global__ __launch_bounds__(NT) void step2_kernel(const void *__restrict__ src, void *__restrict__ dst,
-                                                   int64_t stride, const R *__restrict__ sr_src,
+                                                   const R *__restrict__ sr_src,
                                                    R *__restrict__ sr_dst, double *__restrict__ acc,
                                                    const CavityConst<R> *__restrict__ cav,
                                                    const Tile2 *__restrict__ tiles, int ntiles, int xcd_remap) {
@@ -245,11 +250,11 @@ __global__ __launch_bounds__(NT) void step2_kernel(const void *__restrict__ src,
     const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
     if (!LOOP) {
         if (b < ntiles)
-            step2_advance<Lay, R, RH, TW, TH, NT>(src, dst, stride, sr_src, sr_dst, acc, cav, tiles[b], lds_q, lds_sr);
+            step2_advance<Lay, R, RH, TW, TH, NT>(src, dst, sr_src, sr_dst, acc, cav, tiles[b], lds_q, lds_sr);
         return;
     }
     for (int t = b; t < ntiles; t += gridDim.x) {
-        step2_advance<Lay, R, RH, TW, TH, NT>(src, dst, stride, sr_src, sr_dst, acc, cav, tiles[t], lds_q, lds_sr);
+        step2_advance<Lay, R, RH, TW, TH, NT>(src, dst, sr_src, sr_dst, acc, cav, tiles[t], lds_q, lds_sr);
         __syncthreads();  // the next tile reuses the LDS
     }
 }
@@ -262,11 +267,11 @@ static hipError_t launch_step2_s(const Step2Launch &L, hipStream_t s) {
     using Tl = Step2Tile<ST>;
     if (L.grid >= L.ntiles)
         hipLaunchKernelGGL((step2_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, false>), dim3(L.grid), dim3(Tl::NT),
-                           0, s, L.src, L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                           0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     else
         hipLaunchKernelGGL((step2_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, true>), dim3(L.grid), dim3(Tl::NT),
-                           0, s, L.src, L.dst, L.plane_stride, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                           0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     return hipGetLastError();
 }
@@ -309,7 +314,7 @@ constexpr int MB = 256;  // threads per block of the diagnostics kernels
 int macro_blocks(int nx, int ny) { return (int)(((int64_t)nx * ny + MB - 1) / MB); }
 
 template <class Lay, typename R, typename RH>
-__global__ __launch_bounds__(MB) void macro_kernel(const void *__restrict__ src, int64_t stride,
+__global__ __launch_bounds__(MB) void macro_kernel(const void *__restrict__ src,
                                                    const CavityConst<R> *__restrict__ cav, int ci,
                                                    int raw, double *__restrict__ fields,
                                                    double *__restrict__ partials) {
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(MB) void macro_kernel(const void *__restrict__ src,
     if (kk < nn) {
         const int x = (int)(kk % nx), y = (int)(kk / nx);
         double out[6];
-        macro_node<Lay, R, RH>(c, src, stride, raw != 0, x, y, out, v);
+        macro_node<Lay, R, RH>(c, src, raw != 0, x, y, out, v);
 #pragma unroll
         for (int q = 0; q < 6; ++q) fields[q * nn + kk] = out[q];
     }
@@ -350,7 +355,7 @@ static hipError_t launch_macro_s(const MacroLaunch &L, hipStream_t s) {
     using Lay = typename LayoutOf<ST>::L;
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
-    hipLaunchKernelGGL((macro_kernel<Lay, R, RH>), dim3(L.nblocks), dim3(MB), 0, s, L.src, L.plane_stride,
+    hipLaunchKernelGGL((macro_kernel<Lay, R, RH>), dim3(L.nblocks), dim3(MB), 0, s, L.src,
                        (const CavityConst<R> *)L.cav, L.cav_index, L.raw, L.fields, L.partials);
     return hipGetLastError();
 }
@@ -469,7 +474,7 @@ hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s) {
 // ---------------------------------------------------------------------------
 template <class Lay, typename R, typename RH>
 __global__ __launch_bounds__(MB) void init_kernel(const CavityConst<R> *__restrict__ cav, int ci,
-                                                  void *__restrict__ dst, int64_t stride,
+                                                  void *__restrict__ dst,
                                                   R *__restrict__ sr, const double *__restrict__ T_pcm,
                                                   const double *__restrict__ T_mf) {
     const CavityConst<R> &c = cav[ci];
@@ -479,7 +484,7 @@ __global__ __launch_bounds__(MB) void init_kernel(const CavityConst<R> *__restri
     if (kk >= nn) return;
     const double Tf = T_pcm ? T_pcm[kk] : c.T_init;
     const double Tm = T_mf ? T_mf[kk] : c.T_init;
-    init_node<Lay, R, RH>(c, dst, stride, sr, (int)(kk % nx), (int)(kk / nx), Tf, Tm);
+    init_node<Lay, R, RH>(c, dst, sr, (int)(kk % nx), (int)(kk / nx), Tf, Tm);
 }
 
 template <int ST>
@@ -488,7 +493,7 @@ static hipError_t launch_init_s(const InitLaunch &L, int nx, int ny, hipStream_t
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
     hipLaunchKernelGGL((init_kernel<Lay, R, RH>), dim3(macro_blocks(nx, ny)), dim3(MB), 0, s,
-                       (const CavityConst<R> *)L.cav, L.cav_index, L.dst, L.plane_stride, (R *)L.sr,
+                       (const CavityConst<R> *)L.cav, L.cav_index, L.dst, (R *)L.sr,
                        L.T_pcm, L.T_mf);
     return hipGetLastError();
 }

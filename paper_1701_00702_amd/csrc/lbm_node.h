@@ -134,40 +134,45 @@ LBM_HD void st_stream(T *p, T v) {
 #endif
 }
 
-// A node's place in a population plane: a packed node index (int64_t), or
-// an origin k0 that is the same for the whole wavefront plus a 32-bit
-// offset rel (NodeRef).  With the second form the address of each plane at
-// the origin is held in scalar registers (the empty asm keeps the compiler
-// from regrouping the sum into a per-lane 64-bit base plus plane offsets)
-// and an access is that scalar base plus a 32-bit vector offset; the
-// caller keeps rel times the element size below 2^31.
+// A node's place in a population plane of a band block (the banded layout
+// of the state buffers is described with CavityConst).  NodeRef: the node's
+// offset rel within its band's plane plus the byte distance jump of its
+// band's block from the block the plane pointer points into, both 32-bit;
+// the step kernels use it with the same block for the whole workgroup (the
+// tile's first band), so the address of each plane stays in scalar
+// registers (the empty asm keeps the compiler from regrouping the sum into
+// a per-lane 64-bit base plus plane offsets) and an access is that scalar
+// base plus one 32-bit vector offset.  FarRef: the same in 64 bits, for an
+// access anywhere in a cavity from its first band's block.
 struct NodeRef {
-    int64_t k0;
-    uint32_t rel;
+    uint32_t rel, jump;
+};
+struct FarRef {
+    int64_t rel, jump;
 };
 template <typename T>
-LBM_HD T *at(T *plane, int64_t k) {
-    return plane + k;
+using ByteOf = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+template <typename T>
+LBM_HD T *at(T *plane, FarRef r) {
+    return (T *)((ByteOf<T> *)(plane + r.rel) + r.jump);
 }
 template <typename T>
 LBM_HD T *at(T *plane, NodeRef r) {
-    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
-    T *b = plane + r.k0;
 #if defined(__HIP_DEVICE_COMPILE__)
-    __attribute__((address_space(1))) T *gb = (__attribute__((address_space(1))) T *)b;  // global memory
-    asm("" : "+s"(gb));
-    b = (T *)gb;
+    __attribute__((address_space(1))) T *gp = (__attribute__((address_space(1))) T *)plane;  // global memory
+    asm("" : "+s"(gp));
+    plane = (T *)gp;
 #endif
-    return (T *)((B *)b + r.rel * (uint32_t)sizeof(T));
+    return (T *)((ByteOf<T> *)plane + (r.rel * (uint32_t)sizeof(T) + r.jump));
 }
 // The address of a store of v to plane p (of stride elements) from base:
 // as at(), with the plane's scalar base formed from a copy of the stride
 // that depends on v.  The bases are then computed next to the stores, not
 // shared with the loads' and held in scalar registers across the update.
 template <typename T, typename V>
-LBM_HD T *at_store(T *base, int p, int64_t stride, int64_t k, V v) {
+LBM_HD T *at_store(T *base, int p, int64_t stride, FarRef r, V v) {
     (void)v;
-    return base + (int64_t)p * stride + k;
+    return at(base + (int64_t)p * stride, r);
 }
 template <typename T, typename V>
 LBM_HD T *at_store(T *base, int p, int64_t stride, NodeRef r, V v) {
@@ -779,27 +784,54 @@ LBM_HD void ring_node(const CavityConst<R> &c, int r, int &x, int &y) {
     }
 }
 
-// Where node (x, y) of a cavity sits in the planes: its packed index, or
-// (RowOrigin) an offset from the start of row yb, whose packed index k0 is
-// uniform across the workgroup; rows yb .. yb + span of the cavity must fit
-// the 32-bit offset (checked on the host).
-struct PackedIndex {
-    int64_t node0;
+// Where node (x, y) of a cavity sits relative to a band block.  BandOrigin:
+// rows of band ba and ba + 1 from band ba's block (the step kernels' tiles
+// span at most two bands).  AnyBand: any row, from the cavity's first block.
+struct BandOrigin {
+    int y_first, y_next;  // first rows of bands ba and ba + 1
     int nx;
-    LBM_HD int64_t operator()(int x, int y) const { return node0 + (int64_t)y * nx + x; }
+    uint32_t band_bytes;
+    LBM_HD NodeRef operator()(int x, int y) const {
+        return y < y_next ? NodeRef{(uint32_t)((y - y_first) * nx + x), 0u}
+                          : NodeRef{(uint32_t)((y - y_next) * nx + x), band_bytes};
+    }
 };
-struct RowOrigin {
-    int64_t k0;
-    int yb, nx;
-    LBM_HD NodeRef operator()(int x, int y) const { return NodeRef{k0, (uint32_t)((y - yb) * nx + x)}; }
+struct AnyBand {
+    int band_rows, nx;
+    int64_t band_bytes;
+    LBM_HD FarRef operator()(int x, int y) const {
+        const int b = y / band_rows;
+        return FarRef{(int64_t)(y - b * band_rows) * nx + x, (int64_t)b * band_bytes};
+    }
 };
+template <typename R>
+LBM_HD BandOrigin band_origin(const CavityConst<R> &c, int y) {  // from the band of row y
+    const int ba = y / c.band_rows;
+    return BandOrigin{ba * c.band_rows, (ba + 1) * c.band_rows, c.nx, (uint32_t)c.band_bytes};
+}
+template <typename R>
+LBM_HD AnyBand any_band(const CavityConst<R> &c) {
+    return AnyBand{c.band_rows, c.nx, c.band_bytes};
+}
+// The block of band b of cavity c in a state buffer.
+template <typename R, typename V>
+LBM_HD V *band_block(const CavityConst<R> &c, V *buf, int b) {
+    return (V *)((ByteOf<V> *)buf + c.pop_off + (int64_t)b * c.band_bytes);
+}
+// Index of node (x, y) in the flat per-node arrays (interstitial source).
+template <typename R>
+LBM_HD int64_t flat_index(const CavityConst<R> &c, int x, int y) {
+    return c.node0 + (int64_t)y * c.nx + x;
+}
 
 // Offsets of the node's post-streaming populations: pulled from the
 // neighbours (Eqs. 15, 33, 44), or read in place for the initial state.
+// src is the band block addr is relative to.
 template <class Lay, typename R, typename RH, bool PULL, class A>
-LBM_HD void gather_at(const CavityConst<R> &c, const void *src, int64_t stride, const NodeGeom &g, int x,
-                      int y, A addr, R qf[9], RH qg[9], R qh[9]) {
+LBM_HD void gather_at(const CavityConst<R> &c, const void *src, const NodeGeom &g, int x, int y, A addr,
+                      R qf[9], RH qg[9], R qh[9]) {
     const int nx = c.nx;
+    const int64_t stride = c.band_nodes;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int px = x, py = y;
@@ -820,10 +852,11 @@ LBM_HD void gather_at(const CavityConst<R> &c, const void *src, int64_t stride, 
     }
 }
 
+// From a whole state buffer.
 template <class Lay, typename R, typename RH, bool PULL>
-LBM_HD void gather(const CavityConst<R> &c, const void *src, int64_t stride, const NodeGeom &g, int x,
-                   int y, R qf[9], RH qg[9], R qh[9]) {
-    gather_at<Lay, R, RH, PULL>(c, src, stride, g, x, y, PackedIndex{c.node0, c.nx}, qf, qg, qh);
+LBM_HD void gather(const CavityConst<R> &c, const void *buf, const NodeGeom &g, int x, int y, R qf[9],
+                   RH qg[9], R qh[9]) {
+    gather_at<Lay, R, RH, PULL>(c, band_block(c, buf, 0), g, x, y, any_band(c), qf, qg, qh);
 }
 
 // Energy and mass carried by direction i of the given offsets (FP64);
@@ -923,32 +956,34 @@ LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, 
 
 // One node's full time step.  KIND selects which of the interior and wall
 // code paths this instantiation carries (the caller guarantees the node is
-// of that kind); addr places the node and its neighbours in the planes.
+// of that kind); addr places the node and its neighbours relative to the
+// band blocks src and dst.
 template <class Lay, typename R, typename RH, bool PULL, int KIND, class A>
-LBM_HD void step_node_at(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
-                         const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
-                         int x, int y, A addr) {
+LBM_HD void step_node_at(const CavityConst<R> &c, const void *src, void *dst, const R *__restrict__ sr_src,
+                         R *__restrict__ sr_dst, double *__restrict__ acc, int x, int y, A addr) {
     const NodeGeom g = geometry_of<R, KIND>(c, x, y, PULL);
     R qf[9], qh[9];
     RH qg[9];
-    gather_at<Lay, R, RH, PULL>(c, src, stride, g, x, y, addr, qf, qg, qh);
+    gather_at<Lay, R, RH, PULL>(c, src, g, x, y, addr, qf, qg, qh);
     const auto k = addr(x, y);
+    const int64_t kf = flat_index(c, x, y);
     Thermo<RH> th;
     Macro<R> m;
-    const RH srf = update_node<Lay::QT, R, RH, PULL>(c, g, x, y, qf, qg, qh, *at(sr_src, k), true, acc, th, m);
+    const RH srf = update_node<Lay::QT, R, RH, PULL>(c, g, x, y, qf, qg, qh, sr_src[kf], true, acc, th, m);
     const ThermalConst<RH> &t = thermal<RH>(c);
+    const int64_t stride = c.band_nodes;
     Lay::template store<R>(dst, stride, 0, qf, m.drho, k, c);
     Lay::template store<RH>(dst, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);
     Lay::template store<R>(dst, stride, 2, qh, c.c_mref * m.dTm, k, c);
-    *at(sr_dst, k) = (R)srf;
+    sr_dst[kf] = (R)srf;
 }
 
+// The same on whole state buffers.
 template <class Lay, typename R, typename RH, bool PULL, int KIND = NODE_ANY>
-LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, int64_t stride,
-                      const R *__restrict__ sr_src, R *__restrict__ sr_dst, double *__restrict__ acc,
-                      int x, int y) {
-    step_node_at<Lay, R, RH, PULL, KIND>(c, src, dst, stride, sr_src, sr_dst, acc, x, y,
-                                         PackedIndex{c.node0, c.nx});
+LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, const R *__restrict__ sr_src,
+                      R *__restrict__ sr_dst, double *__restrict__ acc, int x, int y) {
+    step_node_at<Lay, R, RH, PULL, KIND>(c, band_block(c, src, 0), band_block(c, dst, 0), sr_src, sr_dst, acc,
+                                         x, y, any_band(c));
 }
 
 // ---------------------------------------------------------------------------
@@ -1025,20 +1060,21 @@ struct Step2Shape {
     static constexpr size_t LDS_BYTES = Codec::bytes(NSLOT);
 };
 
-// Global accesses of a tile go through 32-bit offsets from the first row
-// either update touches, y0 - 2 (the ring's pulls), clipped to the cavity:
-// at most TH + 4 rows (the host enables the kernel only where they fit).
+// Global accesses of a tile go through 32-bit offsets from the block of the
+// band of the first row either update touches, y0 - 2 (the ring's pulls),
+// clipped to the cavity: at most TH + 4 <= LBM_MIN_BAND_ROWS rows, so at
+// most two bands.
 template <typename R>
-LBM_HD RowOrigin tile_origin(const CavityConst<R> &c, const Tile2 &tl) {
-    const int yb = tl.y0 >= 2 ? tl.y0 - 2 : 0;
-    return RowOrigin{c.node0 + (int64_t)yb * c.nx, yb, c.nx};
+LBM_HD int tile_first_row(const CavityConst<R> &c, const Tile2 &tl) {
+    (void)c;
+    return tl.y0 >= 2 ? tl.y0 - 2 : 0;
 }
 
 // First update: slot s of R1 (row-major with the fixed pitch TW + 2, so the
 // decode divides by a constant; columns beyond w + 2 idle).  Reads the
 // global state, writes the slot's post-collision populations and Sr_f to LDS.
 template <class Lay, typename R, typename RH, int TW, int TH>
-LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *src, int64_t stride,
+LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *src,
                          const R *__restrict__ sr_src, double *__restrict__ acc, void *lds_q, R *lds_sr,
                          int s) {
     using Sh = Step2Shape<Lay, TW, TH>;
@@ -1054,14 +1090,16 @@ LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *s
     LBM_HOST_CHECK(xx >= 0 && xx < c.nx);
     const bool owned = x >= tl.x0 && x < tl.x0 + tl.w && y >= tl.y0 && y < tl.y0 + tl.h;
     const NodeGeom g = geometry(c, xx, y, true);
-    const RowOrigin org = tile_origin(c, tl);
-    LBM_HOST_CHECK(g.sy - 1 >= org.yb && g.sy + 1 < org.yb + TH + 4);
+    const int yb = tile_first_row(c, tl);
+    const BandOrigin org = band_origin(c, yb);
+    LBM_HOST_CHECK(g.sy - 1 >= yb && g.sy + 1 < yb + TH + 4 && TH + 4 <= LBM_MIN_BAND_ROWS);
+    LBM_HOST_CHECK(g.sy + 1 < org.y_next + c.band_rows);
     R qf[9], qh[9];
     RH qg[9];
-    gather_at<Lay, R, RH, true>(c, src, stride, g, xx, y, org, qf, qg, qh);
+    gather_at<Lay, R, RH, true>(c, band_block(c, src, yb / c.band_rows), g, xx, y, org, qf, qg, qh);
     Thermo<RH> th;
     Macro<R> m;
-    const R sr_prev = *at(sr_src, org(xx, y));
+    const R sr_prev = sr_src[flat_index(c, xx, y)];
     const RH srf = update_node<Sh::QT, R, RH, true>(c, g, xx, y, qf, qg, qh, sr_prev, owned, acc, th, m);
     using Cd = typename Sh::Codec;
 #pragma unroll
@@ -1078,9 +1116,8 @@ LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *s
 // Second update: node n of the tile (row-major with pitch TW; columns beyond
 // w idle).  Pulls from LDS, writes the global state.
 template <class Lay, typename R, typename RH, int TW, int TH>
-LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, int64_t stride,
-                         R *__restrict__ sr_dst, double *__restrict__ acc, const void *lds_q,
-                         const R *lds_sr, int n) {
+LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, R *__restrict__ sr_dst,
+                         double *__restrict__ acc, const void *lds_q, const R *lds_sr, int n) {
     using Sh = Step2Shape<Lay, TW, TH>;
     constexpr int LW = TW + 2;
     LBM_HOST_CHECK(n >= 0 && n < TW * tl.h);
@@ -1109,28 +1146,31 @@ LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, in
         }
     }
     const int self = (y - (tl.y0 - 1)) * LW + (x - (tl.x0 - 1));
-    const NodeRef k = tile_origin(c, tl)(x, y);
+    const int yb = tile_first_row(c, tl);
+    const NodeRef k = band_origin(c, yb)(x, y);
+    void *blk = band_block(c, dst, yb / c.band_rows);
     Thermo<RH> th;
     Macro<R> m;
     const RH srf = update_node<Sh::QT, R, RH, true>(c, g, x, y, qf, qg, qh, lds_sr[self], true, acc, th, m);
     const ThermalConst<RH> &t = thermal<RH>(c);
-    Lay::template store<R>(dst, stride, 0, qf, m.drho, k, c);
-    Lay::template store<RH>(dst, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);
-    Lay::template store<R>(dst, stride, 2, qh, c.c_mref * m.dTm, k, c);
-    *at(sr_dst, k) = (R)srf;
+    const int64_t stride = c.band_nodes;
+    Lay::template store<R>(blk, stride, 0, qf, m.drho, k, c);
+    Lay::template store<RH>(blk, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);
+    Lay::template store<R>(blk, stride, 2, qh, c.c_mref * m.dTm, k, c);
+    sr_dst[flat_index(c, x, y)] = (R)srf;
 }
 
 // Macroscopic fields of one node (post-streaming state) plus its
 // contributions to the diagnostics partial sums.
 template <class Lay, typename R, typename RH>
-LBM_HD void macro_node(const CavityConst<R> &c, const void *src, int64_t stride, bool raw, int x, int y,
-                       double out[6], double v[NPART]) {
+LBM_HD void macro_node(const CavityConst<R> &c, const void *src, bool raw, int x, int y, double out[6],
+                       double v[NPART]) {
     const int nx = c.nx, ny = c.ny;
     const NodeGeom g = geometry(c, x, y, !raw);
     R qf[9], qh[9];
     RH qg[9];
-    if (raw) gather<Lay, R, RH, false>(c, src, stride, g, x, y, qf, qg, qh);
-    else gather<Lay, R, RH, true>(c, src, stride, g, x, y, qf, qg, qh);
+    if (raw) gather<Lay, R, RH, false>(c, src, g, x, y, qf, qg, qh);
+    else gather<Lay, R, RH, true>(c, src, g, x, y, qf, qg, qh);
     bool finite = true;
 #pragma unroll
     for (int i = 0; i < 9; ++i)
@@ -1191,8 +1231,7 @@ LBM_HD void macro_node(const CavityConst<R> &c, const void *src, int64_t stride,
 // given temperatures, stored as offsets; the previous-step source equals the
 // current one.
 template <class Lay, typename R, typename RH>
-LBM_HD void init_node(const CavityConst<R> &c, void *dst, int64_t stride, R *sr, int x, int y, double Tf,
-                      double Tm) {
+LBM_HD void init_node(const CavityConst<R> &c, void *dst, R *sr, int x, int y, double Tf, double Tm) {
     const ThermalConst<double> &t = c.td;
     const int nx = c.nx;
     const bool wall = (!c.periodic && (x == 0 || x == nx - 1)) || y == 0 || y == c.ny - 1;
@@ -1219,11 +1258,13 @@ LBM_HD void init_node(const CavityConst<R> &c, void *dst, int64_t stride, R *sr,
         qg[i] = (RH)(i == 0 ? dH - wrest * cf * dT : wi * cf * dT);
         qh[i] = (R)(i == 0 ? (cpm - wrest * cm) * dTm : wi * cm * dTm);
     }
-    const int64_t k = c.node0 + (int64_t)y * nx + x;
-    Lay::template store<R>(dst, stride, 0, qf, R(0), k, c);
-    Lay::template store<RH>(dst, stride, 1, qg, (RH)(cf * dT), k, c);
-    Lay::template store<R>(dst, stride, 2, qh, (R)(cm * dTm), k, c);
-    sr[k] = (R)((double)c.hv_f * (Tm - Tf));
+    const FarRef k = any_band(c)(x, y);
+    void *blk = band_block(c, dst, 0);
+    const int64_t stride = c.band_nodes;
+    Lay::template store<R>(blk, stride, 0, qf, R(0), k, c);
+    Lay::template store<RH>(blk, stride, 1, qg, (RH)(cf * dT), k, c);
+    Lay::template store<R>(blk, stride, 2, qh, (R)(cm * dTm), k, c);
+    sr[flat_index(c, x, y)] = (R)((double)c.hv_f * (Tm - Tf));
 }
 
 }  // namespace lbm

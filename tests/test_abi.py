@@ -89,7 +89,7 @@ def test_host_validation_rejects_bad_sets():
            dict(base, thermal_lattice=5, varpi=1.5), dict(base, thermal_collision=1, zeta_e=1.0),
            dict(base, wall_type=(3, 0, 0, 0)),
            dict(base, bc_x=1, wall_type=(1, 0, 0, 0)), dict(base, solid_treatment=2),
-           dict(base, nx=4194305, ny=4)]
+           dict(base, nx=262145, ny=4)]
     for q in bad:
         with pytest.raises(lbm.LbmError) as e:
             lbm.lbm_lattice_of(q, "f32")
