@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--forms", action="store_true", help="also time the 16-bit and batched forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB device-to-device copy 3 times (counter calibration)")
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration and its bandwidth)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -182,8 +182,17 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        # the same copy timed: the practical HBM ceiling of a pure stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
         print(json.dumps({"calibration": "copy", "bytes_read_per_copy": src.numel() * 4,
-                          "bytes_written_per_copy": dst.numel() * 4, "copies": 3}))
+                          "bytes_written_per_copy": dst.numel() * 4, "copies": 13,
+                          "copy_GBps": 2 * src.numel() * 4 / (ms * 1e-3) / 1e9}))
         return
     from paper_1701_00702_amd import lbm
     import lbm_workloads as W

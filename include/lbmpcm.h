@@ -183,10 +183,9 @@ typedef struct lbm_launch_config {
                                  through LDS (2-D tiles with a one-node ring,
                                  the state crosses HBM once per two steps;
                                  LBM_F64, LBM_F32 and LBM_F32_H64).  Default 2
-                                 for LBM_F32, LBM_F32_H64 (and LBM_F64 on
-                                 D2Q5) when every
-                                 cavity's rows are 32-node aligned
-                                 (nx % 32 == 0) or at least 1024 wide, else 1.
+                                 for these forms when every cavity's rows
+                                 are 32-node aligned (nx % 32 == 0) or at
+                                 least 1024 wide, else 1.
                                  block and nodes_per_thread then do not apply. */
 } lbm_launch_config;
 

@@ -822,13 +822,12 @@ lbm_status setup(lbm_handle *h) {
         HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     }
-    // Two steps per launch by default where it measured faster: the FP32
-    // forms and D2Q5 in FP64 (D2Q9 in FP64 holds too few waves per SIMD to
-    // hide the first update's loads), with every cavity's rows 32-node
-    // aligned or at least 1024 nodes wide.  Batches of narrow, unaligned
-    // cavities (a tile row then writes partial cache lines shared with its
-    // neighbour) stay at one step per launch.
-    bool two = h->pl.tiles2 > 0 && h->st != ST_F64;
+    // Two steps per launch by default where it measured faster: every form
+    // that has the two-step kernel, with every cavity's rows 32-node aligned
+    // or at least 1024 nodes wide.  Batches of narrow, unaligned cavities (a
+    // tile row then writes partial cache lines shared with its neighbour)
+    // stay at one step per launch.
+    bool two = h->pl.tiles2 > 0;
     for (int c = 0; c < h->n; ++c)
         if (!(h->params[c].nx % 32 == 0 || h->params[c].nx >= 1024)) two = false;
     h->lc.steps_per_launch = two ? 2 : 1;
