@@ -135,6 +135,12 @@ typedef struct lbm_params {
                                   with f_l < 0.5 reflects its flow populations
                                   and is at rest, other nodes collide their
                                   unblended f+                                */
+    int32_t band_rows;         /* storage only: rows per band of the state
+                                  blocks; 0: automatic (about 256 MiB of
+                                  state per band); else at least
+                                  max(32, ceil(2048 / nx) + 4), at most ny
+                                  (larger values take ny).  Results do not
+                                  depend on it.                               */
 } lbm_params;
 
 /* Derived lattice constants of one cavity (read-only view). */

@@ -26,7 +26,7 @@ PARAM_FIELDS = (
     "F_phi", "dp_over_L", "k_f", "cf_ref", "cm_ref", "J",
     "T_hot", "T_cold", "T_init", "T_solidus", "T_liquidus",
     "thermal_lattice", "thermal_collision", "varpi", "zeta_e", "wall_type", "wall_T", "L_char",
-    "solid_treatment",
+    "solid_treatment", "band_rows",
 )
 
 _DEFAULTS = dict(
@@ -50,6 +50,7 @@ _DEFAULTS = dict(
     wall_T=(0.0, 0.0, 0.0, 0.0),
     L_char=0.0,             # <= 0: nx - 1 (periodic channel: ny - 1)
     solid_treatment=0,      # 0: volumetric scheme (Eq. 20); 1: bounce-back (Sec. V B)
+    band_rows=0,            # storage only (GPU library): rows per state band, 0 automatic
 )
 
 

@@ -77,11 +77,19 @@ double char_length(const lbm_params &p) {
     return p.bc_x == 1 ? p.ny - 1.0 : p.nx - 1.0;
 }
 
+// Fewest rows a band may hold: any step-kernel tile (a two-step tile of at
+// most 20 rows plus 4 rows of pulls, or a one-step tile of at most 2048
+// nodes plus a row of pulls either side) then spans at most two bands.
+int min_band_rows(int nx) { return std::max(LBM_MIN_BAND_ROWS, (2048 + nx - 1) / nx + 4); }
+
 lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     if (p.nx < 4 || p.ny < 4) return fail(LBM_EINVAL, "grid %dx%d: each side needs >= 4 nodes", p.nx, p.ny);
     // the step kernels address a tile's rows by 32-bit byte offsets from its
     // first row: a few dozen rows of 8-byte elements must stay below 2^31
     if (p.nx > LBM_MAX_NX) return fail(LBM_EINVAL, "grid %dx%d: rows longer than %d nodes", p.nx, p.ny, LBM_MAX_NX);
+    if (p.band_rows < 0 || (p.band_rows > 0 && p.band_rows < min_band_rows(p.nx) && p.band_rows < p.ny))
+        return fail(LBM_EINVAL, "band_rows %d: need 0 or at least %d (or the cavity's %d rows)", p.band_rows,
+                    min_band_rows(p.nx), p.ny);
     if ((int64_t)p.nx * p.ny > (int64_t)1 << 31)
         return fail(LBM_EINVAL, "cavity of %dx%d nodes exceeds 2^31 nodes", p.nx, p.ny);
     if (p.bc_x != 0 && p.bc_x != 1) return fail(LBM_EINVAL, "bc_x must be 0 or 1");
@@ -290,14 +298,14 @@ struct Bands {
     int count;      // number of bands
 };
 
-// Rows per band: about LBM_BAND_BYTES of state per block, at least enough
-// rows for any step-kernel tile to span at most two bands, at most the
-// cavity.  The plane stride is a multiple of 128 nodes, so every plane of
+// Rows per band: about LBM_BAND_BYTES of state per block (or the rows the
+// caller asked for), at least min_band_rows, at most the cavity.  The plane stride is a multiple of 128 nodes, so every plane of
 // every block starts 256-byte aligned.
-Bands bands_of(int nx, int ny, int bpn, int64_t off) {
+Bands bands_of(int nx, int ny, int bpn, int64_t off, int rows_wanted) {
     Bands b;
     int64_t rows = LBM_BAND_BYTES / ((int64_t)bpn * nx);
-    rows = std::max<int64_t>(rows, std::max<int64_t>(LBM_MIN_BAND_ROWS, (2048 + nx - 1) / nx + 4));
+    rows = std::max<int64_t>(rows, min_band_rows(nx));
+    if (rows_wanted > 0) rows = rows_wanted;
     b.rows = (int)std::min<int64_t>(rows, ny);
     b.nodes = ((int64_t)b.rows * nx + 127) & ~(int64_t)127;
     b.bytes = (int64_t)bpn * b.nodes;
@@ -377,7 +385,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // checkpoints compare parameters byte for byte.
 lbm_params normalized(const lbm_params &p) {
     lbm_params q = p;
-    const size_t end = offsetof(lbm_params, solid_treatment) + sizeof(q.solid_treatment);
+    const size_t end = offsetof(lbm_params, band_rows) + sizeof(q.band_rows);
     std::memset((char *)&q + end, 0, sizeof(q) - end);
     return q;
 }
@@ -505,7 +513,7 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     const int st = pl.st;
     pl.stride = (pl.nodes + 127) & ~(int64_t)127;
     for (int c = 0; c < n; ++c) {
-        const Bands b = bands_of(p[c].nx, p[c].ny, bytes_per_node(st), pl.pop_bytes);
+        const Bands b = bands_of(p[c].nx, p[c].ny, bytes_per_node(st), pl.pop_bytes, p[c].band_rows);
         // the step kernels' 32-bit offsets within two consecutive blocks
         if (b.nodes * (bytes_per_node(st) + 8) >= ((int64_t)1 << 31))
             return fail(LBM_EINVAL, "cavity %d: rows of %d nodes are too long", c, p[c].nx);

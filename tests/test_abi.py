@@ -124,3 +124,18 @@ def test_workspace_plan_sizes():
     b5 = lbm.lbm_workspace_bytes(q5, "f32")
     assert b5 >= 2 * 19 * 4 * n and b32 - b5 >= 2 * 8 * 4 * n * 0.99
     assert lbm.state_bytes_per_node("f32h64", 5) == 80 and lbm.state_bytes_per_node("f64", 5) == 152
+
+
+def test_band_rows_validation_and_sizes():
+    """Storage bands: 0 (automatic), at least max(32, ceil(2048 / nx) + 4)
+    rows, or the whole cavity; a cut layout never needs less memory."""
+    from paper_1701_00702_amd import lbm
+    p = W.case_c1()[0]                                   # 64 x 64: minimum 36 rows
+    b_one = lbm.lbm_workspace_bytes(dict(p, band_rows=64), "f32")
+    b_cut = lbm.lbm_workspace_bytes(dict(p, band_rows=36), "f32")
+    assert b_cut >= b_one == lbm.lbm_workspace_bytes(p, "f32")
+    assert lbm.lbm_workspace_bytes(dict(p, band_rows=500), "f32") == b_one   # clipped to ny
+    for bad in (-1, 5, 35):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_workspace_bytes(dict(p, band_rows=bad), "f32")
+        assert e.value.status == lbm.LBM_EINVAL
