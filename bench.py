@@ -84,7 +84,7 @@ def traffic_from_profile(sha: str, workload_name: str, precision: str, thermal_l
     """HBM bytes per launch measured with rocprofv3 counters, if the summary
     in profiles/ was taken on the current kernel source."""
     tag = f"{workload_name}_d2q5_{precision}" if thermal_lattice == 5 else f"{workload_name}_{precision}"
-    kernel = "step2_kernel" if steps_per_launch == 2 else "step_kernel"
+    kernel = f"stepk_kernel_k{steps_per_launch}" if steps_per_launch > 1 else "step_kernel"
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{tag}.md")
     if not os.path.exists(path):
         return None
@@ -161,8 +161,8 @@ def main():
     ap.add_argument("--npt", type=int, default=1)
     ap.add_argument("--xcd", type=int, default=1)
     ap.add_argument("--persistent", type=int, default=0)
-    ap.add_argument("--steps-per-launch", type=int, default=0, choices=[0, 1, 2],
-                    help="0: the library's default (two steps per launch through LDS where available)")
+    ap.add_argument("--steps-per-launch", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="0: the library's default (several steps per launch through LDS where available)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--forms", action="store_true", help="also time the 16-bit and batched forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -222,7 +222,7 @@ def main():
     ms_step = ms / args.steps
     mlups = nodes / (ms_step * 1e-3) / 1e6
     # A launch reads and writes the state once, whether it advances one step
-    # or two (through LDS); the roofline is per launch.
+    # or several (through LDS); the roofline is per launch.
     spl = launch["steps_per_launch"]
     alg = bytes_per_node(prec, qt) * nodes
     launch_ms = ms_step * spl
@@ -230,7 +230,7 @@ def main():
     sha = kernel_sha()
     traffic = traffic_from_profile(sha, args.workload, prec, qt, spl)
     single = None
-    if spl == 2:
+    if spl > 1:
         # the one-step kernel on the same state, for reference
         lbm.lbm_set_launch(s.h, launch["block"], launch["nodes_per_thread"], launch["xcd_remap"],
                            launch["persistent"], steps_per_launch=1)
@@ -244,14 +244,17 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
         "config": {"workload": desc, "nodes": nodes, "storage": prec, "thermal_lattice": qt, "launch": launch,
                    "seed": seed,
-                   "step_kernel": ("lbm::step2_kernel (two fused steps per launch through LDS tiles)"
-                                   if launch["steps_per_launch"] == 2 else
+                   "step_kernel": (f"lbm::stepk_kernel ({launch['steps_per_launch']} fused steps per launch "
+                                   "through LDS tiles)" if launch["steps_per_launch"] > 1 else
                                    "lbm::step_kernel (fused pull-stream + NEE walls + 3 MRT collisions)")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBPS,
                      "traffic": None if traffic is None else traffic,
                      "algorithmic_bytes_per_launch": alg, "steps_per_launch": spl,
-                     "launch_ms": launch_ms, "kernel_sha": sha},
+                     "launch_ms": launch_ms, "kernel_sha": sha,
+                     # the bytes a one-step sweep would move per step, over the
+                     # measured time per step (above peak: temporal blocking)
+                     "per_step_equivalent_GBps": alg / (ms_step * 1e-3) / 1e9},
         "check": {"nonfinite": d["nonfinite"], "liquid_fraction": d["liquid_fraction"],
                   "energy_residual_rel": d["energy_residual"] / max(abs(d["E_int"]), 1e-300)},
     }

@@ -188,8 +188,10 @@ typedef struct lbm_launch_config {
     int32_t steps_per_launch; /* 1: one step per launch; 2: two steps per launch
                                  through LDS (2-D tiles with a one-node ring,
                                  the state crosses HBM once per two steps;
-                                 LBM_F64, LBM_F32 and LBM_F32_H64).  Default 2
-                                 for these forms when every cavity's rows
+                                 LBM_F64, LBM_F32 and LBM_F32_H64); 3: three
+                                 steps per launch (a two-node ring; LBM_F32
+                                 and LBM_F32_H64).  Default: the most of
+                                 these the form has when every cavity's rows
                                  are 32-node aligned (nx % 32 == 0) or at
                                  least 1024 wide, else 1.
                                  block and nodes_per_thread then do not apply. */

@@ -472,8 +472,9 @@ struct Plan {
     // nodes: packed index range of the flat per-node arrays (stride each)
     int64_t nodes = 0, stride = 0, slots = 0, max_nodes = 0;
     int max_tiles = 0;
-    int64_t tiles2 = 0;  // tiles of the two-step kernel (0: not available for this storage)
-    size_t off_tiles2 = 0;
+    // tiles of the K-step kernels, K = 2, 3 (0: not available for this storage)
+    int64_t tilesk[4] = {0, 0, 0, 0};
+    size_t off_tilesk[4] = {0, 0, 0, 0};
     size_t off_pop[2], off_sr[2], off_acc, off_accs, off_cav, off_tiles, off_fields, off_part,
         off_out, total;
 };
@@ -537,13 +538,14 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     off = align256(off + (size_t)n * std::max(sizeof(CavityConst<double>), sizeof(CavityConst<float>)));
     pl.off_tiles = off;
     off = align256(off + (size_t)pl.max_tiles * sizeof(Tile));
-    if (step2_supported(st)) {
+    for (int k = 2; k <= 3; ++k) {
+        if (!stepk_supported(st, k)) continue;
         int tw, th;
-        step2_tile(st, &tw, &th);
-        for (int c = 0; c < n; ++c) pl.tiles2 += count_tiles2(p[c].nx, p[c].ny, tw, th);
-        if (pl.tiles2 >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
-        pl.off_tiles2 = off;
-        off = align256(off + (size_t)pl.tiles2 * sizeof(Tile2));
+        stepk_tile(st, k, &tw, &th);
+        for (int c = 0; c < n; ++c) pl.tilesk[k] += count_tiles2(p[c].nx, p[c].ny, tw, th);
+        if (pl.tilesk[k] >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
+        pl.off_tilesk[k] = off;
+        off = align256(off + (size_t)pl.tilesk[k] * sizeof(Tile2));
     }
     pl.off_fields = off;
     off = align256(off + (size_t)6 * pl.max_nodes * sizeof(double));
@@ -583,8 +585,8 @@ struct lbm_handle {
     int graph_chunk = 32;  // launches per captured graph
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipGraph_t gsrc[2] = {nullptr, nullptr};
-    hipGraphExec_t graph2[2] = {nullptr, nullptr};  // two-step launches
-    hipGraph_t gsrc2[2] = {nullptr, nullptr};
+    hipGraphExec_t graphk[4][2] = {};  // K-step launches, K = 2, 3
+    hipGraph_t gsrck[4][2] = {};
 
     void *pop(int b) { return ws + pl.off_pop[b]; }
     void *sr(int b) { return ws + pl.off_sr[b]; }
@@ -592,7 +594,7 @@ struct lbm_handle {
     double *acc_scratch() { return (double *)(ws + pl.off_accs); }
     void *cav() { return ws + pl.off_cav; }
     Tile *dtiles() { return (Tile *)(ws + pl.off_tiles); }
-    Tile2 *dtiles2() { return (Tile2 *)(ws + pl.off_tiles2); }
+    Tile2 *dtilesk(int k) { return (Tile2 *)(ws + pl.off_tilesk[k]); }
     double *fields() { return (double *)(ws + pl.off_fields); }
     double *partials() { return (double *)(ws + pl.off_part); }
     double *dout() { return (double *)(ws + pl.off_out); }
@@ -604,23 +606,30 @@ void drop_graphs(lbm_handle *h) {
     for (int b = 0; b < 2; ++b) {
         if (h->graph[b]) (void)hipGraphExecDestroy(h->graph[b]);
         if (h->gsrc[b]) (void)hipGraphDestroy(h->gsrc[b]);
-        if (h->graph2[b]) (void)hipGraphExecDestroy(h->graph2[b]);
-        if (h->gsrc2[b]) (void)hipGraphDestroy(h->gsrc2[b]);
-        h->graph[b] = h->graph2[b] = nullptr;
-        h->gsrc[b] = h->gsrc2[b] = nullptr;
+        h->graph[b] = nullptr;
+        h->gsrc[b] = nullptr;
+        for (int k = 2; k <= 3; ++k) {
+            if (h->graphk[k][b]) (void)hipGraphExecDestroy(h->graphk[k][b]);
+            if (h->gsrck[k][b]) (void)hipGraphDestroy(h->gsrck[k][b]);
+            h->graphk[k][b] = nullptr;
+            h->gsrck[k][b] = nullptr;
+        }
     }
 }
 
-// Tile table of the two-step kernel (fixed per storage form).
-lbm_status build_tiles2(lbm_handle *h) {
-    if (!h->pl.tiles2) return LBM_OK;
-    int tw, th;
-    step2_tile(h->st, &tw, &th);
-    std::vector<Tile2> t;
-    for (int c = 0; c < h->n; ++c) cavity_tiles2(c, h->params[c].nx, h->params[c].ny, tw, th, t);
-    if ((int64_t)t.size() != h->pl.tiles2) return fail(LBM_EINVAL, "two-step tile table mismatch");
-    HIP_TRY(hipMemcpyAsync(h->dtiles2(), t.data(), t.size() * sizeof(Tile2), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+// Tile tables of the K-step kernels (fixed per storage form).
+lbm_status build_tilesk(lbm_handle *h) {
+    for (int k = 2; k <= 3; ++k) {
+        if (!h->pl.tilesk[k]) continue;
+        int tw, th;
+        stepk_tile(h->st, k, &tw, &th);
+        std::vector<Tile2> t;
+        for (int c = 0; c < h->n; ++c) cavity_tiles2(c, h->params[c].nx, h->params[c].ny, tw, th, t);
+        if ((int64_t)t.size() != h->pl.tilesk[k]) return fail(LBM_EINVAL, "K-step tile table mismatch");
+        HIP_TRY(hipMemcpyAsync(h->dtilesk(k), t.data(), t.size() * sizeof(Tile2), hipMemcpyHostToDevice,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
     return LBM_OK;
 }
 
@@ -649,18 +658,21 @@ lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
     return LBM_OK;
 }
 
-// two_step: the plan has the two-step kernel's tiles
-bool valid_launch(const lbm_launch_config &lc, bool two_step) {
+// whether the plan has the tiles of K steps per launch
+bool has_k(const Plan &pl, int k) { return k == 1 || ((k == 2 || k == 3) && pl.tilesk[k] > 0); }
+
+bool valid_launch(const lbm_launch_config &lc, const Plan &pl) {
     const bool b = lc.block == 64 || lc.block == 128 || lc.block == 256 || lc.block == 512;
     const bool n = lc.nodes_per_thread == 1 || lc.nodes_per_thread == 2 || lc.nodes_per_thread == 4;
-    const bool t = lc.steps_per_launch == 1 || (lc.steps_per_launch == 2 && two_step);
+    const bool t = has_k(pl, lc.steps_per_launch);
     return b && n && t && (lc.xcd_remap == 0 || lc.xcd_remap == 1) && lc.persistent >= 0 && lc.persistent <= 64;
 }
 
-Step2Launch step2_args(lbm_handle *h, int src_buf, double *acc, const lbm_launch_config &lc) {
+Step2Launch stepk_args(lbm_handle *h, int k, int src_buf, double *acc, const lbm_launch_config &lc) {
     Step2Launch L;
     L.storage = h->st;
-    const int nt = (int)h->pl.tiles2;
+    L.steps = k;
+    const int nt = (int)h->pl.tilesk[k];
     L.grid = lc.persistent > 0 ? std::min(nt, h->n_cu * lc.persistent) : nt;
     L.xcd_remap = lc.xcd_remap;
     L.src = h->pop(src_buf);
@@ -669,7 +681,7 @@ Step2Launch step2_args(lbm_handle *h, int src_buf, double *acc, const lbm_launch
     L.sr_dst = h->sr(1 - src_buf);
     L.acc = acc;
     L.cav = h->cav();
-    L.tiles = h->dtiles2();
+    L.tiles = h->dtilesk(k);
     L.ntiles = nt;
     return L;
 }
@@ -700,15 +712,16 @@ lbm_status launch_one(lbm_handle *h, hipStream_t s, int pull, int src_buf) {
     return LBM_OK;
 }
 
-lbm_status build_graph(lbm_handle *h, int parity, bool two) {
+// Graph of graph_chunk launches of K steps each (K = 1: the one-step kernel).
+lbm_status build_graph(lbm_handle *h, int parity, int kk) {
     if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     int b = parity;
     for (int k = 0; k < h->graph_chunk; ++k) {
         hipError_t e;
-        if (two) {
-            Step2Launch L = step2_args(h, b, h->acc(), h->lc);
-            e = launch_step2(L, h->cap);
+        if (kk > 1) {
+            Step2Launch L = stepk_args(h, kk, b, h->acc(), h->lc);
+            e = launch_stepk(L, h->cap);
         } else {
             StepLaunch L = step_args(h, 1, b, h->acc(), 0, (int)h->tiles.size(), h->lc);
             e = launch_step(L, h->cap);
@@ -721,8 +734,8 @@ lbm_status build_graph(lbm_handle *h, int parity, bool two) {
         }
         b ^= 1;
     }
-    hipGraph_t *src = two ? &h->gsrc2[parity] : &h->gsrc[parity];
-    hipGraphExec_t *ex = two ? &h->graph2[parity] : &h->graph[parity];
+    hipGraph_t *src = kk > 1 ? &h->gsrck[kk][parity] : &h->gsrc[parity];
+    hipGraphExec_t *ex = kk > 1 ? &h->graphk[kk][parity] : &h->graph[parity];
     HIP_TRY(hipStreamEndCapture(h->cap, src));
     HIP_TRY(hipGraphInstantiate(ex, *src, nullptr, nullptr, 0));
     return LBM_OK;
@@ -732,10 +745,10 @@ lbm_status build_graph(lbm_handle *h, int parity, bool two) {
 // every change of launch shape), so that no lbm_step spends host time on
 // capture and instantiation while the device waits.
 lbm_status prepare_graphs(lbm_handle *h) {
-    const bool two = h->lc.steps_per_launch == 2;
+    const int kk = h->lc.steps_per_launch;
     for (int parity = 0; parity < 2; ++parity) {
-        if (two ? h->graph2[parity] : h->graph[parity]) continue;
-        lbm_status s = build_graph(h, parity, two);
+        if (kk > 1 ? h->graphk[kk][parity] : h->graph[parity]) continue;
+        lbm_status s = build_graph(h, parity, kk);
         if (s != LBM_OK) return s;
     }
     return LBM_OK;
@@ -830,18 +843,18 @@ lbm_status setup(lbm_handle *h) {
         HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     }
-    // Two steps per launch by default where it measured faster: every form
-    // that has the two-step kernel, with every cavity's rows 32-node aligned
-    // or at least 1024 nodes wide.  Batches of narrow, unaligned cavities (a
-    // tile row then writes partial cache lines shared with its neighbour)
-    // stay at one step per launch.
-    bool two = h->pl.tiles2 > 0;
+    // Several steps per launch by default where it measured faster: three
+    // where the three-step kernel exists (the FP32 forms), else two, with
+    // every cavity's rows 32-node aligned or at least 1024 nodes wide.
+    // Batches of narrow, unaligned cavities (a tile row then writes partial
+    // cache lines shared with its neighbour) stay at one step per launch.
+    bool multi = true;
     for (int c = 0; c < h->n; ++c)
-        if (!(h->params[c].nx % 32 == 0 || h->params[c].nx >= 1024)) two = false;
-    h->lc.steps_per_launch = two ? 2 : 1;
+        if (!(h->params[c].nx % 32 == 0 || h->params[c].nx >= 1024)) multi = false;
+    h->lc.steps_per_launch = !multi ? 1 : (h->pl.tilesk[3] > 0 ? 3 : (h->pl.tilesk[2] > 0 ? 2 : 1));
     lbm_status s = build_tiles(h, h->lc);
     if (s != LBM_OK) return s;
-    s = build_tiles2(h);
+    s = build_tilesk(h);
     if (s != LBM_OK) return s;
     h->E0.assign(h->n, 0.0);
     h->M0.assign(h->n, 0.0);
@@ -975,27 +988,36 @@ extern "C" lbm_status lbm_step(lbm_handle *h, int64_t n) {
         h->step += 1;
         n -= 1;
     }
-    if (h->lc.steps_per_launch == 2) {
-        // pairs of steps, one launch each (a launch swaps the buffers once)
-        while (n >= 2 * (int64_t)h->graph_chunk && h->graph_chunk > 0) {
-            if (!h->graph2[h->cur]) {
-                lbm_status s = build_graph(h, h->cur, true);
+    const int kk = h->lc.steps_per_launch;
+    if (kk > 1) {
+        // runs of kk steps, one launch each (a launch swaps the buffers once)
+        while (n >= (int64_t)kk * h->graph_chunk && h->graph_chunk > 0) {
+            if (!h->graphk[kk][h->cur]) {
+                lbm_status s = build_graph(h, h->cur, kk);
                 if (s != LBM_OK) return s;
             }
-            HIP_TRY(hipGraphLaunch(h->graph2[h->cur], h->stream));
-            h->step += 2 * (int64_t)h->graph_chunk;
-            n -= 2 * (int64_t)h->graph_chunk;
+            HIP_TRY(hipGraphLaunch(h->graphk[kk][h->cur], h->stream));
+            h->step += (int64_t)kk * h->graph_chunk;
+            n -= (int64_t)kk * h->graph_chunk;
         }
-        for (; n >= 2; n -= 2) {
-            Step2Launch L = step2_args(h, h->cur, h->acc(), h->lc);
-            HIP_TRY(launch_step2(L, h->stream));
+        for (; n >= kk; n -= kk) {
+            Step2Launch L = stepk_args(h, kk, h->cur, h->acc(), h->lc);
+            HIP_TRY(launch_stepk(L, h->stream));
+            h->cur ^= 1;
+            h->step += kk;
+        }
+        // two steps left of three-step runs: one two-step launch
+        if (n == 2 && kk == 3 && h->pl.tilesk[2] > 0) {
+            Step2Launch L = stepk_args(h, 2, h->cur, h->acc(), h->lc);
+            HIP_TRY(launch_stepk(L, h->stream));
             h->cur ^= 1;
             h->step += 2;
+            n -= 2;
         }
     }
     while (n >= h->graph_chunk && h->graph_chunk > 0) {
         if (!h->graph[h->cur]) {
-            lbm_status s = build_graph(h, h->cur, false);
+            lbm_status s = build_graph(h, h->cur, 1);
             if (s != LBM_OK) return s;
         }
         HIP_TRY(hipGraphLaunch(h->graph[h->cur], h->stream));
@@ -1149,7 +1171,7 @@ extern "C" lbm_status lbm_get_launch(const lbm_handle *h, lbm_launch_config *out
 
 extern "C" lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg) {
     if (!h || !cfg) return fail(LBM_EINVAL, "NULL argument");
-    if (!valid_launch(*cfg, h->pl.tiles2 > 0))
+    if (!valid_launch(*cfg, h->pl))
         return fail(LBM_EINVAL, "unsupported launch shape block=%d npt=%d xcd=%d persistent=%d steps=%d",
                     cfg->block, cfg->nodes_per_thread, cfg->xcd_remap, cfg->persistent, cfg->steps_per_launch);
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1186,7 +1208,7 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
             lbm_launch_config lc;
             while (fscanf(f, "%255s %d %d %d %d %d", k, &lc.block, &lc.nodes_per_thread, &lc.xcd_remap,
                           &lc.persistent, &lc.steps_per_launch) == 6) {
-                if (key == k && valid_launch(lc, h->pl.tiles2 > 0)) {
+                if (key == k && valid_launch(lc, h->pl)) {
                     fclose(f);
                     lbm_status s = lbm_set_launch(h, &lc);
                     if (s == LBM_OK && chosen) *chosen = lc;
@@ -1209,11 +1231,11 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
     // Every trial reads the live buffer and writes only the other buffer and
     // scratch tallies; times are per step.
     auto trial = [&](const lbm_launch_config &lc, float *ms_per_step) -> lbm_status {
-        if (lc.steps_per_launch == 2) {
-            Step2Launch L = step2_args(h, h->cur, h->acc_scratch(), lc);
-            HIP_TRY(launch_step2(L, h->stream));
+        if (lc.steps_per_launch > 1) {
+            Step2Launch L = stepk_args(h, lc.steps_per_launch, h->cur, h->acc_scratch(), lc);
+            HIP_TRY(launch_stepk(L, h->stream));
             HIP_TRY(hipEventRecord(e0, h->stream));
-            for (int k = 0; k < steps; ++k) HIP_TRY(launch_step2(L, h->stream));
+            for (int k = 0; k < steps; ++k) HIP_TRY(launch_stepk(L, h->stream));
         } else {
             lbm_status s = build_tiles(h, lc);
             if (s != LBM_OK) return s;
@@ -1242,11 +1264,12 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
                         best = lc;
                     }
                 }
-    if (h->pl.tiles2 > 0) {
-        const lbm_launch_config one = best;
+    const lbm_launch_config one = best;
+    for (int kk = 2; kk <= 3; ++kk) {
+        if (!has_k(h->pl, kk)) continue;
         for (int xr : xcds)
             for (int pp : pers) {
-                lbm_launch_config lc{one.block, one.nodes_per_thread, xr, pp, 2};
+                lbm_launch_config lc{one.block, one.nodes_per_thread, xr, pp, kk};
                 float ms;
                 lbm_status s = trial(lc, &ms);
                 if (s != LBM_OK) return s;

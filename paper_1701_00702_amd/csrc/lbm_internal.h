@@ -108,7 +108,7 @@ struct StepLaunch {
     int ntiles;
 };
 
-// A tile of the two-steps-per-launch kernel: w x h nodes of one cavity at
+// A tile of the K-steps-per-launch kernels: w x h nodes of one cavity at
 // (x0, y0); no tile starts on the last column or row of its cavity.
 struct Tile2 {
     int32_t cav, x0, y0, w, h;
@@ -116,6 +116,7 @@ struct Tile2 {
 
 struct Step2Launch {
     int storage;
+    int steps;  // K: 2 or 3 steps per launch
     int grid, xcd_remap;
     const void *src;
     void *dst;
@@ -172,9 +173,9 @@ struct InitLaunch {
 };
 
 hipError_t launch_step(const StepLaunch &L, hipStream_t s);
-hipError_t launch_step2(const Step2Launch &L, hipStream_t s);
-bool step2_supported(int storage);
-void step2_tile(int storage, int *tw, int *th);  // tile shape of the two-step kernel
+hipError_t launch_stepk(const Step2Launch &L, hipStream_t s);
+bool stepk_supported(int storage, int k);                // K steps per launch (K = 2, 3)
+void stepk_tile(int storage, int k, int *tw, int *th);  // tile shape of the K-step kernel
 hipError_t launch_macro(const MacroLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_init(const InitLaunch &L, int nx, int ny, hipStream_t s);

@@ -222,27 +222,37 @@ struct Step2Tile<ST5_F64> {  // 19 x 8 + 8 = 160 B per slot, 18 x 22 slots
 // the persistent launch.  Without the loop nothing in the tile's code is
 // loop-invariant, so the compiler does not keep the 27 plane addresses live
 // across iterations (they would spill to vector registers).
-template <class Lay, typename R, typename RH, int TW, int TH, int NT>
-__device__ __forceinline__ void step2_advance(const void *__restrict__ src, void *__restrict__ dst,
-                                              const R *__restrict__ sr_src,
-                                              R *__restrict__ sr_dst, double *__restrict__ acc,
-                                              const CavityConst<R> *__restrict__ cav, const Tile2 &tl,
-                                              void *lds_q, R *lds_sr) {
+template <class Lay, typename R, typename RH, int TW, int TH, int NT, int K>
+__device__ __forceinline__ void stepk_advance(const void *__restrict__ src, void *__restrict__ dst,
+                                              const R *__restrict__ sr_src, R *__restrict__ sr_dst,
+                                              double *__restrict__ acc, const CavityConst<R> *__restrict__ cav,
+                                              const Tile2 &tl, void *lds_q, R *lds_sr) {
+    using Sh = StepKShape<Lay, TW, TH, K>;
     const CavityConst<R> &c = cav[tl.cav];
-    // NT >= NSLOT: each thread advances at most one slot per update
+    // NT >= NSLOT: each thread advances at most one node per update
     const int s = (int)threadIdx.x;
-    if (s < (TW + 2) * (tl.h + 2)) step2_phase1<Lay, R, RH, TW, TH>(c, tl, src, sr_src, acc, lds_q, lds_sr, s);
+    if (s < Sh::LW * (tl.h + 2 * Sh::RING))
+        stepk_first<Lay, R, RH, TW, TH, K>(c, tl, src, sr_src, acc, lds_q, lds_sr, s);
     __syncthreads();
-    if (s < TW * tl.h) step2_phase2<Lay, R, RH, TW, TH>(c, tl, dst, sr_dst, acc, lds_q, lds_sr, s);
+#pragma unroll
+    for (int j = K - 2; j >= 1; --j) {
+        MidNode<R, RH> n;
+        const bool act = s < (TW + 2 * j) * (tl.h + 2 * j) &&
+                         stepk_mid_load<Lay, R, RH, TW, TH, K>(c, tl, j, lds_q, lds_sr, s, n);
+        __syncthreads();  // every pull of this update is in registers
+        if (act) stepk_mid_store<Lay, R, RH, TW, TH, K>(c, acc, lds_q, lds_sr, n);
+        __syncthreads();
+    }
+    if (s < TW * tl.h) stepk_last<Lay, R, RH, TW, TH, K>(c, tl, dst, sr_dst, acc, lds_q, lds_sr, s);
 }
 
-template <class Lay, typename R, typename RH, int TW, int TH, int NT, bool LOOP>
-__global__ __launch_bounds__(NT) void step2_kernel(const void *__restrict__ src, void *__restrict__ dst,
+template <class Lay, typename R, typename RH, int TW, int TH, int NT, int K, bool LOOP>
+__global__ __launch_bounds__(NT) void stepk_kernel(const void *__restrict__ src, void *__restrict__ dst,
                                                    const R *__restrict__ sr_src,
                                                    R *__restrict__ sr_dst, double *__restrict__ acc,
                                                    const CavityConst<R> *__restrict__ cav,
                                                    const Tile2 *__restrict__ tiles, int ntiles, int xcd_remap) {
-    using Sh = Step2Shape<Lay, TW, TH>;
+    using Sh = StepKShape<Lay, TW, TH, K>;
     static_assert(Sh::LDS_BYTES + Sh::NSLOT * sizeof(R) <= 65536, "tile exceeds 64 KiB of LDS");
     static_assert(NT >= Sh::NSLOT && NT % 64 == 0, "one thread per slot of the first update");
     __shared__ __align__(16) unsigned char lds_q[Sh::LDS_BYTES];
@@ -250,58 +260,127 @@ __global__ __launch_bounds__(NT) void step2_kernel(const void *__restrict__ src,
     const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
     if (!LOOP) {
         if (b < ntiles)
-            step2_advance<Lay, R, RH, TW, TH, NT>(src, dst, sr_src, sr_dst, acc, cav, tiles[b], lds_q, lds_sr);
+            stepk_advance<Lay, R, RH, TW, TH, NT, K>(src, dst, sr_src, sr_dst, acc, cav, tiles[b], lds_q, lds_sr);
         return;
     }
     for (int t = b; t < ntiles; t += gridDim.x) {
-        step2_advance<Lay, R, RH, TW, TH, NT>(src, dst, sr_src, sr_dst, acc, cav, tiles[t], lds_q, lds_sr);
+        stepk_advance<Lay, R, RH, TW, TH, NT, K>(src, dst, sr_src, sr_dst, acc, cav, tiles[t], lds_q, lds_sr);
         __syncthreads();  // the next tile reuses the LDS
     }
 }
 
+// Tile shapes of the three-steps-per-launch kernel (a two-node ring; build
+// options LBM_S3_* for tuning).  Measured on the 8192^2 cavity: the shape
+// must leave three (D2Q9) or four (D2Q5) workgroups per CU; with two, the
+// three updates and their barriers leave too little to overlap (32 x 11:
+// 28.6 GLUPS against 43.7 for 32 x 9).
 template <int ST>
-static hipError_t launch_step2_s(const Step2Launch &L, hipStream_t s) {
+struct Step3Tile;
+#ifndef LBM_S3_F32_TW
+#define LBM_S3_F32_TW 32
+#define LBM_S3_F32_TH 9
+#endif
+#ifndef LBM_S3_F32Q5_TW
+#define LBM_S3_F32Q5_TW 32
+#define LBM_S3_F32Q5_TH 10
+#endif
+template <>
+struct Step3Tile<ST_F32> {  // 112 B per slot (default 36 x 13 slots, 52 KiB: 3 per CU)
+    static constexpr int TW = LBM_S3_F32_TW, TH = LBM_S3_F32_TH, NT = round64((TW + 4) * (TH + 4));
+};
+template <>
+struct Step3Tile<ST5_F32> {  // 80 B per slot (default 36 x 14 slots, 39 KiB: 4 per CU)
+    static constexpr int TW = LBM_S3_F32Q5_TW, TH = LBM_S3_F32Q5_TH, NT = round64((TW + 4) * (TH + 4));
+};
+template <>
+struct Step3Tile<ST_F32H> {  // 116 B per slot, 36 x 13 slots (53 KiB: 3 per CU)
+    static constexpr int TW = 32, TH = 9, NT = 512;
+};
+template <>
+struct Step3Tile<ST5_F32H> {  // 84 B per slot, 36 x 14 slots (41 KiB: 3 per CU)
+    static constexpr int TW = 32, TH = 10, NT = 512;
+};
+
+template <int ST, int K>
+struct StepKTile;
+template <int ST>
+struct StepKTile<ST, 2> : Step2Tile<ST> {};
+template <int ST>
+struct StepKTile<ST, 3> : Step3Tile<ST> {};
+
+template <int ST, int K>
+static hipError_t launch_stepk_s(const Step2Launch &L, hipStream_t s) {
     using Lay = typename LayoutOf<ST>::L;
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
-    using Tl = Step2Tile<ST>;
+    using Tl = StepKTile<ST, K>;
     if (L.grid >= L.ntiles)
-        hipLaunchKernelGGL((step2_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, false>), dim3(L.grid), dim3(Tl::NT),
+        hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, false>), dim3(L.grid), dim3(Tl::NT),
                            0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     else
-        hipLaunchKernelGGL((step2_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, true>), dim3(L.grid), dim3(Tl::NT),
+        hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, true>), dim3(L.grid), dim3(Tl::NT),
                            0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     return hipGetLastError();
 }
 
-bool step2_supported(int storage) {
-    return storage == ST_F32 || storage == ST5_F32 || storage == ST_F64 || storage == ST5_F64 ||
-           storage == ST_F32H || storage == ST5_F32H;
+bool stepk_supported(int storage, int k) {
+    if (k == 2)
+        return storage == ST_F32 || storage == ST5_F32 || storage == ST_F64 || storage == ST5_F64 ||
+               storage == ST_F32H || storage == ST5_F32H;
+    if (k == 3) return storage == ST_F32 || storage == ST5_F32 || storage == ST_F32H || storage == ST5_F32H;
+    return false;
 }
 
-void step2_tile(int storage, int *tw, int *th) {
+template <int ST, int K>
+static void tile_of(int *tw, int *th) {
+    *tw = StepKTile<ST, K>::TW;
+    *th = StepKTile<ST, K>::TH;
+}
+
+void stepk_tile(int storage, int k, int *tw, int *th) {
+    *tw = *th = 0;
+    if (k == 3) {
+        switch (storage) {
+            case ST_F32: return tile_of<ST_F32, 3>(tw, th);
+            case ST5_F32: return tile_of<ST5_F32, 3>(tw, th);
+            case ST_F32H: return tile_of<ST_F32H, 3>(tw, th);
+            case ST5_F32H: return tile_of<ST5_F32H, 3>(tw, th);
+            default: return;
+        }
+    }
+    if (k != 2) return;
     switch (storage) {
-        case ST_F32: *tw = Step2Tile<ST_F32>::TW; *th = Step2Tile<ST_F32>::TH; return;
-        case ST5_F32: *tw = Step2Tile<ST5_F32>::TW; *th = Step2Tile<ST5_F32>::TH; return;
-        case ST_F64: *tw = Step2Tile<ST_F64>::TW; *th = Step2Tile<ST_F64>::TH; return;
-        case ST5_F64: *tw = Step2Tile<ST5_F64>::TW; *th = Step2Tile<ST5_F64>::TH; return;
-        case ST_F32H: *tw = Step2Tile<ST_F32H>::TW; *th = Step2Tile<ST_F32H>::TH; return;
-        case ST5_F32H: *tw = Step2Tile<ST5_F32H>::TW; *th = Step2Tile<ST5_F32H>::TH; return;
-        default: *tw = *th = 0;
+        case ST_F32: return tile_of<ST_F32, 2>(tw, th);
+        case ST5_F32: return tile_of<ST5_F32, 2>(tw, th);
+        case ST_F64: return tile_of<ST_F64, 2>(tw, th);
+        case ST5_F64: return tile_of<ST5_F64, 2>(tw, th);
+        case ST_F32H: return tile_of<ST_F32H, 2>(tw, th);
+        case ST5_F32H: return tile_of<ST5_F32H, 2>(tw, th);
+        default: return;
     }
 }
 
-hipError_t launch_step2(const Step2Launch &L, hipStream_t s) {
+hipError_t launch_stepk(const Step2Launch &L, hipStream_t s) {
     if (L.grid < 1 || L.ntiles < 1) return hipErrorInvalidValue;
+    if (L.steps == 3) {
+        switch (L.storage) {
+            case ST_F32: return launch_stepk_s<ST_F32, 3>(L, s);
+            case ST5_F32: return launch_stepk_s<ST5_F32, 3>(L, s);
+            case ST_F32H: return launch_stepk_s<ST_F32H, 3>(L, s);
+            case ST5_F32H: return launch_stepk_s<ST5_F32H, 3>(L, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (L.steps != 2) return hipErrorInvalidValue;
     switch (L.storage) {
-        case ST_F32: return launch_step2_s<ST_F32>(L, s);
-        case ST5_F32: return launch_step2_s<ST5_F32>(L, s);
-        case ST_F64: return launch_step2_s<ST_F64>(L, s);
-        case ST5_F64: return launch_step2_s<ST5_F64>(L, s);
-        case ST_F32H: return launch_step2_s<ST_F32H>(L, s);
-        case ST5_F32H: return launch_step2_s<ST5_F32H>(L, s);
+        case ST_F32: return launch_stepk_s<ST_F32, 2>(L, s);
+        case ST5_F32: return launch_stepk_s<ST5_F32, 2>(L, s);
+        case ST_F64: return launch_stepk_s<ST_F64, 2>(L, s);
+        case ST5_F64: return launch_stepk_s<ST5_F64, 2>(L, s);
+        case ST_F32H: return launch_stepk_s<ST_F32H, 2>(L, s);
+        case ST5_F32H: return launch_stepk_s<ST5_F32H, 2>(L, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -987,18 +987,22 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, const
 }
 
 // ---------------------------------------------------------------------------
-// Two steps per sweep through LDS.  A tile of w x h nodes (w <= TW, h <= TH)
-// at (x0, y0) first advances the tile and a one-node ring around it (the
-// region R1, (w+2) x (h+2) slots, unwrapped coordinates) from the global
-// state into LDS, then advances the tile from LDS to the global state: the
-// same two updates as two single steps, with the intermediate populations
-// kept in their storage type, so the result is bit-identical.  The state
-// crosses HBM once per two steps.  A wall node of the tile pulls through its
-// partner from at most one node outside the tile, so R1 covers the second
-// update as long as no tile starts on the last column or row of a cavity
-// (the host's tiling guarantees it).  Only the tile's own nodes write wall
-// tallies.  Plain layouts and the FP32 layout with the FP64 rest enthalpy
-// population: the LDS holds each population in the type it is stored in.
+// K steps per sweep through LDS (K = 2 or 3).  A tile of w x h nodes
+// (w <= TW, h <= TH) at (x0, y0) is advanced K steps by updates over
+// shrinking regions: R_j is the tile grown by a ring of j nodes (clipped to
+// the cavity; unwrapped coordinates across a periodic seam).  The first
+// update advances R_(K-1) from the global state into LDS, each middle update
+// advances R_j (j = K-2 .. 1) in place in LDS (every node first reads its
+// pulls into registers, then, after a barrier, writes its own slot), and the
+// last update advances the tile from LDS into the global state.  The
+// intermediate populations are kept in their storage type, so the result is
+// bit-identical to K single steps.  The state crosses HBM once per K steps.
+// A wall node pulls through its partner from at most one node beyond it
+// inward, so R_j covers the update of R_(j-1) as long as no tile starts on
+// the last column or row of a cavity (the host's tiling guarantees it).
+// Only the tile's own nodes write wall tallies.  Plain layouts and the FP32
+// layout with the FP64 rest enthalpy population: the LDS holds each
+// population in the type it is stored in.
 // ---------------------------------------------------------------------------
 #if defined(__HIP_DEVICE_COMPILE__)
 #define LBM_HOST_CHECK(cond) ((void)0)
@@ -1052,37 +1056,47 @@ struct LdsCodec<PlainH64<QT_>> {
     }
 };
 
-template <class Lay, int TW, int TH>
-struct Step2Shape {
+template <class Lay, int TW, int TH, int K>
+struct StepKShape {
     static constexpr int QT = Lay::QT;
-    static constexpr int NSLOT = (TW + 2) * (TH + 2);  // LDS plane stride
+    static constexpr int RING = K - 1;          // ring of the first update
+    static constexpr int LW = TW + 2 * RING;    // fixed LDS row pitch
+    static constexpr int NSLOT = LW * (TH + 2 * RING);  // LDS plane stride
     using Codec = LdsCodec<Lay>;
     static constexpr size_t LDS_BYTES = Codec::bytes(NSLOT);
+    static_assert(TH + 2 * K <= LBM_MIN_BAND_ROWS, "a tile's rows must span at most two bands");
 };
+template <class Lay, int TW, int TH>
+using Step2Shape = StepKShape<Lay, TW, TH, 2>;
 
 // Global accesses of a tile go through 32-bit offsets from the block of the
-// band of the first row either update touches, y0 - 2 (the ring's pulls),
-// clipped to the cavity: at most TH + 4 <= LBM_MIN_BAND_ROWS rows, so at
-// most two bands.
-template <typename R>
+// band of the first row any update touches, y0 - K (the first update's ring
+// and its pulls), clipped to the cavity: at most TH + 2K <= LBM_MIN_BAND_ROWS
+// rows, so at most two bands.
+template <typename R, int K>
 LBM_HD int tile_first_row(const CavityConst<R> &c, const Tile2 &tl) {
     (void)c;
-    return tl.y0 >= 2 ? tl.y0 - 2 : 0;
+    return tl.y0 >= K ? tl.y0 - K : 0;
 }
 
-// First update: slot s of R1 (row-major with the fixed pitch TW + 2, so the
-// decode divides by a constant; columns beyond w + 2 idle).  Reads the
+// LDS slot of the node at unwrapped (x, y) of a tile's K-step sweep.
+template <class Sh>
+LBM_HD int lds_slot(const Tile2 &tl, int x, int y) {
+    return (y - (tl.y0 - Sh::RING)) * Sh::LW + (x - (tl.x0 - Sh::RING));
+}
+
+// First update: slot s of R_(K-1) (row-major with the fixed pitch LW, so the
+// decode divides by a constant; columns beyond w + 2 RING idle).  Reads the
 // global state, writes the slot's post-collision populations and Sr_f to LDS.
-template <class Lay, typename R, typename RH, int TW, int TH>
-LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *src,
-                         const R *__restrict__ sr_src, double *__restrict__ acc, void *lds_q, R *lds_sr,
-                         int s) {
-    using Sh = Step2Shape<Lay, TW, TH>;
-    constexpr int LW = TW + 2;
-    LBM_HOST_CHECK(s >= 0 && s < LW * (tl.h + 2) && s < Sh::NSLOT);
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
+LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *src,
+                        const R *__restrict__ sr_src, double *__restrict__ acc, void *lds_q, R *lds_sr, int s) {
+    using Sh = StepKShape<Lay, TW, TH, K>;
+    constexpr int LW = Sh::LW, RG = Sh::RING;
+    LBM_HOST_CHECK(s >= 0 && s < LW * (tl.h + 2 * RG) && s < Sh::NSLOT);
     const int lx = s % LW, ly = s / LW;
-    if (lx >= tl.w + 2) return;
-    const int x = tl.x0 - 1 + lx, y = tl.y0 - 1 + ly;  // unwrapped
+    if (lx >= tl.w + 2 * RG) return;
+    const int x = tl.x0 - RG + lx, y = tl.y0 - RG + ly;  // unwrapped
     if (y < 0 || y >= c.ny) return;
     int xx = x;
     if (c.periodic) xx = x < 0 ? x + c.nx : (x >= c.nx ? x - c.nx : x);
@@ -1090,9 +1104,9 @@ LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *s
     LBM_HOST_CHECK(xx >= 0 && xx < c.nx);
     const bool owned = x >= tl.x0 && x < tl.x0 + tl.w && y >= tl.y0 && y < tl.y0 + tl.h;
     const NodeGeom g = geometry(c, xx, y, true);
-    const int yb = tile_first_row(c, tl);
+    const int yb = tile_first_row<R, K>(c, tl);
     const BandOrigin org = band_origin(c, yb);
-    LBM_HOST_CHECK(g.sy - 1 >= yb && g.sy + 1 < yb + TH + 4 && TH + 4 <= LBM_MIN_BAND_ROWS);
+    LBM_HOST_CHECK(g.sy - 1 >= yb && g.sy + 1 < yb + TH + 2 * K);
     LBM_HOST_CHECK(g.sy + 1 < org.y_next + c.band_rows);
     R qf[9], qh[9];
     RH qg[9];
@@ -1113,29 +1127,21 @@ LBM_HD void step2_phase1(const CavityConst<R> &c, const Tile2 &tl, const void *s
     lds_sr[s] = (R)srf;
 }
 
-// Second update: node n of the tile (row-major with pitch TW; columns beyond
-// w idle).  Pulls from LDS, writes the global state.
-template <class Lay, typename R, typename RH, int TW, int TH>
-LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, R *__restrict__ sr_dst,
-                         double *__restrict__ acc, const void *lds_q, const R *lds_sr, int n) {
-    using Sh = Step2Shape<Lay, TW, TH>;
-    constexpr int LW = TW + 2;
-    LBM_HOST_CHECK(n >= 0 && n < TW * tl.h);
-    if (n % TW >= tl.w) return;
-    const int x = tl.x0 + n % TW, y = tl.y0 + n / TW;
-    LBM_HOST_CHECK(x >= 0 && x < c.nx && y >= 0 && y < c.ny);
-    const NodeGeom g = geometry(c, x, y, true);
-    R qf[9], qh[9];
-    RH qg[9];
-    // pull from the LDS slots of the neighbours of the node (or of its wall
-    // partner), in unwrapped coordinates relative to R1's corner
+// A node's pulls from LDS: the slots of the neighbours of the node (or of
+// its wall partner), in unwrapped coordinates.  x is the node's unwrapped
+// column, xx the wrapped one.
+template <class Sh, typename R, typename RH>
+LBM_HD void lds_gather(const Tile2 &tl, const NodeGeom &g, int x, int xx, int h_region, const void *lds_q,
+                       R qf[9], RH qg[9], R qh[9]) {
+    using Cd = typename Sh::Codec;
+    const int px = x + (g.sx - xx);  // partner column, unwrapped
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const int lx = g.sx - ex_of(i) - (tl.x0 - 1), ly = g.sy - ey_of(i) - (tl.y0 - 1);
-        LBM_HOST_CHECK(lx >= 0 && lx < LW && ly >= 0 && ly < tl.h + 2);
-        const int sl = ly * LW + lx;
-        LBM_HOST_CHECK(sl < Sh::NSLOT);
-        using Cd = typename Sh::Codec;
+        const int sl = lds_slot<Sh>(tl, px - ex_of(i), g.sy - ey_of(i));
+        LBM_HOST_CHECK(px - ex_of(i) - (tl.x0 - Sh::RING) >= 0 && px - ex_of(i) - (tl.x0 - Sh::RING) < Sh::LW);
+        LBM_HOST_CHECK(g.sy - ey_of(i) - (tl.y0 - Sh::RING) >= 0 &&
+                       g.sy - ey_of(i) - (tl.y0 - Sh::RING) < h_region);
+        LBM_HOST_CHECK(sl >= 0 && sl < Sh::NSLOT);
         qf[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 0, i, sl);
         if (i < Sh::QT) {
             qg[i] = Cd::template get<RH>(lds_q, Sh::NSLOT, 1, i, sl);
@@ -1145,8 +1151,78 @@ LBM_HD void step2_phase2(const CavityConst<R> &c, const Tile2 &tl, void *dst, R 
             qh[i] = R(0);
         }
     }
-    const int self = (y - (tl.y0 - 1)) * LW + (x - (tl.x0 - 1));
-    const int yb = tile_first_row(c, tl);
+}
+
+// A middle update of ring j (1 <= j <= K - 2), split at the barrier that
+// lets it run in place: stepk_mid_load reads thread t's node's pulls into
+// registers (false: the thread has no node), stepk_mid_store updates the
+// node and writes its own slot.
+template <typename R, typename RH>
+struct MidNode {
+    int x, xx, y, slot;
+    bool owned;
+    NodeGeom g;
+    R qf[9], qh[9], sr_prev;
+    RH qg[9];
+};
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
+LBM_HD bool stepk_mid_load(const CavityConst<R> &c, const Tile2 &tl, int j, const void *lds_q, const R *lds_sr,
+                           int t, MidNode<R, RH> &n) {
+    using Sh = StepKShape<Lay, TW, TH, K>;
+    const int pw = TW + 2 * j;  // pitch of ring j's thread map
+    const int lx = t % pw, ly = t / pw;
+    if (lx >= tl.w + 2 * j || ly >= tl.h + 2 * j) return false;
+    n.x = tl.x0 - j + lx;
+    n.y = tl.y0 - j + ly;  // unwrapped
+    if (n.y < 0 || n.y >= c.ny) return false;
+    n.xx = n.x;
+    if (c.periodic) n.xx = n.x < 0 ? n.x + c.nx : (n.x >= c.nx ? n.x - c.nx : n.x);
+    else if (n.x < 0 || n.x >= c.nx) return false;
+    LBM_HOST_CHECK(n.xx >= 0 && n.xx < c.nx);
+    n.owned = n.x >= tl.x0 && n.x < tl.x0 + tl.w && n.y >= tl.y0 && n.y < tl.y0 + tl.h;
+    n.g = geometry(c, n.xx, n.y, true);
+    n.slot = lds_slot<Sh>(tl, n.x, n.y);
+    LBM_HOST_CHECK(n.slot >= 0 && n.slot < Sh::NSLOT);
+    lds_gather<Sh, R, RH>(tl, n.g, n.x, n.xx, tl.h + 2 * Sh::RING, lds_q, n.qf, n.qg, n.qh);
+    n.sr_prev = lds_sr[n.slot];
+    return true;
+}
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
+LBM_HD void stepk_mid_store(const CavityConst<R> &c, double *__restrict__ acc, void *lds_q, R *lds_sr,
+                            MidNode<R, RH> &n) {
+    using Sh = StepKShape<Lay, TW, TH, K>;
+    using Cd = typename Sh::Codec;
+    Thermo<RH> th;
+    Macro<R> m;
+    const RH srf = update_node<Sh::QT, R, RH, true>(c, n.g, n.xx, n.y, n.qf, n.qg, n.qh, n.sr_prev, n.owned, acc,
+                                                   th, m);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        Cd::put(lds_q, Sh::NSLOT, 0, i, n.slot, n.qf[i]);
+        if (i < Sh::QT) {
+            Cd::put(lds_q, Sh::NSLOT, 1, i, n.slot, n.qg[i]);
+            Cd::put(lds_q, Sh::NSLOT, 2, i, n.slot, n.qh[i]);
+        }
+    }
+    lds_sr[n.slot] = (R)srf;
+}
+
+// Last update: node n of the tile (row-major with pitch TW; columns beyond
+// w idle).  Pulls from LDS, writes the global state.
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
+LBM_HD void stepk_last(const CavityConst<R> &c, const Tile2 &tl, void *dst, R *__restrict__ sr_dst,
+                       double *__restrict__ acc, const void *lds_q, const R *lds_sr, int n) {
+    using Sh = StepKShape<Lay, TW, TH, K>;
+    LBM_HOST_CHECK(n >= 0 && n < TW * tl.h);
+    if (n % TW >= tl.w) return;
+    const int x = tl.x0 + n % TW, y = tl.y0 + n / TW;
+    LBM_HOST_CHECK(x >= 0 && x < c.nx && y >= 0 && y < c.ny);
+    const NodeGeom g = geometry(c, x, y, true);
+    R qf[9], qh[9];
+    RH qg[9];
+    lds_gather<Sh, R, RH>(tl, g, x, x, tl.h + 2 * Sh::RING, lds_q, qf, qg, qh);
+    const int self = lds_slot<Sh>(tl, x, y);
+    const int yb = tile_first_row<R, K>(c, tl);
     const NodeRef k = band_origin(c, yb)(x, y);
     void *blk = band_block(c, dst, yb / c.band_rows);
     Thermo<RH> th;

@@ -1,8 +1,8 @@
 """GPU checks of the banded storage layout: a cavity cut into bands of a
 few rows (every step-kernel tile then crosses band boundaries, and the
-two-step tiles' rings reach into the next band) must give the same
+multi-step tiles' rings reach into the next band) must give the same
 populations, sources, wall tallies and diagnostics, bit for bit, as the
-same cavity stored in one band, with one and with two steps per launch."""
+same cavity stored in one band, with one, two and three steps per launch."""
 import numpy as np
 import pytest
 
@@ -54,8 +54,10 @@ def _run(lbm, ps, prec, steps, spl):
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("qt", [9, 5])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-@pytest.mark.parametrize("spl", [1, 2])
+@pytest.mark.parametrize("spl", [1, 2, 3])
 def test_bands_give_the_same_bits(lbm, case, qt, prec, spl):
+    if spl == 3 and prec != "f32":
+        pytest.skip("three steps per launch exist for the FP32 forms")
     one = [dict(q, thermal_lattice=qt, band_rows=q["ny"]) for q in CASES[case]()]
     cut = [dict(q, band_rows=_min_rows(q["nx"])) for q in one]
     assert any(q["band_rows"] < q["ny"] for q in cut), "the case must hold more than one band"

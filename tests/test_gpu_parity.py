@@ -163,7 +163,9 @@ def test_launch_shapes_bitwise_and_deterministic(lbm):
                    dict(block=64, nodes_per_thread=1, xcd_remap=0, persistent=0, steps_per_launch=1),
                    dict(block=512, nodes_per_thread=4, xcd_remap=1, persistent=1, steps_per_launch=1),
                    dict(block=512, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=2),
-                   dict(block=512, nodes_per_thread=1, xcd_remap=0, persistent=3, steps_per_launch=2)):
+                   dict(block=512, nodes_per_thread=1, xcd_remap=0, persistent=3, steps_per_launch=2),
+                   dict(block=512, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=3),
+                   dict(block=512, nodes_per_thread=1, xcd_remap=0, persistent=2, steps_per_launch=3)):
         s = lbm.Solver(p, "f32")
         lbm.lbm_set_launch(s.h, **launch)
         s.set_initial(0, T_pcm, T_mf)

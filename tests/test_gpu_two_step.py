@@ -1,10 +1,11 @@
-"""GPU checks of the two-steps-per-launch kernel: the state crosses HBM once
-per two steps through LDS tiles, and the result must be the same map as
-two single steps, bit for bit (populations, sources, FP64 wall tallies and
-diagnostics), on every geometry the single-step path handles: walls and
-corners, periodic channels, ragged and batched cavities, mixed wall types,
-the bounce-back alternative, both thermal lattices, FP32, FP64 and FP32 with
-the FP64 rest enthalpy population, odd step counts and graph replays.
+"""GPU checks of the K-steps-per-launch kernels (K = 2, and K = 3 for the FP32 forms):
+the state crosses HBM once per K steps through LDS tiles, and the result
+must be the same map as K single steps, bit for bit (populations, sources,
+FP64 wall tallies and diagnostics), on every geometry the single-step path
+handles: walls and corners, periodic channels, ragged and batched cavities,
+mixed wall types, the bounce-back alternative, both thermal lattices, FP32,
+FP64 and FP32 with the FP64 rest enthalpy population, step counts that
+leave a remainder and graph replays.
 """
 import numpy as np
 import pytest
@@ -65,6 +66,21 @@ def test_two_step_is_bitwise_two_single_steps(lbm, case, qt, prec):
     two = _run(lbm, ps, prec, steps, 2, lambda n: [n])
     mixed = _run(lbm, ps, prec, steps, 2, lambda n: [1, 2, 3, 64, 61])
     for (a, da), (b, db), (m, dm) in zip(ref, two, mixed):
+        assert np.array_equal(a, b) and np.array_equal(a, m)
+        for k in ("flux_E", "flux_M", "E_int", "M_int", "liquid_fraction", "Nu_hot"):
+            assert da[k] == db[k] == dm[k], k
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("qt", [9, 5])
+@pytest.mark.parametrize("prec", ["f32", "f32h64"])
+def test_three_steps_per_launch_are_bitwise_three_single_steps(lbm, case, qt, prec):
+    ps = [dict(q, thermal_lattice=qt) for q in CASES[case]()]
+    steps = 200      # first (raw) step, graph replays of 32 launches, a remaining pair
+    ref = _run(lbm, ps, prec, steps, 1, lambda n: [1] * n)
+    three = _run(lbm, ps, prec, steps, 3, lambda n: [n])
+    mixed = _run(lbm, ps, prec, steps, 3, lambda n: [1, 2, 3, 4, 97, 93])
+    for (a, da), (b, db), (m, dm) in zip(ref, three, mixed):
         assert np.array_equal(a, b) and np.array_equal(a, m)
         for k in ("flux_E", "flux_M", "E_int", "M_int", "liquid_fraction", "Nu_hot"):
             assert da[k] == db[k] == dm[k], k
