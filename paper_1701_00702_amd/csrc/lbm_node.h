@@ -423,18 +423,6 @@ LBM_HD void from_moments(const R d[9], R q[9]) {
     q[8] = diag + xd - yd - a8;
 }
 
-template <typename R>
-LBM_HD R sum9(const R q[9]) {
-    return ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7])) + q[8];
-}
-
-// Zeroth moment of QT populations.
-template <int QT, typename R>
-LBM_HD R sumq(const R q[9]) {
-    if (QT == 9) return sum9(q);
-    return ((q[0] + q[1]) + (q[2] + q[3])) + q[4];
-}
-
 // D2Q5 transforms of Eq. (B1) on offsets: d = M q, and its inverse
 // q0 = d0 - d3, q1,3 = (d3 + d4)/4 +- d1/2, q2,4 = (d3 - d4)/4 +- d2/2.
 template <typename R>
@@ -485,37 +473,61 @@ LBM_HD void eos(const ThermalConst<RH> &t, RH H, RH &T, RH &fl) {
     }
 }
 
-// Blends qf in place (Eq. 20) and computes everything the collisions need.
+// Moments of the three fields' post-streaming offsets, Eq. (13) (D2Q5
+// thermal fields: Eq. B1).  Their zeroth moments are delta rho, delta H
+// (Eq. 37) and c_pm delta T_m (Eq. 48).
+template <typename R, typename RH>
+struct Moments {
+    R f[9], h[9];
+    RH g[9];
+};
 template <int QT, typename R, typename RH>
-LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[9], Thermo<RH> &th,
-                   Macro<R> &m) {
+LBM_HD void field_moments(const R qf[9], const RH qg[9], const R qh[9], Moments<R, RH> &mo) {
+    to_moments(qf, mo.f);
+    if (QT == 9) {
+        to_moments(qg, mo.g);
+        to_moments(qh, mo.h);
+    } else {
+        to_moments5(qg, mo.g);
+        to_moments5(qh, mo.h);
+    }
+}
+
+// Everything the collisions need, from the moments; blends the flow moments
+// in place (Eq. 20: f = f_l f+ + (1 - f_l) w rho, whose moments on offsets
+// are f_l d + (1 - f_l) delta rho (1, -2, 1, 0, ..., 0), M w having the
+// moments (1, -2, 1, 0, ..., 0)).  The bounce-back alternative of Sec. V B
+// keeps f+ unblended.
+template <int QT, typename R, typename RH>
+LBM_HD void macros_of(const CavityConst<R> &c, Moments<R, RH> &mo, Thermo<RH> &th, Macro<R> &m) {
     const ThermalConst<RH> &t = thermal<RH>(c);
     // Eq. (37), Eqs. (38)-(39)
-    th.dH = sumq<QT>(qg);
+    th.dH = mo.g[0];
     th.H = t.H_ref + th.dH;
     eos(t, th.H, th.Tf, th.fl);
     m.Tf = (R)th.Tf;
     m.fl = (R)th.fl;
     // Eq. (48)
-    m.dTm = sumq<QT>(qh) * c.inv_cpm;
+    m.dTm = mo.h[0] * c.inv_cpm;
     m.Tm = c.T_ref + m.dTm;
     // Eq. (21)
-    m.drho = sum9(qf);
+    m.drho = mo.f[0];
     m.rho = R(1) + m.drho;
-    // Eq. (20): f = f_l f+ + (1 - f_l) w rho, written on offsets from w rho_0
-    // (the bounce-back alternative of Sec. V B keeps f+ unblended).
     if (!c.bounce_back) {
         const R sol = (R(1) - m.fl) * m.drho;
+        mo.f[0] = m.drho;
+        mo.f[1] = fma_of(m.fl, mo.f[1], R(-2) * sol);
+        mo.f[2] = fma_of(m.fl, mo.f[2], sol);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) qf[i] = fma_of(m.fl, qf[i], w_of<R>(i) * sol);
+        for (int k = 3; k < 9; ++k) mo.f[k] = m.fl * mo.f[k];
     }
     // Eq. (7): buoyancy along +axis (gravity along -axis).
     const R G = c.gbeta * (m.Tf - c.T0) * m.fl;
     m.Gx = c.gaxis == 0 ? G : R(0);
     m.Gy = c.gaxis == 1 ? G : R(0);
-    // Eq. (24), then the explicit root Eq. (23) with Eq. (25).
-    const R jx = (qf[1] - qf[3]) + ((qf[5] - qf[6]) - (qf[7] - qf[8]));
-    const R jy = (qf[2] - qf[4]) + ((qf[5] + qf[6]) - (qf[7] + qf[8]));
+    // Eq. (24) (j = the blended moments 3 and 5), then the explicit root
+    // Eq. (23) with Eq. (25).
+    const R jx = mo.f[3], jy = mo.f[5];
     const R inv_rho = rcp_of(m.rho);
     const R vx = fma_of(jx, inv_rho, R(0.5) * c.phi * m.Gx);
     const R vy = fma_of(jy, inv_rho, R(0.5) * c.phi * m.Gy);
@@ -532,12 +544,21 @@ LBM_HD void macros(const CavityConst<R> &c, R qf[9], const RH qg[9], const R qh[
     }
 }
 
-// Flow collision, Eqs. (14), (16)-(19), on the blended offsets; with the
-// bounce-back alternative (Sec. V B) a solid node instead returns every
-// population along the opposite link (the reference w_i rho_0 is symmetric,
-// so the offsets swap the same way).
+// The same from populations (wall partners, diagnostics).
+template <int QT, typename R, typename RH>
+LBM_HD void macros(const CavityConst<R> &c, const R qf[9], const RH qg[9], const R qh[9], Thermo<RH> &th,
+                   Macro<R> &m) {
+    Moments<R, RH> mo;
+    field_moments<QT>(qf, qg, qh, mo);
+    macros_of<QT>(c, mo, th, m);
+}
+
+// Flow collision, Eqs. (14), (16)-(19), from the blended moments d (into q);
+// with the bounce-back alternative (Sec. V B) a solid node instead returns
+// every population of q along the opposite link (the reference w_i rho_0 is
+// symmetric, so the offsets swap the same way).
 template <typename R>
-LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R q[9]) {
+LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R d[9], R q[9]) {
     if (c.bounce_back && m.fl < R(0.5)) {
         R t;
         t = q[1]; q[1] = q[3]; q[3] = t;
@@ -546,8 +567,6 @@ LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R q[9]) {
         t = q[6]; q[6] = q[8]; q[8] = t;
         return;
     }
-    R d[9];
-    to_moments(q, d);
     const R ux = m.ux, uy = m.uy, rho = m.rho;
     const R uu = fma_of(ux, ux, uy * uy);
     // Eq. (3): F = -(drag_lin + drag_quad |u|) u + phi G
@@ -582,10 +601,8 @@ LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R q[9]) {
 // PCM enthalpy collision, Eqs. (32), (34)-(35).
 template <typename R, typename RH>
 LBM_HD void collide_pcm(const CavityConst<R> &c, const Thermo<RH> &th, const Macro<R> &m, RH S_pcm,
-                        RH q[9]) {
+                        RH d[9], RH q[9]) {
     const ThermalConst<RH> &t = thermal<RH>(c);
-    RH d[9];
-    to_moments(q, d);
     const RH dT = th.Tf - t.T_ref;
     const RH jT = t.c_pl * th.Tf * t.inv_phi;
     RH eq[9];
@@ -608,9 +625,7 @@ LBM_HD void collide_pcm(const CavityConst<R> &c, const Thermo<RH> &th, const Mac
 
 // Metal-foam collision, Eqs. (43), (45)-(46).
 template <typename R>
-LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal, R q[9]) {
-    R d[9];
-    to_moments(q, d);
+LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal, R d[9], R q[9]) {
     R eq[9];
     eq[0] = c.c_pm * m.dTm;
     eq[1] = (-R(4) * c.c_pm + R(2) * c.c_mref) * m.dTm;
@@ -629,10 +644,8 @@ LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal,
 // offsets, Theta in the moment order of Eq. (B1), source S (1, 0, 0, varpi, 0).
 template <typename R, typename RH>
 LBM_HD void collide_pcm5(const CavityConst<R> &c, const Thermo<RH> &th, const Macro<R> &m, RH S_pcm,
-                         RH q[9]) {
+                         RH d[9], RH q[9]) {
     const ThermalConst<RH> &t = thermal<RH>(c);
-    RH d[5];
-    to_moments5(q, d);
     const RH jT = t.c_pl * th.Tf * t.inv_phi;
     RH eq[5];
     eq[0] = th.dH;
@@ -649,9 +662,7 @@ LBM_HD void collide_pcm5(const CavityConst<R> &c, const Thermo<RH> &th, const Ma
 
 // D2Q5 metal-foam collision (Appendix B): Eq. (B4), Q, S (1, 0, 0, varpi, 0).
 template <typename R>
-LBM_HD void collide_metal5(const CavityConst<R> &c, const Macro<R> &m, R S_metal, R q[9]) {
-    R d[5];
-    to_moments5(q, d);
+LBM_HD void collide_metal5(const CavityConst<R> &c, const Macro<R> &m, R S_metal, R d[9], R q[9]) {
     R eq[5];
     eq[0] = c.c_pm * m.dTm;
     eq[1] = R(0);
@@ -683,12 +694,9 @@ LBM_HD int thermal_wall(const CavityConst<R> &c, int x, int y) {
 template <int QT, typename R, typename RH>
 LBM_HD void reconstruct_wall(const CavityConst<R> &c, int x, int y, R qf[9], RH qg[9], R qh[9]) {
     const ThermalConst<RH> &t = thermal<RH>(c);
-    R tf[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) tf[i] = qf[i];
     Thermo<RH> pt;
     Macro<R> p;
-    macros<QT>(c, tf, qg, qh, pt, p);
+    macros<QT>(c, qf, qg, qh, pt, p);
     RH Tb, Hb;
     R Tmb;
     const int w = thermal_wall(c, x, y);
@@ -905,8 +913,10 @@ LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, 
 
     if (PULL && g.wall) reconstruct_wall<QT>(c, x, y, qf, qg, qh);
 
-    macros<QT>(c, qf, qg, qh, th, m);
-    collide_flow(c, m, qf);
+    Moments<R, RH> mo;
+    field_moments<QT>(qf, qg, qh, mo);
+    macros_of<QT>(c, mo, th, m);
+    collide_flow(c, m, mo.f, qf);
     // Eqs. (36), (47) with the backward difference of Remark III.
     const RH srf = (RH)c.hv_f * ((RH)m.Tm - th.Tf);
     const R srm = c.hv_m * (m.Tf - m.Tm);
@@ -914,11 +924,11 @@ LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, 
     const RH S_pcm = srf + RH(0.5) * (srf - (RH)sr_prev);
     const R S_metal = srm + R(0.5) * (srm - srm_prev);
     if (QT == 9) {
-        collide_pcm(c, th, m, S_pcm, qg);
-        collide_metal(c, m, S_metal, qh);
+        collide_pcm(c, th, m, S_pcm, mo.g, qg);
+        collide_metal(c, m, S_metal, mo.h, qh);
     } else {
-        collide_pcm5(c, th, m, S_pcm, qg);
-        collide_metal5(c, m, S_metal, qh);
+        collide_pcm5(c, th, m, S_pcm, mo.g, qg);
+        collide_metal5(c, m, S_metal, mo.h, qh);
     }
 
     if (tally && (g.near_x || g.near_y)) {
