@@ -188,10 +188,10 @@ typedef struct lbm_launch_config {
     int32_t steps_per_launch; /* 1: one step per launch; 2: two steps per launch
                                  through LDS (2-D tiles with a one-node ring,
                                  the state crosses HBM once per two steps;
-                                 LBM_F64, LBM_F32 and LBM_F32_H64); 3: three
-                                 steps per launch (a two-node ring; LBM_F32
-                                 and LBM_F32_H64).  Default: the most of
-                                 these the form has when every cavity's rows
+                                 every form); 3: three steps per launch (a
+                                 two-node ring, the middle step in place in
+                                 LDS; every form but LBM_F64).  Default: the
+                                 most the form has when every cavity's rows
                                  are 32-node aligned (nx % 32 == 0) or at
                                  least 1024 wide, else 1.
                                  block and nodes_per_thread then do not apply. */
@@ -234,7 +234,7 @@ lbm_status lbm_set_initial(lbm_handle *h, int32_t cavity, const double *T_pcm0,
                            const double *T_mf0);
 
 /* Advance every cavity by n >= 0 steps (asynchronous).  Each step is one
- * launch of the fused kernel (or one launch per two steps, see
+ * launch of the fused kernel (or one launch per two or three steps, see
  * lbm_launch_config): streaming, wall reconstruction (Eq. 52),
  * enthalpy/temperature/liquid fraction (Eqs. 37-39, 48), volumetric blend
  * (Eq. 20), velocity (Eqs. 23-25), the three moment-space collisions

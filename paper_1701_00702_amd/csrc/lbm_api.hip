@@ -433,7 +433,7 @@ int plane_groups(int st, PlaneGroup g[2]) {
 
 // Splits [0, n) into runs of at most t (t >= 3, n >= 4) such that no run
 // starts at n - 1: a last run of one would leave a wall node whose partner
-// pulls from outside the two-step kernel's LDS region.
+// pulls from outside the K-step kernels' LDS region.
 void split_runs(int n, int t, std::vector<std::pair<int, int>> &out) {
     out.clear();
     int start = 0;
@@ -445,7 +445,7 @@ void split_runs(int n, int t, std::vector<std::pair<int, int>> &out) {
     }
 }
 
-// Tiles of the two-step kernel for one cavity, row by row (ordering them in
+// Tiles of the K-step kernels for one cavity, row by row (ordering them in
 // narrow vertical strips measured no different).
 void cavity_tiles2(int cav, int nx, int ny, int tw, int th, std::vector<Tile2> &tiles) {
     std::vector<std::pair<int, int>> xs, ys;

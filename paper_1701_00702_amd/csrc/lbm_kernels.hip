@@ -174,12 +174,13 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Two steps per launch through LDS (plain FP32 and FP64 storage).  One
-// workgroup per tile: the first update covers the tile and its one-node
-// ring into LDS, a barrier, then the second update covers the tile into the
-// destination buffer.  Tile shapes fill at most 64 KiB of LDS; the FP32
-// defaults (measured) let three or four workgroups share a CU, whose waves
-// overlap one tile's loads with another's arithmetic.
+// K steps per launch through LDS (K = 2, 3).  One workgroup per tile: the
+// first update covers the tile and its (K-1)-node ring into LDS, a middle
+// update (K = 3) the tile and a one-node ring in place in LDS, the last
+// update the tile into the destination buffer, with barriers between.  Tile
+// shapes fill at most 64 KiB of LDS; the defaults (measured) let three or
+// four workgroups share a CU, whose waves overlap one tile's loads with
+// another's arithmetic.  Two-step tiles first.
 // ---------------------------------------------------------------------------
 template <int ST>
 struct Step2Tile;
@@ -208,6 +209,18 @@ struct Step2Tile<ST_F32H> {  // 26 x 4 + 8 + 4 = 116 B per slot, 34 x 13 slots: 
 template <>
 struct Step2Tile<ST5_F32H> {  // 18 x 4 + 8 + 4 = 84 B per slot, 66 x 7 slots: 4 per CU
     static constexpr int TW = 64, TH = 5, NT = 512;
+};
+template <>
+struct Step2Tile<ST_F16> {  // 27 x 2 + 4 = 58 B per slot, 34 x 15 slots (29 KiB)
+    static constexpr int TW = 32, TH = 13, NT = 512;
+};
+template <>
+struct Step2Tile<ST_BF16> {
+    static constexpr int TW = 32, TH = 13, NT = 512;
+};
+template <>
+struct Step2Tile<ST_F16S> {  // 6 x 4 + 24 x 2 + 4 = 76 B per slot, 34 x 15 slots (38 KiB: 4 per CU)
+    static constexpr int TW = 32, TH = 13, NT = 512;
 };
 template <>
 struct Step2Tile<ST_F64> {  // 27 x 8 + 8 = 224 B per slot, 18 x 16 slots
@@ -293,6 +306,18 @@ struct Step3Tile<ST5_F32> {  // 80 B per slot (default 36 x 14 slots, 39 KiB: 4 
     static constexpr int TW = LBM_S3_F32Q5_TW, TH = LBM_S3_F32Q5_TH, NT = round64((TW + 4) * (TH + 4));
 };
 template <>
+struct Step3Tile<ST_F16> {  // 58 B per slot, 36 x 14 slots (29 KiB)
+    static constexpr int TW = 32, TH = 10, NT = 512;
+};
+template <>
+struct Step3Tile<ST_BF16> {
+    static constexpr int TW = 32, TH = 10, NT = 512;
+};
+template <>
+struct Step3Tile<ST_F16S> {  // 76 B per slot, 36 x 14 slots (38 KiB: 4 per CU)
+    static constexpr int TW = 32, TH = 10, NT = 512;
+};
+template <>
 struct Step3Tile<ST_F32H> {  // 116 B per slot, 36 x 13 slots (53 KiB: 3 per CU)
     static constexpr int TW = 32, TH = 9, NT = 512;
 };
@@ -326,10 +351,10 @@ static hipError_t launch_stepk_s(const Step2Launch &L, hipStream_t s) {
 }
 
 bool stepk_supported(int storage, int k) {
-    if (k == 2)
-        return storage == ST_F32 || storage == ST5_F32 || storage == ST_F64 || storage == ST5_F64 ||
-               storage == ST_F32H || storage == ST5_F32H;
-    if (k == 3) return storage == ST_F32 || storage == ST5_F32 || storage == ST_F32H || storage == ST5_F32H;
+    const bool fp32 = storage == ST_F32 || storage == ST5_F32 || storage == ST_F32H || storage == ST5_F32H;
+    const bool b16 = storage == ST_F16 || storage == ST_BF16 || storage == ST_F16S;
+    if (k == 2) return fp32 || b16 || storage == ST_F64 || storage == ST5_F64;
+    if (k == 3) return fp32 || b16;
     return false;
 }
 
@@ -347,11 +372,17 @@ void stepk_tile(int storage, int k, int *tw, int *th) {
             case ST5_F32: return tile_of<ST5_F32, 3>(tw, th);
             case ST_F32H: return tile_of<ST_F32H, 3>(tw, th);
             case ST5_F32H: return tile_of<ST5_F32H, 3>(tw, th);
+            case ST_F16: return tile_of<ST_F16, 3>(tw, th);
+            case ST_BF16: return tile_of<ST_BF16, 3>(tw, th);
+            case ST_F16S: return tile_of<ST_F16S, 3>(tw, th);
             default: return;
         }
     }
     if (k != 2) return;
     switch (storage) {
+        case ST_F16: return tile_of<ST_F16, 2>(tw, th);
+        case ST_BF16: return tile_of<ST_BF16, 2>(tw, th);
+        case ST_F16S: return tile_of<ST_F16S, 2>(tw, th);
         case ST_F32: return tile_of<ST_F32, 2>(tw, th);
         case ST5_F32: return tile_of<ST5_F32, 2>(tw, th);
         case ST_F64: return tile_of<ST_F64, 2>(tw, th);
@@ -370,6 +401,9 @@ hipError_t launch_stepk(const Step2Launch &L, hipStream_t s) {
             case ST5_F32: return launch_stepk_s<ST5_F32, 3>(L, s);
             case ST_F32H: return launch_stepk_s<ST_F32H, 3>(L, s);
             case ST5_F32H: return launch_stepk_s<ST5_F32H, 3>(L, s);
+            case ST_F16: return launch_stepk_s<ST_F16, 3>(L, s);
+            case ST_BF16: return launch_stepk_s<ST_BF16, 3>(L, s);
+            case ST_F16S: return launch_stepk_s<ST_F16S, 3>(L, s);
             default: return hipErrorInvalidValue;
         }
     }
@@ -381,6 +415,9 @@ hipError_t launch_stepk(const Step2Launch &L, hipStream_t s) {
         case ST5_F64: return launch_stepk_s<ST5_F64, 2>(L, s);
         case ST_F32H: return launch_stepk_s<ST_F32H, 2>(L, s);
         case ST5_F32H: return launch_stepk_s<ST5_F32H, 2>(L, s);
+        case ST_F16: return launch_stepk_s<ST_F16, 2>(L, s);
+        case ST_BF16: return launch_stepk_s<ST_BF16, 2>(L, s);
+        case ST_F16S: return launch_stepk_s<ST_F16S, 2>(L, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -391,6 +428,37 @@ hipError_t launch_stepk(const Step2Launch &L, hipStream_t s) {
 constexpr int MB = 256;  // threads per block of the diagnostics kernels
 
 int macro_blocks(int nx, int ny) { return (int)(((int64_t)nx * ny + MB - 1) / MB); }
+
+// Block reduction of N doubles per thread (maxima for P_DT and P_U, sums
+// otherwise), in a fixed order, so the diagnostics are deterministic: a
+// butterfly across each 64-lane wavefront (after it every lane holds the
+// same value, the operations being commutative), then the MB / 64 wave
+// results in wave order.  The result is valid in thread 0.
+template <int N>
+__device__ __forceinline__ void block_reduce(double v[N], double (*sh)[MB / 64]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double o = __shfl_xor(v[k], off, 64);
+            v[k] = (k == P_DT || k == P_U) ? fmax(v[k], o) : v[k] + o;
+        }
+    }
+    const int w = (int)threadIdx.x / 64;
+    if (threadIdx.x % 64 == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) sh[k][w] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double a = sh[k][0];
+            for (int q = 1; q < MB / 64; ++q) a = (k == P_DT || k == P_U) ? fmax(a, sh[k][q]) : a + sh[k][q];
+            v[k] = a;
+        }
+    }
+}
 
 template <class Lay, typename R, typename RH>
 __global__ __launch_bounds__(MB) void macro_kernel(const void *__restrict__ src,
@@ -411,22 +479,12 @@ __global__ __launch_bounds__(MB) void macro_kernel(const void *__restrict__ src,
 #pragma unroll
         for (int q = 0; q < 6; ++q) fields[q * nn + kk] = out[q];
     }
-    // Fixed-order tree reduction (deterministic).
-    __shared__ double red[NPART][MB];
+    __shared__ double sh[NPART][MB / 64];
+    block_reduce<NPART>(v, sh);
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NPART; ++k) red[k][threadIdx.x] = v[k];
-    __syncthreads();
-    for (int st = MB / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) {
-#pragma unroll
-            for (int k = 0; k < NPART; ++k) {
-                const double a = red[k][threadIdx.x], b = red[k][threadIdx.x + st];
-                red[k][threadIdx.x] = (k == P_DT || k == P_U) ? fmax(a, b) : a + b;
-            }
-        }
-        __syncthreads();
+        for (int k = 0; k < NPART; ++k) partials[(int64_t)blockIdx.x * NPART + k] = v[k];
     }
-    if (threadIdx.x < NPART) partials[(int64_t)blockIdx.x * NPART + threadIdx.x] = red[threadIdx.x][0];
 }
 
 template <int ST>
@@ -451,7 +509,7 @@ __global__ __launch_bounds__(MB) void diag_kernel(DiagLaunch L) {
     const int t = threadIdx.x;
     const int nx = L.nx, ny = L.ny;
     const int64_t nn = (int64_t)nx * ny;
-    __shared__ double red[NPART + 3 + 8][MB];
+    __shared__ double sh[NPART + 3 + 8][MB / 64];
     double v[NPART + 3 + 8];
 #pragma unroll
     for (int k = 0; k < NPART + 11; ++k) v[k] = 0.0;
@@ -490,32 +548,20 @@ __global__ __launch_bounds__(MB) void diag_kernel(DiagLaunch L) {
         v[NPART + 9] += acc[2 * (2 * ny + x) + 1];
         v[NPART + 10] += acc[2 * (2 * ny + nx + x) + 1];
     }
-#pragma unroll
-    for (int k = 0; k < NPART + 11; ++k) red[k][t] = v[k];
-    __syncthreads();
-    for (int st = MB / 2; st > 0; st >>= 1) {
-        if (t < st) {
-#pragma unroll
-            for (int k = 0; k < NPART + 11; ++k) {
-                const double a = red[k][t], b = red[k][t + st];
-                red[k][t] = (k == P_DT || k == P_U) ? fmax(a, b) : a + b;
-            }
-        }
-        __syncthreads();
-    }
+    block_reduce<NPART + 11>(v, sh);
     if (t == 0) {
         double *o = L.out;
         const double nint = L.periodic ? (double)nx * (ny - 2) : (double)(nx - 2) * (ny - 2);
-        o[D_FL] = red[P_FL][0] / nint;
-        o[D_E] = red[P_E][0];
-        o[D_M] = red[P_M][0];
-        o[D_DT] = red[P_DT][0];
-        o[D_U] = red[P_U][0];
-        o[D_NF] = red[P_NF][0];
+        o[D_FL] = v[P_FL] / nint;
+        o[D_E] = v[P_E];
+        o[D_M] = v[P_M];
+        o[D_DT] = v[P_DT];
+        o[D_U] = v[P_U];
+        o[D_NF] = v[P_NF];
         const double nrow = (double)(ny - 2);
-        o[D_NUH] = L.periodic ? 0.0 : -(L.L / (L.ke * L.dT)) * (red[NPART + 1][0] / nrow);
-        o[D_NUHP] = L.periodic ? 0.0 : -(L.L / L.dT) * (red[NPART + 0][0] / nrow);
-        o[D_NUC] = L.periodic ? 0.0 : -(L.L / (L.ke * L.dT)) * (red[NPART + 2][0] / nrow);
+        o[D_NUH] = L.periodic ? 0.0 : -(L.L / (L.ke * L.dT)) * (v[NPART + 1] / nrow);
+        o[D_NUHP] = L.periodic ? 0.0 : -(L.L / L.dT) * (v[NPART + 0] / nrow);
+        o[D_NUC] = L.periodic ? 0.0 : -(L.L / (L.ke * L.dT)) * (v[NPART + 2] / nrow);
         // melt front: first f_l = 0.5 crossing on row ny/2 seen from x = 0
         double xf = 1.0;
         if (!L.periodic) {
@@ -536,8 +582,8 @@ __global__ __launch_bounds__(MB) void diag_kernel(DiagLaunch L) {
         }
         o[D_FRONT] = xf;
         for (int w = 0; w < 4; ++w) {
-            o[D_FLUXE + w] = red[NPART + 3 + w][0] + red[P_INE0 + w][0];
-            o[D_FLUXM + w] = red[NPART + 7 + w][0] + red[P_INM0 + w][0];
+            o[D_FLUXE + w] = v[NPART + 3 + w] + v[P_INE0 + w];
+            o[D_FLUXM + w] = v[NPART + 7 + w] + v[P_INM0 + w];
         }
     }
 }

@@ -1026,25 +1026,44 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, const
     } while (0)
 #endif
 
-// How a layout keeps its populations in LDS for the two-step kernel: in
-// the element type it stores them in, so that the second update sees the
-// same values as a one-step launch would load.  NSLOT is the plane stride.
+// How a layout keeps its populations in LDS for the K-step kernels: encoded
+// exactly as it stores them (element type, 16-bit scale, split base), so
+// that the next update sees the same values as a one-step launch would
+// load.  put_node writes a node's post-collision offsets and the split
+// layout's base values (bf, bg, bh, as the stores take them); get returns
+// one population as the layout's load does.  NSLOT is the plane stride.
 template <class Lay>
 struct LdsCodec;
 template <class E, bool SCALED, int QT_>
 struct LdsCodec<Plain<E, SCALED, QT_>> {
-    static_assert(!SCALED, "16-bit forms have no two-step kernel");
     using T = typename E::T;
+    using C = decltype(E::dec(T()));
     static constexpr int QT = QT_;
     static constexpr size_t bytes(int nslot) { return (size_t)(9 + 2 * QT) * nslot * sizeof(T); }
     LBM_HD static int plane(int f, int i) { return f == 0 ? i : 9 + (f - 1) * QT + i; }
-    template <typename V>
-    LBM_HD static void put(void *lds, int nslot, int f, int i, int slot, V v) {
-        ((T *)lds)[plane(f, i) * nslot + slot] = (T)v;
+    template <typename V, typename R>
+    LBM_HD static void put1(void *lds, int nslot, int f, int i, int slot, V v, const CavityConst<R> &c) {
+        ((T *)lds)[plane(f, i) * nslot + slot] = E::enc((C)(SCALED ? v * (V)c.scale[f] : v));
     }
-    template <typename V>
-    LBM_HD static V get(const void *lds, int nslot, int f, int i, int slot) {
-        return (V)((const T *)lds)[plane(f, i) * nslot + slot];
+    template <typename R, typename RH>
+    LBM_HD static void put_node(void *lds, int nslot, int slot, const CavityConst<R> &c, const R qf[9],
+                                const RH qg[9], const R qh[9], R bf, RH bg, R bh) {
+        (void)bf;
+        (void)bg;
+        (void)bh;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            put1(lds, nslot, 0, i, slot, qf[i], c);
+            if (i < QT) {
+                put1(lds, nslot, 1, i, slot, qg[i], c);
+                put1(lds, nslot, 2, i, slot, qh[i], c);
+            }
+        }
+    }
+    template <typename V, typename R>
+    LBM_HD static V get(const void *lds, int nslot, int f, int i, int slot, const CavityConst<R> &c) {
+        const V v = (V)E::dec(((const T *)lds)[plane(f, i) * nslot + slot]);
+        return SCALED ? v * (V)c.inv_scale[f] : v;
     }
 };
 template <int QT_>
@@ -1055,14 +1074,65 @@ struct LdsCodec<PlainH64<QT_>> {
     static constexpr size_t f64_offset(int nslot) { return ((size_t)NF32 * nslot * 4 + 7) & ~(size_t)7; }
     static constexpr size_t bytes(int nslot) { return f64_offset(nslot) + (size_t)nslot * 8; }
     template <typename V>
-    LBM_HD static void put(void *lds, int nslot, int f, int i, int slot, V v) {
+    LBM_HD static void put1(void *lds, int nslot, int f, int i, int slot, V v) {
         if (f == 1 && i == 0) ((double *)((char *)lds + f64_offset(nslot)))[slot] = (double)v;
         else ((float *)lds)[PlainH64<QT_>::plane(f, i) * nslot + slot] = (float)v;
     }
-    template <typename V>
-    LBM_HD static V get(const void *lds, int nslot, int f, int i, int slot) {
+    template <typename R, typename RH>
+    LBM_HD static void put_node(void *lds, int nslot, int slot, const CavityConst<R> &c, const R qf[9],
+                                const RH qg[9], const R qh[9], R bf, RH bg, R bh) {
+        (void)c;
+        (void)bf;
+        (void)bg;
+        (void)bh;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            put1(lds, nslot, 0, i, slot, qf[i]);
+            if (i < QT) {
+                put1(lds, nslot, 1, i, slot, qg[i]);
+                put1(lds, nslot, 2, i, slot, qh[i]);
+            }
+        }
+    }
+    template <typename V, typename R>
+    LBM_HD static V get(const void *lds, int nslot, int f, int i, int slot, const CavityConst<R> &c) {
+        (void)c;
         if (f == 1 && i == 0) return (V)((const double *)((const char *)lds + f64_offset(nslot)))[slot];
         return (V)((const float *)lds)[PlainH64<QT_>::plane(f, i) * nslot + slot];
+    }
+};
+// Split 16-bit layout: per field the FP32 rest population and base, then the
+// eight FP16 remainders from the base's rest equilibrium.
+template <>
+struct LdsCodec<Split16> {
+    static constexpr int QT = 9;
+    static constexpr size_t bytes(int nslot) { return (size_t)nslot * (6 * 4 + 24 * 2); }
+    template <typename V, typename R>
+    LBM_HD static void put_field(void *lds, int nslot, int f, int slot, const V q[9], V beta,
+                                 const CavityConst<R> &c) {
+        float *P = (float *)lds;
+        uint16_t *Qp = (uint16_t *)(P + 6 * nslot);
+        P[(2 * f) * nslot + slot] = (float)q[0];
+        P[(2 * f + 1) * nslot + slot] = (float)beta;
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            Qp[(8 * f + i - 1) * nslot + slot] = E16::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f]));
+    }
+    template <typename R, typename RH>
+    LBM_HD static void put_node(void *lds, int nslot, int slot, const CavityConst<R> &c, const R qf[9],
+                                const RH qg[9], const R qh[9], R bf, RH bg, R bh) {
+        put_field(lds, nslot, 0, slot, qf, bf, c);
+        put_field(lds, nslot, 1, slot, qg, bg, c);
+        put_field(lds, nslot, 2, slot, qh, bh, c);
+    }
+    template <typename V, typename R>
+    LBM_HD static V get(const void *lds, int nslot, int f, int i, int slot, const CavityConst<R> &c) {
+        const float *P = (const float *)lds;
+        if (i == 0) return (V)P[(2 * f) * nslot + slot];
+        const V beta = (V)P[(2 * f + 1) * nslot + slot];
+        const uint16_t *Qp = (const uint16_t *)(P + 6 * nslot);
+        const V r = (V)E16::dec(Qp[(8 * f + i - 1) * nslot + slot]);
+        return w_of<V>(i) * beta + r * (V)c.inv_scale[f];
     }
 };
 
@@ -1125,15 +1195,9 @@ LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *sr
     Macro<R> m;
     const R sr_prev = sr_src[flat_index(c, xx, y)];
     const RH srf = update_node<Sh::QT, R, RH, true>(c, g, xx, y, qf, qg, qh, sr_prev, owned, acc, th, m);
-    using Cd = typename Sh::Codec;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        Cd::put(lds_q, Sh::NSLOT, 0, i, s, qf[i]);
-        if (i < Sh::QT) {
-            Cd::put(lds_q, Sh::NSLOT, 1, i, s, qg[i]);
-            Cd::put(lds_q, Sh::NSLOT, 2, i, s, qh[i]);
-        }
-    }
+    const ThermalConst<RH> &t = thermal<RH>(c);
+    Sh::Codec::put_node(lds_q, Sh::NSLOT, s, c, qf, qg, qh, m.drho, t.c_fref * (th.Tf - t.T_ref),
+                        c.c_mref * m.dTm);
     lds_sr[s] = (R)srf;
 }
 
@@ -1141,8 +1205,8 @@ LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *sr
 // its wall partner), in unwrapped coordinates.  x is the node's unwrapped
 // column, xx the wrapped one.
 template <class Sh, typename R, typename RH>
-LBM_HD void lds_gather(const Tile2 &tl, const NodeGeom &g, int x, int xx, int h_region, const void *lds_q,
-                       R qf[9], RH qg[9], R qh[9]) {
+LBM_HD void lds_gather(const CavityConst<R> &c, const Tile2 &tl, const NodeGeom &g, int x, int xx, int h_region,
+                       const void *lds_q, R qf[9], RH qg[9], R qh[9]) {
     using Cd = typename Sh::Codec;
     const int px = x + (g.sx - xx);  // partner column, unwrapped
 #pragma unroll
@@ -1152,10 +1216,10 @@ LBM_HD void lds_gather(const Tile2 &tl, const NodeGeom &g, int x, int xx, int h_
         LBM_HOST_CHECK(g.sy - ey_of(i) - (tl.y0 - Sh::RING) >= 0 &&
                        g.sy - ey_of(i) - (tl.y0 - Sh::RING) < h_region);
         LBM_HOST_CHECK(sl >= 0 && sl < Sh::NSLOT);
-        qf[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 0, i, sl);
+        qf[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 0, i, sl, c);
         if (i < Sh::QT) {
-            qg[i] = Cd::template get<RH>(lds_q, Sh::NSLOT, 1, i, sl);
-            qh[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 2, i, sl);
+            qg[i] = Cd::template get<RH>(lds_q, Sh::NSLOT, 1, i, sl, c);
+            qh[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 2, i, sl, c);
         } else {
             qg[i] = RH(0);
             qh[i] = R(0);
@@ -1193,7 +1257,7 @@ LBM_HD bool stepk_mid_load(const CavityConst<R> &c, const Tile2 &tl, int j, cons
     n.g = geometry(c, n.xx, n.y, true);
     n.slot = lds_slot<Sh>(tl, n.x, n.y);
     LBM_HOST_CHECK(n.slot >= 0 && n.slot < Sh::NSLOT);
-    lds_gather<Sh, R, RH>(tl, n.g, n.x, n.xx, tl.h + 2 * Sh::RING, lds_q, n.qf, n.qg, n.qh);
+    lds_gather<Sh, R, RH>(c, tl, n.g, n.x, n.xx, tl.h + 2 * Sh::RING, lds_q, n.qf, n.qg, n.qh);
     n.sr_prev = lds_sr[n.slot];
     return true;
 }
@@ -1201,19 +1265,13 @@ template <class Lay, typename R, typename RH, int TW, int TH, int K>
 LBM_HD void stepk_mid_store(const CavityConst<R> &c, double *__restrict__ acc, void *lds_q, R *lds_sr,
                             MidNode<R, RH> &n) {
     using Sh = StepKShape<Lay, TW, TH, K>;
-    using Cd = typename Sh::Codec;
     Thermo<RH> th;
     Macro<R> m;
     const RH srf = update_node<Sh::QT, R, RH, true>(c, n.g, n.xx, n.y, n.qf, n.qg, n.qh, n.sr_prev, n.owned, acc,
                                                    th, m);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        Cd::put(lds_q, Sh::NSLOT, 0, i, n.slot, n.qf[i]);
-        if (i < Sh::QT) {
-            Cd::put(lds_q, Sh::NSLOT, 1, i, n.slot, n.qg[i]);
-            Cd::put(lds_q, Sh::NSLOT, 2, i, n.slot, n.qh[i]);
-        }
-    }
+    const ThermalConst<RH> &t = thermal<RH>(c);
+    Sh::Codec::put_node(lds_q, Sh::NSLOT, n.slot, c, n.qf, n.qg, n.qh, m.drho, t.c_fref * (th.Tf - t.T_ref),
+                        c.c_mref * m.dTm);
     lds_sr[n.slot] = (R)srf;
 }
 
@@ -1230,7 +1288,7 @@ LBM_HD void stepk_last(const CavityConst<R> &c, const Tile2 &tl, void *dst, R *_
     const NodeGeom g = geometry(c, x, y, true);
     R qf[9], qh[9];
     RH qg[9];
-    lds_gather<Sh, R, RH>(tl, g, x, x, tl.h + 2 * Sh::RING, lds_q, qf, qg, qh);
+    lds_gather<Sh, R, RH>(c, tl, g, x, x, tl.h + 2 * Sh::RING, lds_q, qf, qg, qh);
     const int self = lds_slot<Sh>(tl, x, y);
     const int yb = tile_first_row<R, K>(c, tl);
     const NodeRef k = band_origin(c, yb)(x, y);

@@ -1,11 +1,11 @@
-"""GPU checks of the K-steps-per-launch kernels (K = 2, and K = 3 for the FP32 forms):
+"""GPU checks of the K-steps-per-launch kernels (K = 2, 3; K = 2 only for FP64):
 the state crosses HBM once per K steps through LDS tiles, and the result
 must be the same map as K single steps, bit for bit (populations, sources,
 FP64 wall tallies and diagnostics), on every geometry the single-step path
 handles: walls and corners, periodic channels, ragged and batched cavities,
 mixed wall types, the bounce-back alternative, both thermal lattices, FP32,
-FP64 and FP32 with the FP64 rest enthalpy population, step counts that
-leave a remainder and graph replays.
+FP64, FP32 with the FP64 rest enthalpy population and the 16-bit forms, step
+counts that leave a remainder and graph replays.
 """
 import numpy as np
 import pytest
@@ -84,3 +84,19 @@ def test_three_steps_per_launch_are_bitwise_three_single_steps(lbm, case, qt, pr
         assert np.array_equal(a, b) and np.array_equal(a, m)
         for k in ("flux_E", "flux_M", "E_int", "M_int", "liquid_fraction", "Nu_hot"):
             assert da[k] == db[k] == dm[k], k
+
+
+@pytest.mark.parametrize("case", ["c1", "ragged", "periodic", "corner", "batch"])
+@pytest.mark.parametrize("prec", ["f16split", "f16", "bf16"])
+@pytest.mark.parametrize("spl", [2, 3])
+def test_16bit_multi_step_is_bitwise_single_steps(lbm, case, prec, spl):
+    # the LDS holds the 16-bit codes (and the split form's FP32 rest
+    # populations and bases) exactly as the global state stores them
+    ps = CASES[case]()
+    steps = 100
+    ref = _run(lbm, ps, prec, steps, 1, lambda n: [1] * n)
+    got = _run(lbm, ps, prec, steps, spl, lambda n: [n])
+    for (a, da), (b, db) in zip(ref, got):
+        assert np.array_equal(a, b)
+        for k in ("flux_E", "flux_M", "E_int", "M_int", "liquid_fraction"):
+            assert (da[k] == db[k]) or (np.isnan(da[k]) and np.isnan(db[k])), k
