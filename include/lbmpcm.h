@@ -191,9 +191,7 @@ typedef struct lbm_launch_config {
                                  every form); 3: three steps per launch (a
                                  two-node ring, the middle step in place in
                                  LDS; every form but LBM_F64).  Default: the
-                                 most the form has when every cavity's rows
-                                 are 32-node aligned (nx % 32 == 0) or at
-                                 least 1024 wide, else 1.
+                                 most the form has.
                                  block and nodes_per_thread then do not apply. */
 } lbm_launch_config;
 

@@ -87,6 +87,8 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     // the step kernels address a tile's rows by 32-bit byte offsets from its
     // first row: a few dozen rows of 8-byte elements must stay below 2^31
     if (p.nx > LBM_MAX_NX) return fail(LBM_EINVAL, "grid %dx%d: rows longer than %d nodes", p.nx, p.ny, LBM_MAX_NX);
+    if ((int64_t)((p.nx + 63) & ~63) * p.ny >= ((int64_t)1 << 31) - 4096)
+        return fail(LBM_EINVAL, "grid %dx%d: rows padded to 64 nodes exceed 2^31 nodes", p.nx, p.ny);
     if (p.band_rows < 0 || (p.band_rows > 0 && p.band_rows < min_band_rows(p.nx) && p.band_rows < p.ny))
         return fail(LBM_EINVAL, "band_rows %d: need 0 or at least %d (or the cavity's %d rows)", p.band_rows,
                     min_band_rows(p.nx), p.ny);
@@ -292,22 +294,25 @@ ThermalConst<T> make_thermal(const Lattice &l) {
 // Banded placement of one cavity's populations in a state buffer.
 struct Bands {
     int rows;       // rows per band
-    int64_t nodes;  // plane stride within a band (rows * nx, rounded up)
+    int pitch;      // row pitch: nx rounded up to 64 nodes
+    int64_t nodes;  // plane stride within a band (rows * pitch, rounded up)
     int64_t bytes;  // bytes of one band's block
     int64_t off;    // byte offset of the cavity's first block
     int count;      // number of bands
 };
 
 // Rows per band: about LBM_BAND_BYTES of state per block (or the rows the
-// caller asked for), at least min_band_rows, at most the cavity.  The plane stride is a multiple of 128 nodes, so every plane of
-// every block starts 256-byte aligned.
+// caller asked for), at least min_band_rows, at most the cavity.  Rows are
+// padded to a pitch of 64 nodes and the plane stride is a multiple of 128
+// nodes, so every row of every plane starts on a cache-line boundary.
 Bands bands_of(int nx, int ny, int bpn, int64_t off, int rows_wanted) {
     Bands b;
-    int64_t rows = LBM_BAND_BYTES / ((int64_t)bpn * nx);
+    b.pitch = (nx + 63) & ~63;
+    int64_t rows = LBM_BAND_BYTES / ((int64_t)bpn * b.pitch);
     rows = std::max<int64_t>(rows, min_band_rows(nx));
     if (rows_wanted > 0) rows = rows_wanted;
     b.rows = (int)std::min<int64_t>(rows, ny);
-    b.nodes = ((int64_t)b.rows * nx + 127) & ~(int64_t)127;
+    b.nodes = ((int64_t)b.rows * b.pitch + 127) & ~(int64_t)127;
     b.bytes = (int64_t)bpn * b.nodes;
     b.off = off;
     b.count = (ny + b.rows - 1) / b.rows;
@@ -325,6 +330,7 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0, const B
     c.node0 = node0;
     c.acc0 = acc0;
     c.band_rows = bd.rows;
+    c.pitch = bd.pitch;
     c.band_nodes = bd.nodes;
     c.band_bytes = bd.bytes;
     c.pop_off = bd.off;
@@ -505,7 +511,8 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
         pl.slots += 2 * ((int64_t)p[c].nx + p[c].ny);
         pl.max_nodes = std::max(pl.max_nodes, nn);
         // interior rows and the wall ring, in tiles of at least 64 nodes
-        tiles += ((int64_t)p[c].nx * (p[c].ny - 2) + 63) / 64 + 1 + 2 * (((int64_t)p[c].nx + 63) / 64);
+        const int64_t pitch = (p[c].nx + 63) & ~63;
+        tiles += (pitch * (p[c].ny - 2) + 63) / 64 + 1 + 2 * (((int64_t)p[c].nx + 63) / 64);
     }
     if (pl.nodes >= ((int64_t)1 << 31) - 1024) return fail(LBM_EINVAL, "more than 2^31 nodes in total");
     if (tiles >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
@@ -641,10 +648,12 @@ lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
     for (int c = 0; c < h->n; ++c) {
         h->cav_tile0[c] = (int)h->tiles.size();
         const int nx = h->params[c].nx, ny = h->params[c].ny;
-        // interior tiles start on 64-node boundaries of the cavity (which is
-        // 64-aligned in the packed index); lanes on row 0 idle
-        for (int k0 = (nx / 64) * 64; k0 < nx * (ny - 1); k0 += tw)
-            h->tiles.push_back(Tile{c, TILE_INTERIOR, k0, std::min(nx * (ny - 1), k0 + tw)});
+        const int pitch = h->pl.bands[c].pitch;
+        // interior tiles run over the pitched index k = y * pitch + x of
+        // rows 1..ny-2 (rows start on 64-node boundaries, so every wavefront
+        // stores whole cache lines; lanes on the padding idle)
+        for (int k0 = pitch; k0 < pitch * (ny - 1); k0 += tw)
+            h->tiles.push_back(Tile{c, TILE_INTERIOR, k0, std::min(pitch * (ny - 1), k0 + tw)});
         // wall tiles hold nodes of one row (the bottom or the top)
         for (int row = 0; row < 2; ++row)
             for (int r0 = row * nx; r0 < (row + 1) * nx; r0 += tw)
@@ -843,15 +852,9 @@ lbm_status setup(lbm_handle *h) {
         HIP_TRY(hipMemcpyAsync(h->cav(), t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     }
-    // Several steps per launch by default where it measured faster: three
-    // where the three-step kernel exists (the FP32 forms), else two, with
-    // every cavity's rows 32-node aligned or at least 1024 nodes wide.
-    // Batches of narrow, unaligned cavities (a tile row then writes partial
-    // cache lines shared with its neighbour) stay at one step per launch.
-    bool multi = true;
-    for (int c = 0; c < h->n; ++c)
-        if (!(h->params[c].nx % 32 == 0 || h->params[c].nx >= 1024)) multi = false;
-    h->lc.steps_per_launch = !multi ? 1 : (h->pl.tilesk[3] > 0 ? 3 : (h->pl.tilesk[2] > 0 ? 2 : 1));
+    // By default the most steps per launch the form has (measured faster
+    // for every cavity size and batch, the rows being padded to 64 nodes).
+    h->lc.steps_per_launch = h->pl.tilesk[3] > 0 ? 3 : (h->pl.tilesk[2] > 0 ? 2 : 1);
     lbm_status s = build_tiles(h, h->lc);
     if (s != LBM_OK) return s;
     s = build_tilesk(h);
@@ -1404,7 +1407,8 @@ extern "C" lbm_status lbm_copy_state(lbm_handle *h, int32_t c, void *host, uint6
             for (int b = 0; b < bd.count; ++b) {
                 const int rows = std::min(bd.rows, ny - b * bd.rows);
                 const char *src = blocks + (size_t)b * bd.bytes + group_off + (size_t)p * bd.nodes * eb;
-                HIP_TRY(hipMemcpy(dst, src, (size_t)rows * nx * eb, hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy2D(dst, (size_t)nx * eb, src, (size_t)bd.pitch * eb, (size_t)nx * eb, rows,
+                                    hipMemcpyDeviceToHost));
                 dst += (size_t)rows * nx * eb;
             }
         }
@@ -1425,7 +1429,7 @@ extern "C" lbm_status lbm_debug_poke(lbm_handle *h, int32_t c, int32_t x, int32_
     // the node's band block, its index within the band, the plane stride
     const Bands &bd = h->pl.bands[c];
     const int b = y / bd.rows;
-    const int64_t node = (int64_t)(y - b * bd.rows) * p.nx + x;
+    const int64_t node = (int64_t)(y - b * bd.rows) * bd.pitch + x;
     const size_t S = (size_t)bd.nodes;
     char *base = (char *)h->pop(h->cur) + bd.off + (size_t)b * bd.bytes;
     char *ptr;

@@ -54,11 +54,13 @@ struct CavityConst {
     // Populations are stored by bands: rows [b * band_rows, (b + 1) *
     // band_rows) of the cavity form band b, a block of band_bytes holding
     // every population plane of those rows (node (x, y) at index
-    // (y - b * band_rows) * nx + x of a plane, plane stride band_nodes).  The
-    // cavity's blocks follow each other from byte pop_off of a state buffer.
-    // Kept to a few hundred MiB, a block keeps the planes a tile reads and
-    // writes close together in the address space.
-    int32_t band_rows;
+    // (y - b * band_rows) * pitch + x of a plane, plane stride band_nodes).
+    // The cavity's blocks follow each other from byte pop_off of a state
+    // buffer.  Kept to a few hundred MiB, a block keeps the planes a tile
+    // reads and writes close together in the address space; the row pitch
+    // (nx rounded up to 64 nodes, the padding never read or written) starts
+    // every row of every plane on a cache-line boundary.
+    int32_t band_rows, pitch;
     int64_t band_nodes, band_bytes, pop_off;
     // materials
     R phi, inv_phi, inv_cpm, c_pm, c_mref;

@@ -75,7 +75,7 @@ __device__ __forceinline__ int remap_block(int b, int grid, int xcd_remap) {
 // The tile of one workgroup.  Accesses are 32-bit offsets from the block of
 // the band of a row the workgroup shares: for interior tiles the row before
 // their first one (the pulls reach one row either side; a tile of at most
-// 2048 nodes then spans at most 2048 / nx + 3 <= LBM_MIN_BAND_ROWS rows),
+// 2048 pitched nodes then spans at most 2048 / nx + 3 rows, so two bands),
 // for wall tiles (one row each) the first of the three rows their wall
 // partners pull from.  Both kinds share one instantiation of the node
 // update (decided per node), so the kernel holds a single copy of the
@@ -91,7 +91,7 @@ __device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__
     if (wall) {
         yb = tl.k0 < c.nx ? 0 : c.ny - 3;
     } else {
-        const int y0 = tl.k0 / c.nx;
+        const int y0 = tl.k0 / c.pitch;
         yb = y0 >= 1 ? y0 - 1 : 0;
     }
     const BandOrigin org = band_origin(c, yb);
@@ -106,12 +106,13 @@ __device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__
             if (wall) {
                 ring_node(c, k, x, y);
             } else {
-                y = k / c.nx;
-                x = k - y * c.nx;
+                y = k / c.pitch;
+                x = k - y * c.pitch;
             }
-            // interior tiles cover whole rows: the wall columns ride along
-            // (each stored cache line then has one writer); lanes on row 0 idle
-            if (wall || y >= 1)
+            // interior tiles cover whole (pitched) rows: the wall columns ride
+            // along (each stored cache line then has one writer); lanes on
+            // the row padding idle
+            if (wall || x < c.nx)
                 step_node_at<Lay, R, RH, PULL, NODE_ANY>(c, sblk, dblk, sr_src, sr_dst, acc, x, y, org);
         }
     }

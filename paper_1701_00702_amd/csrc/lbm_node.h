@@ -797,29 +797,29 @@ LBM_HD void ring_node(const CavityConst<R> &c, int r, int &x, int &y) {
 // span at most two bands).  AnyBand: any row, from the cavity's first block.
 struct BandOrigin {
     int y_first, y_next;  // first rows of bands ba and ba + 1
-    int nx;
+    int pitch;
     uint32_t band_bytes;
     LBM_HD NodeRef operator()(int x, int y) const {
-        return y < y_next ? NodeRef{(uint32_t)((y - y_first) * nx + x), 0u}
-                          : NodeRef{(uint32_t)((y - y_next) * nx + x), band_bytes};
+        return y < y_next ? NodeRef{(uint32_t)((y - y_first) * pitch + x), 0u}
+                          : NodeRef{(uint32_t)((y - y_next) * pitch + x), band_bytes};
     }
 };
 struct AnyBand {
-    int band_rows, nx;
+    int band_rows, pitch;
     int64_t band_bytes;
     LBM_HD FarRef operator()(int x, int y) const {
         const int b = y / band_rows;
-        return FarRef{(int64_t)(y - b * band_rows) * nx + x, (int64_t)b * band_bytes};
+        return FarRef{(int64_t)(y - b * band_rows) * pitch + x, (int64_t)b * band_bytes};
     }
 };
 template <typename R>
 LBM_HD BandOrigin band_origin(const CavityConst<R> &c, int y) {  // from the band of row y
     const int ba = y / c.band_rows;
-    return BandOrigin{ba * c.band_rows, (ba + 1) * c.band_rows, c.nx, (uint32_t)c.band_bytes};
+    return BandOrigin{ba * c.band_rows, (ba + 1) * c.band_rows, c.pitch, (uint32_t)c.band_bytes};
 }
 template <typename R>
 LBM_HD AnyBand any_band(const CavityConst<R> &c) {
-    return AnyBand{c.band_rows, c.nx, c.band_bytes};
+    return AnyBand{c.band_rows, c.pitch, c.band_bytes};
 }
 // The block of band b of cavity c in a state buffer.
 template <typename R, typename V>
