@@ -1,11 +1,12 @@
 """Throughput of the fused three-field MRT step on one MI355X.
 
 Prints one JSON line.  A step advances every node of the workload by one
-time step; the library's default launch does two steps per launch through
-LDS tiles (FP32/FP64 storage), bit-identical to two one-step launches, and
-the one-step kernel is timed beside it.  Workload (default: the 8192 x 8192 cavity, Ra = 1e7, Da = 1e-5,
-phi = 0.9, Ste = 0.5, lambda = 1000, FP32 storage, 67.1 M nodes, 15 GB of
-double-buffered populations).  Inputs are resident in HBM before timing;
+time step; the library's default launch does three steps per launch
+through LDS tiles (two for FP64 storage), bit-identical to one-step
+launches, and the one-step kernel is timed beside it.  Workload (default:
+the 8192 x 8192 cavity, Ra = 1e7, Da = 1e-5, phi = 0.9, Ste = 0.5,
+lambda = 1000, FP32 storage, 67.1 M nodes, 15 GB of double-buffered
+populations).  Inputs are resident in HBM before timing;
 the timed region is bracketed by HIP events on the stream the kernels run
 on.  MLUPS counts every node (walls included) advancing all 27 populations.
 

@@ -113,7 +113,7 @@ __device__ __forceinline__ void step_tile(const void *__restrict__ src, void *__
             // along (each stored cache line then has one writer); lanes on
             // the row padding idle
             if (wall || x < c.nx)
-                step_node_at<Lay, R, RH, PULL, NODE_ANY>(c, sblk, dblk, sr_src, sr_dst, acc, x, y, org);
+                step_node_at<Lay, R, RH, PULL>(c, sblk, dblk, sr_src, sr_dst, acc, x, y, org);
         }
     }
 }

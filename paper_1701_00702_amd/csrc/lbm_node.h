@@ -763,21 +763,6 @@ LBM_HD NodeGeom geometry(const CavityConst<R> &c, int x, int y, bool pull) {
     return g;
 }
 
-// Node kinds a kernel instantiation handles: interior nodes only, wall
-// nodes only, or either (decided per node).
-enum { NODE_INTERIOR = 0, NODE_WALL = 1, NODE_ANY = 2 };
-
-template <typename R, int KIND>
-LBM_HD NodeGeom geometry_of(const CavityConst<R> &c, int x, int y, bool pull) {
-    NodeGeom g = geometry(c, x, y, pull);
-    if (KIND == NODE_INTERIOR) g.wall = false;
-    if (KIND == NODE_WALL) {
-        g.wall = true;
-        g.near_x = g.near_y = false;
-    }
-    return g;
-}
-
 // Position of wall node r of the bottom and top rows (the wall columns are
 // handled with their rows).
 template <typename R>
@@ -964,14 +949,12 @@ LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, 
     return srf;
 }
 
-// One node's full time step.  KIND selects which of the interior and wall
-// code paths this instantiation carries (the caller guarantees the node is
-// of that kind); addr places the node and its neighbours relative to the
-// band blocks src and dst.
-template <class Lay, typename R, typename RH, bool PULL, int KIND, class A>
+// One node's full time step; addr places the node and its neighbours
+// relative to the band blocks src and dst.
+template <class Lay, typename R, typename RH, bool PULL, class A>
 LBM_HD void step_node_at(const CavityConst<R> &c, const void *src, void *dst, const R *__restrict__ sr_src,
                          R *__restrict__ sr_dst, double *__restrict__ acc, int x, int y, A addr) {
-    const NodeGeom g = geometry_of<R, KIND>(c, x, y, PULL);
+    const NodeGeom g = geometry(c, x, y, PULL);
     R qf[9], qh[9];
     RH qg[9];
     gather_at<Lay, R, RH, PULL>(c, src, g, x, y, addr, qf, qg, qh);
@@ -989,11 +972,11 @@ LBM_HD void step_node_at(const CavityConst<R> &c, const void *src, void *dst, co
 }
 
 // The same on whole state buffers.
-template <class Lay, typename R, typename RH, bool PULL, int KIND = NODE_ANY>
+template <class Lay, typename R, typename RH, bool PULL>
 LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, const R *__restrict__ sr_src,
                       R *__restrict__ sr_dst, double *__restrict__ acc, int x, int y) {
-    step_node_at<Lay, R, RH, PULL, KIND>(c, band_block(c, src, 0), band_block(c, dst, 0), sr_src, sr_dst, acc,
-                                         x, y, any_band(c));
+    step_node_at<Lay, R, RH, PULL>(c, band_block(c, src, 0), band_block(c, dst, 0), sr_src, sr_dst, acc, x, y,
+                                   any_band(c));
 }
 
 // ---------------------------------------------------------------------------
@@ -1146,8 +1129,6 @@ struct StepKShape {
     static constexpr size_t LDS_BYTES = Codec::bytes(NSLOT);
     static_assert(TH + 2 * K <= LBM_MIN_BAND_ROWS, "a tile's rows must span at most two bands");
 };
-template <class Lay, int TW, int TH>
-using Step2Shape = StepKShape<Lay, TW, TH, 2>;
 
 // Global accesses of a tile go through 32-bit offsets from the block of the
 // band of the first row any update touches, y0 - K (the first update's ring
