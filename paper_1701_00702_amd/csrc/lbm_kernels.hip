@@ -223,13 +223,21 @@ template <>
 struct Step2Tile<ST_F16S> {  // 6 x 4 + 24 x 2 + 4 = 76 B per slot, 34 x 15 slots (38 KiB: 4 per CU)
     static constexpr int TW = 32, TH = 13, NT = 512;
 };
+#ifndef LBM_S2_F64_TW
+#define LBM_S2_F64_TW 32
+#define LBM_S2_F64_TH 5
+#endif
 template <>
-struct Step2Tile<ST_F64> {  // 27 x 8 + 8 = 224 B per slot, 18 x 16 slots
-    static constexpr int TW = 16, TH = 14, NT = 320;
+struct Step2Tile<ST_F64> {  // 27 x 8 + 8 = 224 B per slot (default 34 x 7 slots, 53 KiB)
+    static constexpr int TW = LBM_S2_F64_TW, TH = LBM_S2_F64_TH, NT = round64((TW + 2) * (TH + 2));
 };
+#ifndef LBM_S2_F64Q5_TW
+#define LBM_S2_F64Q5_TW 32
+#define LBM_S2_F64Q5_TH 8
+#endif
 template <>
-struct Step2Tile<ST5_F64> {  // 19 x 8 + 8 = 160 B per slot, 18 x 22 slots
-    static constexpr int TW = 16, TH = 20, NT = 448;
+struct Step2Tile<ST5_F64> {  // 19 x 8 + 8 = 160 B per slot (default 34 x 10 slots, 56 KiB)
+    static constexpr int TW = LBM_S2_F64Q5_TW, TH = LBM_S2_F64Q5_TH, NT = round64((TW + 2) * (TH + 2));
 };
 
 // One tile per workgroup, or (LOOP) a grid-stride walk over the tiles for
