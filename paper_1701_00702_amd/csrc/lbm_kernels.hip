@@ -314,17 +314,25 @@ template <>
 struct Step3Tile<ST5_F32> {  // 80 B per slot (default 36 x 14 slots, 39 KiB: 4 per CU)
     static constexpr int TW = LBM_S3_F32Q5_TW, TH = LBM_S3_F32Q5_TH, NT = round64((TW + 4) * (TH + 4));
 };
+#ifndef LBM_S3_F16_TW
+#define LBM_S3_F16_TW 32
+#define LBM_S3_F16_TH 10
+#endif
+#ifndef LBM_S3_F16S_TW
+#define LBM_S3_F16S_TW 32
+#define LBM_S3_F16S_TH 10
+#endif
 template <>
-struct Step3Tile<ST_F16> {  // 58 B per slot, 36 x 14 slots (29 KiB)
-    static constexpr int TW = 32, TH = 10, NT = 512;
+struct Step3Tile<ST_F16> {  // 58 B per slot (default 36 x 14 slots, 29 KiB)
+    static constexpr int TW = LBM_S3_F16_TW, TH = LBM_S3_F16_TH, NT = round64((TW + 4) * (TH + 4));
 };
 template <>
 struct Step3Tile<ST_BF16> {
-    static constexpr int TW = 32, TH = 10, NT = 512;
+    static constexpr int TW = LBM_S3_F16_TW, TH = LBM_S3_F16_TH, NT = round64((TW + 4) * (TH + 4));
 };
 template <>
-struct Step3Tile<ST_F16S> {  // 76 B per slot, 36 x 14 slots (38 KiB: 4 per CU)
-    static constexpr int TW = 32, TH = 10, NT = 512;
+struct Step3Tile<ST_F16S> {  // 76 B per slot (default 36 x 14 slots, 38 KiB)
+    static constexpr int TW = LBM_S3_F16S_TW, TH = LBM_S3_F16S_TH, NT = round64((TW + 4) * (TH + 4));
 };
 template <>
 struct Step3Tile<ST_F32H> {  // 116 B per slot, 36 x 13 slots (53 KiB: 3 per CU)
