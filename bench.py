@@ -268,7 +268,7 @@ def main():
     if args.forms:
         forms = {}
         for wl, pr, q in (("c3", "f32h64", 9), ("c3", "f16split", 9), ("c3", "f16", 9), ("c3", "bf16", 9),
-                          ("c4", "f32", 9), ("c4", "f16split", 9),
+                          ("c4", "f32", 9), ("c4", "f16split", 9), ("c4", "f16", 9), ("c4", "bf16", 9),
                           ("c3", "f32", 5), ("c3", "f32h64", 5), ("c3", "f64", 5), ("c3", "f64", 9)):
             if q == qt and wl == args.workload and pr == prec:
                 continue
@@ -281,7 +281,8 @@ def main():
             lbm.lbm_set_launch(s2.h, args.block, args.npt, args.xcd, args.persistent,
                                steps_per_launch=args.steps_per_launch or None)
             n2 = ps[0]["nx"] * ps[0]["ny"]
-            t = time_steps(lbm, torch, s2, stream, 100, 10) / 100
+            # 96 steps: whole multi-step launches for two and three steps
+            t = time_steps(lbm, torch, s2, stream, 96, 12) / 96
             name = f"{wl}_d2q5_{pr}" if q == 5 else f"{wl}_{pr}"
             sp2 = lbm.lbm_get_launch(s2.h)["steps_per_launch"]
             forms[name] = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t, "steps_per_launch": sp2,
