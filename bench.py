@@ -152,7 +152,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="c3",
                     help="c2, c3 (default), c4, c5, sq<n> for an n x n cavity (sq<nx>x<ny>), bat<k>x<n> for k of them")
     ap.add_argument("--precision", default=None, choices=[None] + list(BYTES_PER_NODE))
