@@ -39,6 +39,10 @@ BYTES_PER_NODE_D2Q5 = {"f64": 320, "f32": 160, "f32h64": 168}
 def bytes_per_node(precision: str, thermal_lattice: int = 9) -> int:
     return BYTES_PER_NODE_D2Q5[precision] if thermal_lattice == 5 else BYTES_PER_NODE[precision]
 PEAK_HBM_GBPS = 8000.0
+# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one 64-lane wave
+# instruction per CU and clock, 39.3 T lane-instructions/s (unpacked FP32; the
+# 157.3 TFLOP/s vector figure counts packed FMAs, 4 flop per lane and clock)
+PEAK_VALU_GIPS = 256 * 64 * 2.4
 METRIC = "MLUPS (3 coupled MRT fields) + achieved HBM GB/s vs peak; FP16-store vs FP32"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1701_00702_amd", "csrc", n)
                   for n in ("lbm_kernels.hip", "lbm_node.h", "lbm_internal.h", "lbm_api.hip")] + \
@@ -95,6 +99,23 @@ def traffic_from_profile(sha: str, workload_name: str, precision: str, thermal_l
     if not m_sha or not m_b or m_sha.group(1) != sha:
         return None
     return float(m_b.group(1))
+
+
+def valu_from_profile(sha: str, workload_name: str, precision: str, thermal_lattice: int,
+                      steps_per_launch: int):
+    """VALU instructions per node and step of the timed kernel, counted with
+    rocprofv3 (SQ_INSTS_VALU) on the current kernel source, if profiled."""
+    if (workload_name, precision, thermal_lattice) != ("c3", "f32", 9):
+        return None
+    path = os.path.join(ROOT, "profiles", "valu_step_kernels_c3_f32.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernel_sha:\s*(\w+)", text)
+    m_v = re.search(rf"valu_per_node_step_k{steps_per_launch}:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_v or m_sha.group(1) != sha:
+        return None
+    return float(m_v.group(1))
 
 
 def make_solver(lbm, torch, params, precision, stream):
@@ -230,6 +251,7 @@ def main():
     achieved = alg / (launch_ms * 1e-3) / 1e9
     sha = kernel_sha()
     traffic = traffic_from_profile(sha, args.workload, prec, qt, spl)
+    valu = valu_from_profile(sha, args.workload, prec, qt, spl)
     single = None
     if spl > 1:
         # the one-step kernel on the same state, for reference
@@ -255,7 +277,13 @@ def main():
                      "launch_ms": launch_ms, "kernel_sha": sha,
                      # the bytes a one-step sweep would move per step, over the
                      # measured time per step (above peak: temporal blocking)
-                     "per_step_equivalent_GBps": alg / (ms_step * 1e-3) / 1e9},
+                     "per_step_equivalent_GBps": alg / (ms_step * 1e-3) / 1e9,
+                     # the same kernel against the VALU issue rate: counted
+                     # instructions per node-step x node-steps per second
+                     "valu": None if valu is None else {
+                         "instructions_per_node_step": valu,
+                         "achieved_Ginstr_per_s": valu * mlups / 1e3, "peak_Ginstr_per_s": PEAK_VALU_GIPS,
+                         "frac": valu * mlups / 1e3 / PEAK_VALU_GIPS}},
         "check": {"nonfinite": d["nonfinite"], "liquid_fraction": d["liquid_fraction"],
                   "energy_residual_rel": d["energy_residual"] / max(abs(d["E_int"]), 1e-300)},
     }

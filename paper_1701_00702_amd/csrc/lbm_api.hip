@@ -264,6 +264,13 @@ lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l) {
     return LBM_OK;
 }
 
+// 1 / |M_k|^2, the squared norms of the rows of the D2Q9 moment matrix
+// (Eq. 13): 9, 36, 36, 6, 12, 6, 12, 4, 4.
+static double row_norm(int k) {
+    static const double n2[9] = {9, 36, 36, 6, 12, 6, 12, 4, 4};
+    return 1.0 / n2[k];
+}
+
 template <typename T>
 ThermalConst<T> make_thermal(const Lattice &l) {
     ThermalConst<T> t;
@@ -279,7 +286,11 @@ ThermalConst<T> make_thermal(const Lattice &l) {
     t.c_pl = (T)l.c_pl;
     t.c_fref = (T)l.c_fref;
     t.inv_phi = (T)(1.0 / l.phi);
-    for (int k = 0; k < 9; ++k) t.zeta[k] = (T)l.zeta[k];
+    for (int k = 0; k < 9; ++k) {
+        t.zeta[k] = (T)l.zeta[k];
+        t.zA[k] = (T)((1.0 - l.zeta[k]) * row_norm(k));
+        t.zB[k] = (T)(l.zeta[k] * row_norm(k));
+    }
     t.varpi = (T)l.varpi;
     t.inv_cs2 = (T)(l.qt == 9 ? 3.0 : 2.0 / l.varpi);
     t.T_ref = (T)l.T_ref;
@@ -343,6 +354,11 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0, const B
         c.s[k] = (R)l.s[k];
         c.s_half[k] = (R)(1.0 - 0.5 * l.s[k]);
         c.eta[k] = (R)l.eta[k];
+        c.fA[k] = (R)((1.0 - l.s[k]) * row_norm(k));
+        c.fB[k] = (R)(l.s[k] * row_norm(k));
+        c.fC[k] = (R)((1.0 - 0.5 * l.s[k]) * row_norm(k));
+        c.mA[k] = (R)((1.0 - l.eta[k]) * row_norm(k));
+        c.mB[k] = (R)(l.eta[k] * row_norm(k));
     }
     c.gbeta = (R)l.gbeta;
     c.T0 = (R)l.T0;

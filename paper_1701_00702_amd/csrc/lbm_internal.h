@@ -35,6 +35,9 @@ struct ThermalConst {
     // equilibrium (Eq. 34 / Eq. B2) and relaxation rates (Theta, Eq. 31 /
     // App. B; D2Q5 uses the first five in the moment order of Eq. B1)
     T c_pl, c_fref, inv_phi, zeta[9];
+    // D2Q9 rates folded with the row norms of M (Eq. 13):
+    // (1 - zeta_k) / |M_k|^2 and zeta_k / |M_k|^2
+    T zA[9], zB[9];
     // D2Q5: varpi and 1/c_sT^2 = 2/varpi (D2Q9: 1/c_s^2 = 3)
     T varpi, inv_cs2;
     // reference state and the isothermal wall values per wall
@@ -66,6 +69,10 @@ struct CavityConst {
     R phi, inv_phi, inv_cpm, c_pm, c_mref;
     // relaxation rates in moment order and the forcing factors 1 - s/2
     R s[9], s_half[9], eta[9];
+    // the same folded with the row norms of M (Eq. 13), D2Q9: flow
+    // (1 - s_k) / |M_k|^2, s_k / |M_k|^2, (1 - s_k/2) / |M_k|^2; metal
+    // (1 - eta_k) / |M_k|^2, eta_k / |M_k|^2
+    R fA[9], fB[9], fC[9], mA[9], mB[9];
     // flow: buoyancy, porous drag, explicit velocity (Eqs. 3, 7, 23-25)
     R gbeta, T0, drag_lin, drag_quad, l0, l0sq, l1;
     // interstitial exchange (Eqs. 36, 47): Sr_f = hv_f (T_m - T_f), Sr_m = hv_m (T_f - T_m)

@@ -377,50 +377,52 @@ struct LayoutOf<ST5_F32H> {
 };
 
 // ---------------------------------------------------------------------------
-// Moment transforms of Eq. (13) on offsets.  d = M q and q = M^-1 d with
-// M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4).
+// Moment transforms of Eq. (13) on offsets.  d = M q, and q = M^-1 d with
+// M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4): the
+// inverse takes the scaled moments a_k = d_k / |M_k|^2 (|M_k|^2 the squared
+// norm of row k of M), whose factors the collisions fold into their rates.
 // ---------------------------------------------------------------------------
 template <typename R>
 LBM_HD void to_moments(const R q[9], R d[9]) {
-    const R s14 = (q[1] + q[2]) + (q[3] + q[4]);
-    const R s58 = (q[5] + q[6]) + (q[7] + q[8]);
-    d[0] = q[0] + s14 + s58;
+    const R p13 = q[1] + q[3], p24 = q[2] + q[4], m13 = q[1] - q[3], m24 = q[2] - q[4];
+    const R p56 = q[5] + q[6], p78 = q[7] + q[8], m56 = q[5] - q[6], m78 = q[7] - q[8];
+    const R s14 = p13 + p24, s58 = p56 + p78;
+    const R dxd = m56 - m78, dyd = p56 - p78;
+    d[0] = (q[0] + s14) + s58;
     d[1] = fma_of(R(2), s58, fma_of(R(-4), q[0], -s14));
-    d[2] = fma_of(R(-2), s14, R(4) * q[0]) + s58;
-    const R dxd = (q[5] - q[6]) - (q[7] - q[8]);
-    const R dyd = (q[5] + q[6]) - (q[7] + q[8]);
-    d[3] = (q[1] - q[3]) + dxd;
-    d[4] = fma_of(R(2), q[3] - q[1], dxd);
-    d[5] = (q[2] - q[4]) + dyd;
-    d[6] = fma_of(R(2), q[4] - q[2], dyd);
-    d[7] = (q[1] + q[3]) - (q[2] + q[4]);
-    d[8] = (q[5] + q[7]) - (q[6] + q[8]);
+    d[2] = fma_of(R(4), q[0], fma_of(R(-2), s14, s58));
+    d[3] = m13 + dxd;
+    d[4] = fma_of(R(-2), m13, dxd);
+    d[5] = m24 + dyd;
+    d[6] = fma_of(R(-2), m24, dyd);
+    d[7] = p13 - p24;
+    d[8] = m56 + m78;
+}
+
+// 1 / |M_k|^2.
+template <typename R>
+__host__ __device__ constexpr R moment_norm(int k) {
+    return k == 0 ? R(1) / R(9) : (k <= 2 ? R(1) / R(36) : (k == 3 || k == 5 ? R(1) / R(6) : (k <= 6 ? R(1) / R(12) : R(0.25))));
 }
 
 template <typename R>
-LBM_HD void from_moments(const R d[9], R q[9]) {
-    const R a0 = d[0] * (R(1) / R(9));
-    const R a1 = d[1] * (R(1) / R(36));
-    const R a2 = d[2] * (R(1) / R(36));
-    const R a3 = d[3] * (R(1) / R(6));
-    const R a4 = d[4] * (R(1) / R(12));
-    const R a5 = d[5] * (R(1) / R(6));
-    const R a6 = d[6] * (R(1) / R(12));
-    const R a7 = d[7] * R(0.25);
-    const R a8 = d[8] * R(0.25);
-    const R axis = fma_of(R(-2), a2, a0 - a1);
-    const R diag = fma_of(R(2), a1, a0) + a2;
-    const R xa = fma_of(R(-2), a4, a3), ya = fma_of(R(-2), a6, a5);
-    const R xd = a3 + a4, yd = a5 + a6;
-    q[0] = fma_of(R(4), a2, fma_of(R(-4), a1, a0));
-    q[1] = axis + xa + a7;
-    q[2] = axis + ya - a7;
-    q[3] = axis - xa + a7;
-    q[4] = axis - ya - a7;
-    q[5] = diag + xd + yd + a8;
-    q[6] = diag - xd + yd - a8;
-    q[7] = diag - xd - yd + a8;
-    q[8] = diag + xd - yd - a8;
+LBM_HD void from_scaled(const R a[9], R q[9]) {
+    const R axis = fma_of(R(-2), a[2], a[0] - a[1]);
+    const R diag = fma_of(R(2), a[1], a[0]) + a[2];
+    const R xa = fma_of(R(-2), a[4], a[3]), ya = fma_of(R(-2), a[6], a[5]);
+    const R xd = a[3] + a[4], yd = a[5] + a[6];
+    const R ap = axis + a[7], am = axis - a[7];
+    const R dp = diag + a[8], dm = diag - a[8];
+    const R u = xd + yd, v = xd - yd;
+    q[0] = fma_of(R(4), a[2], fma_of(R(-4), a[1], a[0]));
+    q[1] = ap + xa;
+    q[3] = ap - xa;
+    q[2] = am + ya;
+    q[4] = am - ya;
+    q[5] = dp + u;
+    q[7] = dp - u;
+    q[6] = dm - v;
+    q[8] = dm + v;
 }
 
 // D2Q5 transforms of Eq. (B1) on offsets: d = M q, and its inverse
@@ -592,10 +594,12 @@ LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R d[9], R q
     S[6] = -S[5];
     S[7] = R(2) * rip * (ux * Fx - uy * Fy);
     S[8] = rip * (ux * Fy + uy * Fx);
-    d[0] = m.drho;
+    // scaled post-collision moments: ((1 - s) d + s eq + (1 - s/2) S) / |M_k|^2
+    R a[9];
+    a[0] = m.drho * moment_norm<R>(0);
 #pragma unroll
-    for (int k = 1; k < 9; ++k) d[k] = fma_of(c.s_half[k], S[k], fma_of(-c.s[k], d[k] - eq[k], d[k]));
-    from_moments(d, q);
+    for (int k = 1; k < 9; ++k) a[k] = fma_of(c.fC[k], S[k], fma_of(c.fB[k], eq[k], c.fA[k] * d[k]));
+    from_scaled(a, q);
 }
 
 // PCM enthalpy collision, Eqs. (32), (34)-(35).
@@ -605,39 +609,41 @@ LBM_HD void collide_pcm(const CavityConst<R> &c, const Thermo<RH> &th, const Mac
     const ThermalConst<RH> &t = thermal<RH>(c);
     const RH dT = th.Tf - t.T_ref;
     const RH jT = t.c_pl * th.Tf * t.inv_phi;
-    RH eq[9];
-    eq[0] = th.dH;
+    RH eq[7];  // eq_0 = delta H; eq_7 = eq_8 = 0
     eq[1] = -RH(4) * th.dH + RH(2) * t.c_fref * dT;
     eq[2] = RH(4) * th.dH - RH(3) * t.c_fref * dT;
     eq[3] = jT * (RH)m.ux;
     eq[4] = -eq[3];
     eq[5] = jT * (RH)m.uy;
     eq[6] = -eq[5];
-    eq[7] = RH(0);
-    eq[8] = RH(0);
+    // scaled moments ((1 - zeta) d + zeta eq + S (1, -2, 1, 0, ...)) / |M_k|^2;
+    // the zeroth moment is conserved (d_0 = eq_0 = delta H), only S moves it
+    RH a[9];
+    a[0] = (d[0] + S_pcm) * moment_norm<RH>(0);
+    a[1] = fma_of(RH(-2) * moment_norm<RH>(1), S_pcm, fma_of(t.zB[1], eq[1], t.zA[1] * d[1]));
+    a[2] = fma_of(moment_norm<RH>(2), S_pcm, fma_of(t.zB[2], eq[2], t.zA[2] * d[2]));
 #pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = fma_of(-t.zeta[k], d[k] - eq[k], d[k]);
-    d[0] += S_pcm;
-    d[1] = fma_of(RH(-2), S_pcm, d[1]);
-    d[2] += S_pcm;
-    from_moments(d, q);
+    for (int k = 3; k < 7; ++k) a[k] = fma_of(t.zB[k], eq[k], t.zA[k] * d[k]);
+    a[7] = t.zA[7] * d[7];
+    a[8] = t.zA[8] * d[8];
+    from_scaled(a, q);
 }
 
 // Metal-foam collision, Eqs. (43), (45)-(46).
 template <typename R>
 LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal, R d[9], R q[9]) {
-    R eq[9];
+    R eq[3];  // eq_3 .. eq_8 = 0
     eq[0] = c.c_pm * m.dTm;
     eq[1] = (-R(4) * c.c_pm + R(2) * c.c_mref) * m.dTm;
     eq[2] = (R(4) * c.c_pm - R(3) * c.c_mref) * m.dTm;
+    // scaled moments ((1 - eta) d + eta eq + S (1, -2, 1, 0, ...)) / |M_k|^2
+    R a[9];
+    a[0] = fma_of(moment_norm<R>(0), S_metal, fma_of(c.mB[0], eq[0], c.mA[0] * d[0]));
+    a[1] = fma_of(R(-2) * moment_norm<R>(1), S_metal, fma_of(c.mB[1], eq[1], c.mA[1] * d[1]));
+    a[2] = fma_of(moment_norm<R>(2), S_metal, fma_of(c.mB[2], eq[2], c.mA[2] * d[2]));
 #pragma unroll
-    for (int k = 3; k < 9; ++k) eq[k] = R(0);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = fma_of(-c.eta[k], d[k] - eq[k], d[k]);
-    d[0] += S_metal;
-    d[1] = fma_of(R(-2), S_metal, d[1]);
-    d[2] += S_metal;
-    from_moments(d, q);
+    for (int k = 3; k < 9; ++k) a[k] = c.mA[k] * d[k];
+    from_scaled(a, q);
 }
 
 // D2Q5 enthalpy collision (Appendix B): equilibrium moments Eq. (B2) on
