@@ -351,8 +351,6 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0, const B
     c.c_pm = (R)l.c_pm;
     c.c_mref = (R)l.c_mref;
     for (int k = 0; k < 9; ++k) {
-        c.s[k] = (R)l.s[k];
-        c.s_half[k] = (R)(1.0 - 0.5 * l.s[k]);
         c.eta[k] = (R)l.eta[k];
         c.fA[k] = (R)((1.0 - l.s[k]) * row_norm(k));
         c.fB[k] = (R)(l.s[k] * row_norm(k));

@@ -67,11 +67,11 @@ struct CavityConst {
     int64_t band_nodes, band_bytes, pop_off;
     // materials
     R phi, inv_phi, inv_cpm, c_pm, c_mref;
-    // relaxation rates in moment order and the forcing factors 1 - s/2
-    R s[9], s_half[9], eta[9];
-    // the same folded with the row norms of M (Eq. 13), D2Q9: flow
-    // (1 - s_k) / |M_k|^2, s_k / |M_k|^2, (1 - s_k/2) / |M_k|^2; metal
-    // (1 - eta_k) / |M_k|^2, eta_k / |M_k|^2
+    // metal relaxation rates in moment order (D2Q5: the first five, Eq. B1)
+    R eta[9];
+    // D2Q9 rates folded with the row norms of M (Eq. 13): flow
+    // (1 - s_k) / |M_k|^2, s_k / |M_k|^2 and the forcing factor
+    // (1 - s_k/2) / |M_k|^2; metal (1 - eta_k) / |M_k|^2, eta_k / |M_k|^2
     R fA[9], fB[9], fC[9], mA[9], mB[9];
     // flow: buoyancy, porous drag, explicit velocity (Eqs. 3, 7, 23-25)
     R gbeta, T0, drag_lin, drag_quad, l0, l0sq, l1;
