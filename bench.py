@@ -169,6 +169,60 @@ def cpu_baseline(params, seed, budget_s=15.0):
                       f"{n} steps, {dt:.1f} s, FP64"}
 
 
+def accuracy(name: str) -> dict:
+    """Full-length runs of the 1024^2 (FP32 forms, 200 000 steps) or the
+    4096^2 (16-bit forms, 100 000 steps) cavity next to the FP64 path on the
+    same GPU, which the parity tests tie to the checker at 1e-10; the
+    checker itself would need hours at these sizes.  Errors in liquid
+    fraction, mid-row melt front, hot-wall Nusselt number and the fields."""
+    from paper_1701_00702_amd import lbm
+    import lbm_workloads as W
+    if name == "c2":
+        p, steps, seed, _ = W.case_c2()
+        forms = ["f64", "f32", "f32h64"]
+    elif name == "c4":
+        p, steps, seed, _ = W.case_c4()
+        forms = ["f64", "f32", "f32h64", "f16split", "f16", "bf16"]
+    else:
+        raise SystemExit("--accuracy takes c2 or c4")
+    T_pcm, T_mf = W.initial_temperatures(p, seed)
+    dT = p["T_hot"] - p["T_cold"]
+    chunk = 10000
+    out, ref = {}, None
+    for prec in forms:
+        s = lbm.Solver(p, prec)
+        s.set_initial(0, T_pcm, T_mf)
+        t0 = time.perf_counter()
+        for done in range(0, steps, chunk):
+            s.step(min(chunk, steps - done))
+            lbm.lbm_synchronize(s.h)
+            print(f"accuracy {name} {prec}: {min(done + chunk, steps)} of {steps} steps", file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        f, d = s.fields(), s.diagnostics(allow_nonfinite=True)
+        s.close()
+        row = {"seconds": wall, "liquid_fraction": d["liquid_fraction"], "x_front_mid": d["x_front_mid"],
+               "Nu_hot": d["Nu_hot"], "energy_residual": d["energy_residual"], "nonfinite": d["nonfinite"]}
+        if ref is None:
+            ref = (f, d)
+        else:
+            rf, rd = ref
+            inner = (slice(1, -1), slice(1, -1))
+            umax = max(np.abs(rf["ux"]).max(), np.abs(rf["uy"]).max(), 1e-300)
+            row["error_vs_f64"] = {
+                "liquid_fraction": abs(d["liquid_fraction"] - rd["liquid_fraction"]),
+                "x_front_mid": abs(d["x_front_mid"] - rd["x_front_mid"]),
+                "Nu_hot_rel": abs(d["Nu_hot"] - rd["Nu_hot"]) / max(abs(rd["Nu_hot"]), 1e-300),
+                "T_pcm": float(np.abs(f["T_pcm"] - rf["T_pcm"])[inner].max() / dT),
+                "T_mf": float(np.abs(f["T_mf"] - rf["T_mf"])[inner].max() / dT),
+                "f_l": float(np.abs(f["f_l"] - rf["f_l"])[inner].max()),
+                "u": float(max(np.abs(f["ux"] - rf["ux"]).max(), np.abs(f["uy"] - rf["uy"]).max()) / umax),
+            }
+        out[prec] = row
+        del f
+    return {"accuracy": name, "nx": p["nx"], "ny": p["ny"], "steps": steps, "seed": seed,
+            "reference": "f64 on the GPU (the FP64 path matches the checker to 1e-10)", "forms": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +242,8 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--forms", action="store_true", help="also time the 16-bit and batched forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy", default=None, choices=["c2", "c4"],
+                    help="only run the full-length error report of the 1024^2 (c2) or 4096^2 (c4) cavity")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration and its bandwidth)")
     args = ap.parse_args()
@@ -215,6 +271,9 @@ def main():
         print(json.dumps({"calibration": "copy", "bytes_read_per_copy": src.numel() * 4,
                           "bytes_written_per_copy": dst.numel() * 4, "copies": 13,
                           "copy_GBps": 2 * src.numel() * 4 / (ms * 1e-3) / 1e9}))
+        return
+    if args.accuracy:
+        print(json.dumps(accuracy(args.accuracy)))
         return
     from paper_1701_00702_amd import lbm
     import lbm_workloads as W
