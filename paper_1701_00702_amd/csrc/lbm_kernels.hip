@@ -268,8 +268,36 @@ __device__ __forceinline__ void stepk_advance(const void *__restrict__ src, void
     if (s < TW * tl.h) stepk_last<Lay, R, RH, TW, TH, K>(c, tl, dst, sr_dst, acc, lds_q, lds_sr, s);
 }
 
-template <class Lay, typename R, typename RH, int TW, int TH, int NT, int K, bool LOOP>
-__global__ __launch_bounds__(NT) void stepk_kernel(const void *__restrict__ src, void *__restrict__ dst,
+// Waves per SIMD a multi-step kernel is built for: as many workgroups per
+// CU as the LDS of one tile allows (160 KiB per CU; at most 32 waves per
+// CU), so that the register budget never holds residency below that.
+template <class Lay, typename R, int TW, int TH, int NT, int K>
+constexpr int stepk_waves_per_eu() {
+    using Sh = StepKShape<Lay, TW, TH, K>;
+    constexpr int lds = (int)(Sh::LDS_BYTES + Sh::NSLOT * sizeof(R));
+    constexpr int by_lds = (160 * 1024) / lds;
+    constexpr int by_waves = 32 / (NT / 64);
+    constexpr int wgs = by_lds < by_waves ? by_lds : by_waves;
+    return (wgs * (NT / 64) + 3) / 4;
+}
+
+// Storage forms whose single-tile multi-step kernels carry that occupancy
+// as a waves-per-EU bound (bit ST of the mask).  Measured on the 8192^2
+// cavity: the FP32 D2Q5 forms keep their registers (50 and 57) and gain
+// 5% (three steps) and 3-4% (two steps) from the schedule the bound
+// selects; FP32 D2Q9 is unchanged (LDS holds it at three workgroups per
+// CU); the 16-bit and D2Q9 FP32_H64 forms fit the bound only by spilling
+// and lose 5-24%.
+#ifndef LBM_WPE_MASK
+#define LBM_WPE_MASK ((1 << ST5_F32) | (1 << ST5_F32H))
+#endif
+template <int ST, class Lay, typename R, int TW, int TH, int NT, int K>
+constexpr int stepk_wpe() {
+    return ((LBM_WPE_MASK >> ST) & 1) ? stepk_waves_per_eu<Lay, R, TW, TH, NT, K>() : 1;
+}
+
+template <class Lay, typename R, typename RH, int TW, int TH, int NT, int K, bool LOOP, int WPE>
+__global__ __launch_bounds__(NT, WPE) void stepk_kernel(const void *__restrict__ src, void *__restrict__ dst,
                                                    const R *__restrict__ sr_src,
                                                    R *__restrict__ sr_dst, double *__restrict__ acc,
                                                    const CavityConst<R> *__restrict__ cav,
@@ -357,11 +385,13 @@ static hipError_t launch_stepk_s(const Step2Launch &L, hipStream_t s) {
     using RH = typename LayoutOf<ST>::RH;
     using Tl = StepKTile<ST, K>;
     if (L.grid >= L.ntiles)
-        hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, false>), dim3(L.grid), dim3(Tl::NT),
+        hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, false,
+                                         stepk_wpe<ST, Lay, R, Tl::TW, Tl::TH, Tl::NT, K>()>),
+                           dim3(L.grid), dim3(Tl::NT),
                            0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     else
-        hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, true>), dim3(L.grid), dim3(Tl::NT),
+        hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, true, 1>), dim3(L.grid), dim3(Tl::NT),
                            0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
     return hipGetLastError();
