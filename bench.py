@@ -337,6 +337,7 @@ def main():
                      # the bytes a one-step sweep would move per step, over the
                      # measured time per step (above peak: temporal blocking)
                      "per_step_equivalent_GBps": alg / (ms_step * 1e-3) / 1e9,
+                     "per_step_equivalent_frac": alg / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBPS,
                      # the same kernel against the VALU issue rate: counted
                      # instructions per node-step x node-steps per second
                      "valu": None if valu is None else {
