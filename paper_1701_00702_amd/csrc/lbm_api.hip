@@ -271,6 +271,13 @@ static double row_norm(int k) {
     return 1.0 / n2[k];
 }
 
+// Factors g_k of the thermal lattice's inverse transform: D2Q9 1/|M_k|^2;
+// D2Q5 (Eq. B1) 1, 1/2, 1/2, 1/4, 1/4.
+static double thermal_factor(const Lattice &l, int k) {
+    static const double g5[5] = {1.0, 0.5, 0.5, 0.25, 0.25};
+    return l.qt == 5 ? (k < 5 ? g5[k] : 0.0) : row_norm(k);
+}
+
 template <typename T>
 ThermalConst<T> make_thermal(const Lattice &l) {
     ThermalConst<T> t;
@@ -287,9 +294,8 @@ ThermalConst<T> make_thermal(const Lattice &l) {
     t.c_fref = (T)l.c_fref;
     t.inv_phi = (T)(1.0 / l.phi);
     for (int k = 0; k < 9; ++k) {
-        t.zeta[k] = (T)l.zeta[k];
-        t.zA[k] = (T)((1.0 - l.zeta[k]) * row_norm(k));
-        t.zB[k] = (T)(l.zeta[k] * row_norm(k));
+        t.zA[k] = (T)((1.0 - l.zeta[k]) * thermal_factor(l, k));
+        t.zB[k] = (T)(l.zeta[k] * thermal_factor(l, k));
     }
     t.varpi = (T)l.varpi;
     t.inv_cs2 = (T)(l.qt == 9 ? 3.0 : 2.0 / l.varpi);
@@ -351,12 +357,11 @@ CavityConst<R> make_const(const Lattice &l, int64_t node0, int64_t acc0, const B
     c.c_pm = (R)l.c_pm;
     c.c_mref = (R)l.c_mref;
     for (int k = 0; k < 9; ++k) {
-        c.eta[k] = (R)l.eta[k];
         c.fA[k] = (R)((1.0 - l.s[k]) * row_norm(k));
         c.fB[k] = (R)(l.s[k] * row_norm(k));
         c.fC[k] = (R)((1.0 - 0.5 * l.s[k]) * row_norm(k));
-        c.mA[k] = (R)((1.0 - l.eta[k]) * row_norm(k));
-        c.mB[k] = (R)(l.eta[k] * row_norm(k));
+        c.mA[k] = (R)((1.0 - l.eta[k]) * thermal_factor(l, k));
+        c.mB[k] = (R)(l.eta[k] * thermal_factor(l, k));
     }
     c.gbeta = (R)l.gbeta;
     c.T0 = (R)l.T0;

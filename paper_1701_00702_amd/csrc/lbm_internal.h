@@ -32,11 +32,12 @@ template <typename T>
 struct ThermalConst {
     // enthalpy -> temperature, liquid fraction (Eqs. 38-39)
     T H_fs, H_fl, T_fs, T_fl, inv_dH, dT_band, inv_cps, inv_cpl;
-    // equilibrium (Eq. 34 / Eq. B2) and relaxation rates (Theta, Eq. 31 /
-    // App. B; D2Q5 uses the first five in the moment order of Eq. B1)
-    T c_pl, c_fref, inv_phi, zeta[9];
-    // D2Q9 rates folded with the row norms of M (Eq. 13):
-    // (1 - zeta_k) / |M_k|^2 and zeta_k / |M_k|^2
+    // equilibrium (Eq. 34 / Eq. B2)
+    T c_pl, c_fref, inv_phi;
+    // relaxation rates Theta (Eq. 31; D2Q5: the first five in the moment
+    // order of Eq. B1) folded with the factors g_k of the inverse transform
+    // (D2Q9: 1/|M_k|^2 of Eq. 13; D2Q5: 1, 1/2, 1/2, 1/4, 1/4 of Eq. B1):
+    // (1 - zeta_k) g_k and zeta_k g_k
     T zA[9], zB[9];
     // D2Q5: varpi and 1/c_sT^2 = 2/varpi (D2Q9: 1/c_s^2 = 3)
     T varpi, inv_cs2;
@@ -67,11 +68,10 @@ struct CavityConst {
     int64_t band_nodes, band_bytes, pop_off;
     // materials
     R phi, inv_phi, inv_cpm, c_pm, c_mref;
-    // metal relaxation rates in moment order (D2Q5: the first five, Eq. B1)
-    R eta[9];
-    // D2Q9 rates folded with the row norms of M (Eq. 13): flow
-    // (1 - s_k) / |M_k|^2, s_k / |M_k|^2 and the forcing factor
-    // (1 - s_k/2) / |M_k|^2; metal (1 - eta_k) / |M_k|^2, eta_k / |M_k|^2
+    // rates folded with the factors of the inverse transform: flow (D2Q9,
+    // 1/|M_k|^2 of Eq. 13) (1 - s_k) / |M_k|^2, s_k / |M_k|^2 and the forcing
+    // factor (1 - s_k/2) / |M_k|^2; metal (1 - eta_k) g_k, eta_k g_k with the
+    // thermal lattice's g_k (D2Q5: 1, 1/2, 1/2, 1/4, 1/4 of Eq. B1)
     R fA[9], fB[9], fC[9], mA[9], mB[9];
     // flow: buoyancy, porous drag, explicit velocity (Eqs. 3, 7, 23-25)
     R gbeta, T0, drag_lin, drag_quad, l0, l0sq, l1;

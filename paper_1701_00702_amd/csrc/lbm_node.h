@@ -426,7 +426,9 @@ LBM_HD void from_scaled(const R a[9], R q[9]) {
 }
 
 // D2Q5 transforms of Eq. (B1) on offsets: d = M q, and its inverse
-// q0 = d0 - d3, q1,3 = (d3 + d4)/4 +- d1/2, q2,4 = (d3 - d4)/4 +- d2/2.
+// q0 = d0 - d3, q1,3 = (d3 + d4)/4 +- d1/2, q2,4 = (d3 - d4)/4 +- d2/2,
+// taken from e_k = g_k d_k with g = (1, 1/2, 1/2, 1/4, 1/4), whose factors
+// the collisions fold into their rates (powers of two: the same bits).
 template <typename R>
 LBM_HD void to_moments5(const R q[9], R d[5]) {
     const R ax = q[1] + q[3], ay = q[2] + q[4];
@@ -438,14 +440,13 @@ LBM_HD void to_moments5(const R q[9], R d[5]) {
 }
 
 template <typename R>
-LBM_HD void from_moments5(const R d[5], R q[9]) {
-    const R a = (d[3] + d[4]) * R(0.25), b = (d[3] - d[4]) * R(0.25);
-    const R hx = d[1] * R(0.5), hy = d[2] * R(0.5);
-    q[0] = d[0] - d[3];
-    q[1] = a + hx;
-    q[3] = a - hx;
-    q[2] = b + hy;
-    q[4] = b - hy;
+LBM_HD void from_scaled5(const R e[5], R q[9]) {
+    const R a = e[3] + e[4], b = e[3] - e[4];
+    q[0] = fma_of(R(-4), e[3], e[0]);
+    q[1] = a + e[1];
+    q[3] = a - e[1];
+    q[2] = b + e[2];
+    q[4] = b - e[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -647,39 +648,37 @@ LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal,
 }
 
 // D2Q5 enthalpy collision (Appendix B): equilibrium moments Eq. (B2) on
-// offsets, Theta in the moment order of Eq. (B1), source S (1, 0, 0, varpi, 0).
+// offsets, Theta in the moment order of Eq. (B1), source S (1, 0, 0, varpi, 0);
+// scaled moments e_k = g_k ((1 - zeta_k) d_k + zeta_k eq_k + S_k), the
+// zeroth moment conserved (d_0 = eq_0 = delta H) so only S moves it.
 template <typename R, typename RH>
 LBM_HD void collide_pcm5(const CavityConst<R> &c, const Thermo<RH> &th, const Macro<R> &m, RH S_pcm,
                          RH d[9], RH q[9]) {
     const ThermalConst<RH> &t = thermal<RH>(c);
     const RH jT = t.c_pl * th.Tf * t.inv_phi;
-    RH eq[5];
-    eq[0] = th.dH;
-    eq[1] = jT * (RH)m.ux;
-    eq[2] = jT * (RH)m.uy;
-    eq[3] = t.varpi * t.c_fref * (th.Tf - t.T_ref);
-    eq[4] = RH(0);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) d[k] = fma_of(-t.zeta[k], d[k] - eq[k], d[k]);
-    d[0] += S_pcm;
-    d[3] = fma_of(t.varpi, S_pcm, d[3]);
-    from_moments5(d, q);
+    const RH eq1 = jT * (RH)m.ux, eq2 = jT * (RH)m.uy;  // eq_4 = 0
+    const RH eq3 = t.varpi * t.c_fref * (th.Tf - t.T_ref);
+    RH e[5];
+    e[0] = d[0] + S_pcm;
+    e[1] = fma_of(t.zB[1], eq1, t.zA[1] * d[1]);
+    e[2] = fma_of(t.zB[2], eq2, t.zA[2] * d[2]);
+    e[3] = fma_of(t.varpi * RH(0.25), S_pcm, fma_of(t.zB[3], eq3, t.zA[3] * d[3]));
+    e[4] = t.zA[4] * d[4];
+    from_scaled5(e, q);
 }
 
-// D2Q5 metal-foam collision (Appendix B): Eq. (B4), Q, S (1, 0, 0, varpi, 0).
+// D2Q5 metal-foam collision (Appendix B): Eq. (B4), Q, S (1, 0, 0, varpi, 0),
+// in the scaled moments of from_scaled5.
 template <typename R>
 LBM_HD void collide_metal5(const CavityConst<R> &c, const Macro<R> &m, R S_metal, R d[9], R q[9]) {
-    R eq[5];
-    eq[0] = c.c_pm * m.dTm;
-    eq[1] = R(0);
-    eq[2] = R(0);
-    eq[3] = c.varpi * c.c_mref * m.dTm;
-    eq[4] = R(0);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) d[k] = fma_of(-c.eta[k], d[k] - eq[k], d[k]);
-    d[0] += S_metal;
-    d[3] = fma_of(c.varpi, S_metal, d[3]);
-    from_moments5(d, q);
+    const R eq0 = c.c_pm * m.dTm, eq3 = c.varpi * c.c_mref * m.dTm;  // eq_1 = eq_2 = eq_4 = 0
+    R e[5];
+    e[0] = fma_of(c.mB[0], eq0, c.mA[0] * d[0]) + S_metal;
+    e[1] = c.mA[1] * d[1];
+    e[2] = c.mA[2] * d[2];
+    e[3] = fma_of(c.varpi * R(0.25), S_metal, fma_of(c.mB[3], eq3, c.mA[3] * d[3]));
+    e[4] = c.mA[4] * d[4];
+    from_scaled5(e, q);
 }
 
 // Wall whose thermal condition a wall node carries: an isothermal vertical
