@@ -251,7 +251,7 @@ __device__ __forceinline__ void stepk_advance(const void *__restrict__ src, void
                                               const Tile2 &tl, void *lds_q, R *lds_sr) {
     using Sh = StepKShape<Lay, TW, TH, K>;
     const CavityConst<R> &c = cav[tl.cav];
-    // NT >= NSLOT: each thread advances at most one node per update
+    // NT >= NFIRST: each thread advances at most one node per update
     const int s = (int)threadIdx.x;
     if (s < Sh::LW * (tl.h + 2 * Sh::RING))
         stepk_first<Lay, R, RH, TW, TH, K>(c, tl, src, sr_src, acc, lds_q, lds_sr, s);
@@ -262,7 +262,7 @@ __device__ __forceinline__ void stepk_advance(const void *__restrict__ src, void
         const bool act = s < (TW + 2 * j) * (tl.h + 2 * j) &&
                          stepk_mid_load<Lay, R, RH, TW, TH, K>(c, tl, j, lds_q, lds_sr, s, n);
         __syncthreads();  // every pull of this update is in registers
-        if (act) stepk_mid_store<Lay, R, RH, TW, TH, K>(c, acc, lds_q, lds_sr, n);
+        if (act) stepk_mid_store<Lay, R, RH, TW, TH, K>(c, tl, acc, lds_q, lds_sr, n);
         __syncthreads();
     }
     if (s < TW * tl.h) stepk_last<Lay, R, RH, TW, TH, K>(c, tl, dst, sr_dst, acc, lds_q, lds_sr, s);
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(NT, WPE) void stepk_kernel(const void *__restrict__
                                                    const Tile2 *__restrict__ tiles, int ntiles, int xcd_remap) {
     using Sh = StepKShape<Lay, TW, TH, K>;
     static_assert(Sh::LDS_BYTES + Sh::NSLOT * sizeof(R) <= 65536, "tile exceeds 64 KiB of LDS");
-    static_assert(NT >= Sh::NSLOT && NT % 64 == 0, "one thread per slot of the first update");
+    static_assert(NT >= Sh::NFIRST && NT % 64 == 0, "one thread per node of the first update");
     __shared__ __align__(16) unsigned char lds_q[Sh::LDS_BYTES];
     __shared__ R lds_sr[Sh::NSLOT];
     const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
@@ -328,14 +328,14 @@ template <int ST>
 struct Step3Tile;
 #ifndef LBM_S3_F32_TW
 #define LBM_S3_F32_TW 32
-#define LBM_S3_F32_TH 9
+#define LBM_S3_F32_TH (LBM_PUSH_F32_K3 ? 8 : 9)
 #endif
 #ifndef LBM_S3_F32Q5_TW
 #define LBM_S3_F32Q5_TW 32
 #define LBM_S3_F32Q5_TH 10
 #endif
 template <>
-struct Step3Tile<ST_F32> {  // 112 B per slot (default 36 x 13 slots, 52 KiB: 3 per CU)
+struct Step3Tile<ST_F32> {  // 112 B per slot (default 32 x 8 with push placement: 34 x 10 slots, 37 KiB: 4 per CU)
     static constexpr int TW = LBM_S3_F32_TW, TH = LBM_S3_F32_TH, NT = round64((TW + 4) * (TH + 4));
 };
 template <>

@@ -1124,12 +1124,37 @@ struct LdsCodec<Split16> {
     }
 };
 
+// LDS placement of the intermediate populations.  Pull placement: a node
+// writes its post-collision populations to its own slot and the next update
+// reads each pull from the neighbour's slot, so the planes cover the first
+// update's whole region.  Push placement: a node writes population i to the
+// slot of the node that pulls it (x + e_i) and the next update reads all of
+// its pulls from its own slot, so the planes need only cover the nodes that
+// later updates read, the tile grown by K - 2 nodes; writes that fall
+// outside are dropped.  Push is chosen where the smaller planes let one more
+// workgroup share a CU.
+#ifndef LBM_PUSH_F32_K3
+#define LBM_PUSH_F32_K3 1
+#endif
+template <class Lay, int K>
+struct PushLds {
+    static constexpr bool value = false;
+};
+template <>
+struct PushLds<Plain<E32, false, 9>, 3> {
+    static constexpr bool value = LBM_PUSH_F32_K3;
+};
+
 template <class Lay, int TW, int TH, int K>
 struct StepKShape {
     static constexpr int QT = Lay::QT;
     static constexpr int RING = K - 1;          // ring of the first update
-    static constexpr int LW = TW + 2 * RING;    // fixed LDS row pitch
-    static constexpr int NSLOT = LW * (TH + 2 * RING);  // LDS plane stride
+    static constexpr int LW = TW + 2 * RING;    // thread map pitch of the first update
+    static constexpr int NFIRST = LW * (TH + 2 * RING);  // threads of the first update
+    static constexpr bool PUSH = PushLds<Lay, K>::value;
+    static constexpr int WR = PUSH ? K - 2 : RING;       // ring of the LDS window
+    static constexpr int WW = TW + 2 * WR, WH = TH + 2 * WR;  // LDS window
+    static constexpr int NSLOT = WW * WH;                // LDS plane stride
     using Codec = LdsCodec<Lay>;
     static constexpr size_t LDS_BYTES = Codec::bytes(NSLOT);
     static_assert(TH + 2 * K <= LBM_MIN_BAND_ROWS, "a tile's rows must span at most two bands");
@@ -1148,7 +1173,30 @@ LBM_HD int tile_first_row(const CavityConst<R> &c, const Tile2 &tl) {
 // LDS slot of the node at unwrapped (x, y) of a tile's K-step sweep.
 template <class Sh>
 LBM_HD int lds_slot(const Tile2 &tl, int x, int y) {
-    return (y - (tl.y0 - Sh::RING)) * Sh::LW + (x - (tl.x0 - Sh::RING));
+    return (y - (tl.y0 - Sh::WR)) * Sh::WW + (x - (tl.x0 - Sh::WR));
+}
+
+// Push placement: population i of the node at unwrapped (x, y) goes to the
+// slot of x + e_i if that lies in the window; Sr_f to the node's own slot.
+template <class Sh, typename R, typename RH>
+LBM_HD void lds_push(const CavityConst<R> &c, const Tile2 &tl, int x, int y, void *lds_q, R *lds_sr, const R qf[9],
+                     const RH qg[9], const R qh[9], RH srf) {
+    using Cd = typename Sh::Codec;
+    const int wx = x - (tl.x0 - Sh::WR), wy = y - (tl.y0 - Sh::WR);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int dx = wx + ex_of(i), dy = wy + ey_of(i);
+        if (dx >= 0 && dx < Sh::WW && dy >= 0 && dy < Sh::WH) {
+            const int sl = dy * Sh::WW + dx;
+            LBM_HOST_CHECK(sl >= 0 && sl < Sh::NSLOT);
+            Cd::put1(lds_q, Sh::NSLOT, 0, i, sl, qf[i], c);
+            if (i < Sh::QT) {
+                Cd::put1(lds_q, Sh::NSLOT, 1, i, sl, qg[i], c);
+                Cd::put1(lds_q, Sh::NSLOT, 2, i, sl, qh[i], c);
+            }
+        }
+    }
+    if (wx >= 0 && wx < Sh::WW && wy >= 0 && wy < Sh::WH) lds_sr[wy * Sh::WW + wx] = (R)srf;
 }
 
 // First update: slot s of R_(K-1) (row-major with the fixed pitch LW, so the
@@ -1159,7 +1207,7 @@ LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *sr
                         const R *__restrict__ sr_src, double *__restrict__ acc, void *lds_q, R *lds_sr, int s) {
     using Sh = StepKShape<Lay, TW, TH, K>;
     constexpr int LW = Sh::LW, RG = Sh::RING;
-    LBM_HOST_CHECK(s >= 0 && s < LW * (tl.h + 2 * RG) && s < Sh::NSLOT);
+    LBM_HOST_CHECK(s >= 0 && s < LW * (tl.h + 2 * RG) && s < Sh::NFIRST);
     const int lx = s % LW, ly = s / LW;
     if (lx >= tl.w + 2 * RG) return;
     const int x = tl.x0 - RG + lx, y = tl.y0 - RG + ly;  // unwrapped
@@ -1181,10 +1229,14 @@ LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *sr
     Macro<R> m;
     const R sr_prev = sr_src[flat_index(c, xx, y)];
     const RH srf = update_node<Sh::QT, R, RH, true>(c, g, xx, y, qf, qg, qh, sr_prev, owned, acc, th, m);
-    const ThermalConst<RH> &t = thermal<RH>(c);
-    Sh::Codec::put_node(lds_q, Sh::NSLOT, s, c, qf, qg, qh, m.drho, t.c_fref * (th.Tf - t.T_ref),
-                        c.c_mref * m.dTm);
-    lds_sr[s] = (R)srf;
+    if constexpr (Sh::PUSH) {
+        lds_push<Sh, R, RH>(c, tl, x, y, lds_q, lds_sr, qf, qg, qh, srf);
+    } else {
+        const ThermalConst<RH> &t = thermal<RH>(c);
+        Sh::Codec::put_node(lds_q, Sh::NSLOT, s, c, qf, qg, qh, m.drho, t.c_fref * (th.Tf - t.T_ref),
+                            c.c_mref * m.dTm);
+        lds_sr[s] = (R)srf;
+    }
 }
 
 // A node's pulls from LDS: the slots of the neighbours of the node (or of
@@ -1195,6 +1247,26 @@ LBM_HD void lds_gather(const CavityConst<R> &c, const Tile2 &tl, const NodeGeom 
                        const void *lds_q, R qf[9], RH qg[9], R qh[9]) {
     using Cd = typename Sh::Codec;
     const int px = x + (g.sx - xx);  // partner column, unwrapped
+    if constexpr (Sh::PUSH) {
+        // every pull of the node (or of its partner) sits in its own slot
+        const int sl = lds_slot<Sh>(tl, px, g.sy);
+        LBM_HOST_CHECK(px - (tl.x0 - Sh::WR) >= 0 && px - (tl.x0 - Sh::WR) < Sh::WW);
+        LBM_HOST_CHECK(g.sy - (tl.y0 - Sh::WR) >= 0 && g.sy - (tl.y0 - Sh::WR) < Sh::WH);
+        LBM_HOST_CHECK(sl >= 0 && sl < Sh::NSLOT);
+        (void)h_region;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            qf[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 0, i, sl, c);
+            if (i < Sh::QT) {
+                qg[i] = Cd::template get<RH>(lds_q, Sh::NSLOT, 1, i, sl, c);
+                qh[i] = Cd::template get<R>(lds_q, Sh::NSLOT, 2, i, sl, c);
+            } else {
+                qg[i] = RH(0);
+                qh[i] = R(0);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int sl = lds_slot<Sh>(tl, px - ex_of(i), g.sy - ey_of(i));
@@ -1248,17 +1320,21 @@ LBM_HD bool stepk_mid_load(const CavityConst<R> &c, const Tile2 &tl, int j, cons
     return true;
 }
 template <class Lay, typename R, typename RH, int TW, int TH, int K>
-LBM_HD void stepk_mid_store(const CavityConst<R> &c, double *__restrict__ acc, void *lds_q, R *lds_sr,
-                            MidNode<R, RH> &n) {
+LBM_HD void stepk_mid_store(const CavityConst<R> &c, const Tile2 &tl, double *__restrict__ acc, void *lds_q,
+                            R *lds_sr, MidNode<R, RH> &n) {
     using Sh = StepKShape<Lay, TW, TH, K>;
     Thermo<RH> th;
     Macro<R> m;
     const RH srf = update_node<Sh::QT, R, RH, true>(c, n.g, n.xx, n.y, n.qf, n.qg, n.qh, n.sr_prev, n.owned, acc,
                                                    th, m);
-    const ThermalConst<RH> &t = thermal<RH>(c);
-    Sh::Codec::put_node(lds_q, Sh::NSLOT, n.slot, c, n.qf, n.qg, n.qh, m.drho, t.c_fref * (th.Tf - t.T_ref),
-                        c.c_mref * m.dTm);
-    lds_sr[n.slot] = (R)srf;
+    if constexpr (Sh::PUSH) {
+        lds_push<Sh, R, RH>(c, tl, n.x, n.y, lds_q, lds_sr, n.qf, n.qg, n.qh, srf);
+    } else {
+        const ThermalConst<RH> &t = thermal<RH>(c);
+        Sh::Codec::put_node(lds_q, Sh::NSLOT, n.slot, c, n.qf, n.qg, n.qh, m.drho, t.c_fref * (th.Tf - t.T_ref),
+                            c.c_mref * m.dTm);
+        lds_sr[n.slot] = (R)srf;
+    }
 }
 
 // Last update: node n of the tile (row-major with pitch TW; columns beyond
