@@ -228,7 +228,7 @@ struct Step2Tile<ST_F16S> {  // 6 x 4 + 24 x 2 + 4 = 76 B per slot, 34 x 15 slot
 #define LBM_S2_F64_TH 5
 #endif
 template <>
-struct Step2Tile<ST_F64> {  // 27 x 8 + 8 = 224 B per slot (default 34 x 7 slots, 53 KiB)
+struct Step2Tile<ST_F64> {  // 27 x 8 + 8 = 224 B per slot (default 32 x 5 with push placement: 160 slots, 37 KiB)
     static constexpr int TW = LBM_S2_F64_TW, TH = LBM_S2_F64_TH, NT = round64((TW + 2) * (TH + 2));
 };
 #ifndef LBM_S2_F64Q5_TW

@@ -1144,6 +1144,13 @@ template <>
 struct PushLds<Plain<E32, false, 9>, 3> {
     static constexpr bool value = LBM_PUSH_F32_K3;
 };
+#ifndef LBM_PUSH_F64_K2
+#define LBM_PUSH_F64_K2 1
+#endif
+template <>
+struct PushLds<Plain<E64, false, 9>, 2> {
+    static constexpr bool value = LBM_PUSH_F64_K2;
+};
 
 template <class Lay, int TW, int TH, int K>
 struct StepKShape {
