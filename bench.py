@@ -20,6 +20,7 @@ FP32 160 B, FP32 with the FP64 rest enthalpy population 168 B.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -162,11 +163,29 @@ def cpu_baseline(params, seed, budget_s=15.0):
     t0 = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     nodes = win[2] * win[3]
+    # the checker's OpenMP runtime: its thread count, then one thread
+    gomp = ctypes.CDLL("libgomp.so.1")
+    cores = int(gomp.omp_get_max_threads())
+    gomp.omp_set_num_threads(1)
+    n1 = max(2, int(budget_s / 3 / max(per * cores, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(n1)
+    dt1 = time.perf_counter() - t0
+    gomp.omp_set_num_threads(cores)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{win[2]}x{win[3]} window at the hot-wall corner of the same cavity, "
-                      f"{n} steps, {dt:.1f} s, FP64"}
+                      f"{n} steps, {dt:.1f} s, FP64",
+            "single_thread_value": nodes * n1 / dt1 / 1e6, "single_thread_sample": f"{n1} steps, {dt1:.1f} s",
+            "host_cpu": model}
 
 
 def accuracy(name: str) -> dict:
