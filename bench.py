@@ -26,6 +26,7 @@ import json
 import os
 import re
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -143,7 +144,7 @@ def time_steps(lbm, torch, s, stream, steps, warmup, looped=False):
 
 
 def cpu_baseline(params, seed, budget_s=15.0):
-    """The FP64 checker on a 384 x 384 window of the same cavity (hot-wall
+    """The FP64 oracle on a 384 x 384 window of the same cavity (hot-wall
     corner), OpenMP over rows on the host cores."""
     import oracle
     import lbm_workloads as W
@@ -164,7 +165,7 @@ def cpu_baseline(params, seed, budget_s=15.0):
     o.step(n)
     dt = time.perf_counter() - t0
     nodes = win[2] * win[3]
-    # the checker's OpenMP runtime: its thread count, then one thread
+    # the oracle's OpenMP runtime: its thread count, then one thread
     gomp = ctypes.CDLL("libgomp.so.1")
     cores = int(gomp.omp_get_max_threads())
     gomp.omp_set_num_threads(1)
@@ -191,8 +192,8 @@ def cpu_baseline(params, seed, budget_s=15.0):
 def accuracy(name: str) -> dict:
     """Full-length runs of the 1024^2 (FP32 forms, 200 000 steps) or the
     4096^2 (16-bit forms, 100 000 steps) cavity next to the FP64 path on the
-    same GPU, which the parity tests tie to the checker at 1e-10; the
-    checker itself would need hours at these sizes.  Errors in liquid
+    same GPU, which the parity tests tie to the oracle at 1e-10; the
+    oracle itself would need hours at these sizes.  Errors in liquid
     fraction, mid-row melt front, hot-wall Nusselt number and the fields."""
     from paper_1701_00702_amd import lbm
     import lbm_workloads as W
@@ -239,7 +240,7 @@ def accuracy(name: str) -> dict:
         out[prec] = row
         del f
     return {"accuracy": name, "nx": p["nx"], "ny": p["ny"], "steps": steps, "seed": seed,
-            "reference": "f64 on the GPU (the FP64 path matches the checker to 1e-10)", "forms": out}
+            "reference": "f64 on the GPU (the FP64 path matches the oracle to 1e-10)", "forms": out}
 
 
 def main():
@@ -267,7 +268,7 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (counter calibration and its bandwidth)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                           "(multi-GPU sharding is a design note only)"}))
         sys.exit(2)
 
@@ -311,7 +312,7 @@ def main():
         T_pcm, T_mf = W.initial_temperatures(p, seed + c if len(params) > 1 else seed)
         s.set_initial(c, T_pcm, T_mf)
     if args.autotune:
-        launch = lbm.lbm_autotune(s.h, 5, os.path.join(ROOT, "gpurun_out", "autotune_cache.txt"))
+        launch = lbm.lbm_autotune(s.h, 5, os.path.join(tempfile.gettempdir(), "lbmpcm_autotune_cache.txt"))
     else:
         lbm.lbm_set_launch(s.h, args.block, args.npt, args.xcd, args.persistent,
                            steps_per_launch=args.steps_per_launch or None)

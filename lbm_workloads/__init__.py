@@ -1,10 +1,10 @@
-"""Seeded synthetic workloads shared by the tests, the benchmark and the checker.
+"""Seeded synthetic workloads shared by the tests, the benchmark and the oracle.
 
 This module only describes problems: grid sizes, dimensionless groups,
 boundary temperatures and seeded random perturbations of the initial PCM
 temperature.  It holds none of the method's arithmetic (no parameter
 mapping, no equilibria, no update); both the GPU library and the CPU
-checker consume the plain dictionaries returned here and do their own
+oracle consume the plain dictionaries returned here and do their own
 mapping.
 
 Cases follow the square-cavity melting problem of the paper (Sec. IV B:

@@ -3,7 +3,7 @@
  * lattice Boltzmann method for solid-liquid phase change in metal foams under
  * local thermal non-equilibrium (Liu, He & Li, arXiv:1701.00702).
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the slow, literal checker that the
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, literal oracle that the
  * GPU library is compared against.  Only the tests, the smoke check and the
  * CPU-baseline leg of the benchmark load it.  It shares no code, header or
  * table with the GPU library.
@@ -28,8 +28,7 @@
  *      analogues), using the partner node's new populations.
  * Wall fluxes for the energy/mass balance are tallied between 4 and 5.
  *
- * Readings where the paper is silent (each is listed with its reason in the
- * design notes): walls sit on the first/last node rows and columns and
+ * Readings where the paper is silent: walls sit on the first/last node rows and columns and
  * L = nx - 1; the extrapolation partner is the inward normal neighbour (the
  * diagonal one at corners) for all nine directions; corners take the
  * isothermal value of their vertical wall; adiabatic walls copy the partner's

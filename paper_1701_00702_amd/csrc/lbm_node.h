@@ -55,7 +55,7 @@ __host__ __device__ constexpr R w_of(int i) {
 // Reciprocal and square root of the velocity solve and the force: correctly
 // rounded in FP64; in FP32 the hardware instructions (about 1 ulp), a tenth
 // of the instructions of the correctly rounded sequences.  The FP32 forms
-// are held to 1e-4 of the FP64 checker, far above that rounding.
+// are held to 1e-4 of the FP64 oracle, far above that rounding.
 template <typename R>
 LBM_HD R rcp_of(R x) {
     return R(1) / x;

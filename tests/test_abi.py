@@ -1,7 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports
 every entry point the header declares, and its host-only parameter mapping
 and validation agree with the paper's printed numbers and with the CPU
-checker's mapping."""
+oracle's mapping."""
 import os
 import re
 
@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
         assert callable(getattr(lbm, n)), f"binding wrapper {n} missing"
 
 
-def test_host_mapping_matches_paper_and_checker():
+def test_host_mapping_matches_paper_and_oracle():
     from paper_1701_00702_amd import lbm
     p, _, _, _ = W.case_p1()
     l = lbm.lbm_lattice_of(p, "f64")
@@ -40,7 +40,7 @@ def test_host_mapping_matches_paper_and_checker():
         assert l[k] == pytest.approx(lo[k], rel=1e-14, abs=1e-300), k
     for k in ("s", "zeta", "eta"):
         assert l[k] == pytest.approx(lo[k], rel=1e-14), k
-    # every BASELINE-shaped case maps, and the rule for k_f gives the
+    # every named workload maps, and the rule for k_f gives the
     # paper's value (tau_h = 2) at lambda = 1000
     for case in (W.case_c1, W.case_c2, W.case_c3, W.case_c4):
         q = case()[0]
@@ -59,7 +59,7 @@ def test_host_mapping_matches_paper_and_checker():
                                   dict(zeta_e=1.2), dict(thermal_lattice=5, zeta_e=0.6),
                                   dict(wall_type=(1, 2, 1, 0), wall_T=(-1.0, 0.0, 0.5, 0.0)),
                                   dict(L_char=40.0), dict(solid_treatment=1)])
-def test_host_mapping_of_variants_matches_checker(over):
+def test_host_mapping_of_variants_matches_oracle(over):
     from paper_1701_00702_amd import lbm
     p = dict(W.case_c1()[0], **over)
     prec = "f64"
@@ -72,7 +72,7 @@ def test_host_mapping_of_variants_matches_checker(over):
     assert a["solid_treatment"] == b["solid_treatment"]
 
 
-def test_corner_case_maps_like_the_checker():
+def test_corner_case_maps_like_the_oracle():
     from paper_1701_00702_amd import lbm
     p = W.case_corner()[0]
     a, b = lbm.lbm_lattice_of(p, "f64"), lattice_params(p)

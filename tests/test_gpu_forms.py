@@ -2,17 +2,18 @@
 
 * Full-size cavity (8192^2, FP32) in the benchmark's launch shape: after a
   few steps every node depends only on a small neighbourhood of the seeded
-  initial state, so the CPU checker run on small windows (with its own
+  initial state, so the CPU oracle run on small windows (with its own
   light-cone bookkeeping) gives exact expected values for sampled nodes at
   the corners, on the walls and in the interior.
 * Full-length runs of the 64^2 FP64 case and the 256^2 FP32 case.
-* 16-bit offset storage: errors against the FP64 checker are measured and
-  bounded; the bounds are what the storage rounding allows,
-  not parity.
+* 16-bit offset storage: errors against the FP64 oracle are measured and
+  bounded; the bounds are what the storage rounding allows (the fixed
+  offsets round the O(1) enthalpy offsets at 5e-4 / 4e-3 relative per
+  step), not parity.
 * Batched cavities: each cavity inside the packed launch is bit-identical to
   the same cavity run alone, and to the one-launch-per-cavity schedule; the
   whole 256-cavity set in the benchmark's launch, sampled cavities against
-  the checker.
+  the oracle.
 """
 import numpy as np
 import pytest
@@ -54,7 +55,7 @@ def test_fullsize_c3_sampled_windows(lbm):
         o.set_initial(T_pcm[y0:y0 + w, x0:x0 + w], T_mf[y0:y0 + w, x0:x0 + w])
         o.step(steps)
         refs.append(o.fields())
-    # one velocity scale for all windows: the largest checker speed sampled
+    # one velocity scale for all windows: the largest oracle speed sampled
     # (near the hot wall); far from it the flow after 8 steps is ~1e-16
     umax = max(max(np.abs(r["ux"][r["valid"]]).max(), np.abs(r["uy"][r["valid"]]).max())
                for r in refs)
@@ -71,7 +72,7 @@ def test_fullsize_c3_sampled_windows(lbm):
 
 def sampled_windows(lbm, p, seed, precision, steps, w=48):
     """Fields of a full-size cavity in the benchmark's launch next to the
-    checker on windows at the corners, the walls and the interior."""
+    oracle on windows at the corners, the walls and the interior."""
     nx, ny = p["nx"], p["ny"]
     T_pcm, T_mf = W.initial_temperatures(p, seed)
     s = lbm.Solver(p, precision)
@@ -123,7 +124,7 @@ def test_fullsize_c5_bench_launch(lbm):
     # The whole 256-cavity set (24 198 641 nodes) in the benchmark's launch
     # and seeds; 96 steps run as one captured graph of 32 three-step
     # launches.  The smallest and the largest cavity and two others are
-    # checked whole against the checker, and bit for bit against the same
+    # checked whole against the oracle, and bit for bit against the same
     # cavity run alone; every cavity must stay finite.
     ps, _, seed, prec = W.case_c5()
     temps = [W.initial_temperatures(q, seed + c) for c, q in enumerate(ps)]
@@ -237,7 +238,7 @@ def test_batched_cavities_bitwise(lbm):
         db, ds = b.diagnostics(c), single.diagnostics()
         assert db["flux_E"] == ds["flux_E"] and db["E_int"] == ds["E_int"]
         single.close()
-    # and the smallest cavity against the FP64 checker
+    # and the smallest cavity against the FP64 oracle
     q = batch[0]
     o = oracle.Oracle(q)
     o.set_initial(*temps[0])

@@ -1,8 +1,8 @@
-"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU checker.
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
 Field errors are measured as: temperatures over the wall temperature
 difference, liquid fraction and density absolutely, velocity over the
-checker's largest speed.  Bars: 1e-10 for the FP64 form, 1e-4 for the FP32
+oracle's largest speed.  Bars: 1e-10 for the FP64 form, 1e-4 for the FP32
 form (the targets the method is built to), computed on the same seeded
 inputs.
 """

@@ -1,5 +1,5 @@
 """GPU parity of the thermal-model variants and wall conditions (HIP path
-through the C ABI against the FP64 CPU checker, same seeded inputs):
+through the C ABI against the FP64 CPU oracle, same seeded inputs):
 
 * D2Q5 thermal fields (Appendix B) in FP64, FP32 and FP32 with the FP64
   rest enthalpy population; ragged tiles, launch shapes, batches and
@@ -9,11 +9,11 @@ through the C ABI against the FP64 CPU checker, same seeded inputs):
 * the conduction-induced solidification of Sec. IV A at the paper's
   200 x 200 grid and full length (Fo = 0.02), and mixed wall types;
 * the 8192^2 cavity on D2Q5 in the benchmark's launch shape, sampled
-  against checker windows.
+  against oracle windows.
 
 Bars as for the D2Q9 path: 1e-10 in FP64, 1e-4 in FP32 (errors as in
 test_gpu_parity: temperatures over the wall temperature difference,
-velocities over the checker's largest speed, f_l and rho absolute).
+velocities over the oracle's largest speed, f_l and rho absolute).
 """
 import os
 import tempfile
