@@ -3,7 +3,8 @@ the state crosses HBM once per K steps through LDS tiles, and the result
 must be the same map as K single steps, bit for bit (populations, sources,
 FP64 wall tallies and diagnostics), on every geometry the single-step path
 handles: walls and corners, periodic channels, ragged and batched cavities,
-mixed wall types, the bounce-back alternative, both thermal lattices, FP32,
+mixed wall types, the bounce-back alternative, the smallest cavities, both
+thermal lattices, FP32,
 FP64, FP32 with the FP64 rest enthalpy population and the 16-bit forms, step
 counts that leave a remainder and graph replays.
 """
@@ -39,6 +40,9 @@ CASES = {
     "batch": lambda: [W.scaled_cavity(_c1(), 33, 70), W.scaled_cavity(_c1(), 70, 34),
                       W.scaled_cavity(_c1(), 16, 16)],
     "wide": lambda: [W.scaled_cavity(W.case_c2()[0], 301, 97)],
+    # the smallest cavities accepted (4 nodes a side) and thin ones, where
+    # every node is a wall node or next to one
+    "tiny": lambda: [W.scaled_cavity(_c1(), nx, ny) for (nx, ny) in ((4, 4), (4, 7), (5, 4), (33, 4), (4, 35))],
 }
 
 
@@ -86,7 +90,7 @@ def test_three_steps_per_launch_are_bitwise_three_single_steps(lbm, case, qt, pr
             assert da[k] == db[k] == dm[k], k
 
 
-@pytest.mark.parametrize("case", ["c1", "ragged", "periodic", "corner", "batch"])
+@pytest.mark.parametrize("case", ["c1", "ragged", "periodic", "corner", "batch", "tiny"])
 @pytest.mark.parametrize("prec", ["f16split", "f16", "bf16"])
 @pytest.mark.parametrize("spl", [2, 3])
 def test_16bit_multi_step_is_bitwise_single_steps(lbm, case, prec, spl):
@@ -100,3 +104,22 @@ def test_16bit_multi_step_is_bitwise_single_steps(lbm, case, prec, spl):
         assert np.array_equal(a, b)
         for k in ("flux_E", "flux_M", "E_int", "M_int", "liquid_fraction"):
             assert (da[k] == db[k]) or (np.isnan(da[k]) and np.isnan(db[k])), k
+
+
+def test_smallest_cavities_against_oracle(lbm):
+    # each tiny cavity alone, in the default launch, against the FP64 oracle
+    import oracle
+    from test_gpu_parity import field_errors
+    for (nx, ny) in ((4, 4), (4, 7), (5, 4), (33, 4), (4, 35)):
+        p = W.scaled_cavity(_c1(), nx, ny)
+        T = W.initial_temperatures(p, 3)
+        s = lbm.Solver(p, "f64")
+        s.set_initial(0, *T)
+        s.step(61)
+        g = s.fields()
+        s.close()
+        o = oracle.Oracle(p)
+        o.set_initial(*T)
+        o.step(61)
+        e = field_errors(g, o.fields(), p)
+        assert max(e.values()) < 1e-10, (nx, ny, e)
