@@ -4,9 +4,8 @@ must be the same map as K single steps, bit for bit (populations, sources,
 FP64 wall tallies and diagnostics), on every geometry the single-step path
 handles: walls and corners, periodic channels, ragged and batched cavities,
 mixed wall types, the bounce-back alternative, the smallest cavities, both
-thermal lattices, FP32,
-FP64, FP32 with the FP64 rest enthalpy population and the 16-bit forms, step
-counts that leave a remainder and graph replays.
+thermal lattices, FP32, FP64, FP32 with the FP64 rest enthalpy population and
+the 16-bit forms, step counts that leave a remainder and graph replays.
 """
 import numpy as np
 import pytest
