@@ -105,6 +105,15 @@ def test_host_validation_rejects_bad_sets():
     # a batch shares one thermal lattice
     with pytest.raises(lbm.LbmError):
         lbm.lbm_workspace_bytes([base, q5], "f32")
+    # an empty batch, and calls on a NULL handle (any step count)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes([], "f32")
+    assert e.value.status == lbm.LBM_EINVAL
+    for call in (lambda: lbm.lbm_step(None, 1), lambda: lbm.lbm_step(None, -1), lambda: lbm.lbm_step(None, 0),
+                 lambda: lbm.lbm_synchronize(None)):
+        with pytest.raises(lbm.LbmError) as e:
+            call()
+        assert e.value.status == lbm.LBM_EINVAL
 
 
 def test_workspace_plan_sizes():

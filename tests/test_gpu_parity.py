@@ -251,3 +251,23 @@ def test_torch_workspace_and_stream(lbm):
     e = field_errors(g, o.fields(), p)
     assert max(e.values()) < 1e-10, e
     del ws
+
+
+def test_zero_and_negative_step_counts(lbm):
+    # step(0) leaves the state and the step counter alone; a negative count
+    # is an error that changes nothing
+    p = W.scaled_cavity(W.case_c1()[0], 16, 12)
+    s = lbm.Solver(p, "f32")
+    s.set_initial(0, *W.initial_temperatures(p, 0))
+    s.step(5)
+    a = s.state().copy()
+    n = s.diagnostics()["step"]
+    s.step(0)
+    assert np.array_equal(s.state().view(np.uint32), a.view(np.uint32))
+    assert s.diagnostics()["step"] == n
+    with pytest.raises(lbm.LbmError):
+        s.step(-1)
+    assert np.array_equal(s.state().view(np.uint32), a.view(np.uint32))
+    s.step(1)
+    assert s.diagnostics()["step"] == n + 1
+    s.close()
