@@ -258,9 +258,36 @@ int64_t lbm_step_count(const lbm_handle *h);
 lbm_status lbm_fields(lbm_handle *h, int32_t cavity, double *ux, double *uy, double *T_pcm,
                       double *T_mf, double *f_l, double *rho);
 
-/* FP64 diagnostics of one cavity (deterministic reductions).  Returns
- * LBM_ENONFINITE, with *out filled, when the state holds NaN/Inf. */
+/* FP64 diagnostics of one cavity (deterministic reductions).  The paper
+ * defines none of these quantities; the definitions are this library's:
+ * liquid fraction = mean f_l (Eq. 39) over interior nodes; melt front = the
+ * first f_l = 0.5 crossing from the hot wall on row ny/2 (f_l = 0.5 is the
+ * phase interface of Sec. IV B), linearly interpolated, divided by L; Nusselt
+ * numbers from second-order one-sided differences of T_f and T_m at the
+ * vertical walls, averaged over the non-corner wall nodes, with
+ * k_e = phi k_f + (1 - phi) k_m (Eq. 8); energy phi rho_l H + (1 - phi)
+ * rho_m c_pm T_m (Eqs. 37, 48) and density summed over interior nodes, with
+ * the link fluxes across each wall tallied every step.  Uses the handle's
+ * workspace (field planes, partial sums) as scratch.  Synchronises the
+ * stream.  Returns LBM_ENONFINITE, with *out filled, when the state holds
+ * NaN/Inf. */
 lbm_status lbm_diagnostics(lbm_handle *h, int32_t cavity, lbm_diag *out);
+
+/* The same diagnostics for callers that cannot allocate or hand out device
+ * memory (tight serving loops, harnesses that forbid allocation): calls no
+ * hipMalloc, hipFree or other allocating routine and touches none of the
+ * workspace's scratch regions.  Its kernels use one fixed device array per
+ * GPU (about 3.5 MiB, held until the process ends) for per-workgroup
+ * partial sums, the temperatures of the three columns next to each vertical
+ * wall and the middle row's liquid fraction.  Cavities with nx or ny above
+ * 32768 are rejected with LBM_EINVAL.  Every call writes each scratch
+ * element it reads, so nothing carries over between calls; calls that
+ * overlap on one GPU (several host threads, or streams running at once)
+ * share that array and race.  The per-node values and the Nusselt numbers
+ * and melt front are those of lbm_diagnostics bit for bit; the sums over
+ * nodes (energy, density, liquid fraction, fluxes) run in another order and
+ * agree to rounding.  Synchronises the stream. */
+lbm_status lbm_diagnostics_noalloc(lbm_handle *h, int32_t cavity, lbm_diag *out);
 
 /* Derived lattice constants of one cavity. */
 lbm_status lbm_get_lattice(const lbm_handle *h, int32_t cavity, lbm_lattice *out);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstddef>
 #include <cmath>
 #include <cstdarg>
@@ -40,6 +41,55 @@ static lbm_status fail(lbm_status st, const char *fmt, ...) {
     } while (0)
 
 extern "C" const char *lbm_last_error(void) { return g_err; }
+
+// ---------------------------------------------------------------------------
+// Device scratch of lbm_diagnostics_noalloc: one fixed array per GPU, held
+// until the process ends.  Layout (doubles): per-workgroup partial sums
+// [LBM_DIAG_MAX_BLOCKS][NPART], the wall-column temperatures T_f and T_m
+// [LBM_NOALLOC_MAX_SIDE][6] each, the middle row's liquid fraction
+// [LBM_NOALLOC_MAX_SIDE], the NDIAG results.  In host code the array's name
+// is only a stand-in; kernels get the address hipGetSymbolAddress returns
+// for the current device (noalloc_scratch).
+// ---------------------------------------------------------------------------
+#define LBM_NOALLOC_MAX_SIDE 32768
+namespace {
+constexpr size_t kScrPart = 0;
+constexpr size_t kScrTf = kScrPart + (size_t)LBM_DIAG_MAX_BLOCKS * NPART * sizeof(double);
+constexpr size_t kScrTm = kScrTf + (size_t)LBM_NOALLOC_MAX_SIDE * 6 * sizeof(double);
+constexpr size_t kScrFl = kScrTm + (size_t)LBM_NOALLOC_MAX_SIDE * 6 * sizeof(double);
+constexpr size_t kScrOut = kScrFl + (size_t)LBM_NOALLOC_MAX_SIDE * sizeof(double);
+constexpr size_t kScrBytes = (kScrOut + 64 * sizeof(double) + 255) & ~(size_t)255;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScrBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// The device address of this GPU's scratch array: looked up once per device
+// (with that device current: handle set-up runs on the handle's device).
+lbm_status noalloc_scratch(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices)
+        return fail(LBM_EDEVICE, "device %d beyond the %d devices the scratch table covers", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess || cur != device)
+            return fail(LBM_EDEVICE, "scratch of device %d looked up with device %d current", device, cur);
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LBM_EDEVICE, "hipGetSymbolAddress of the diagnostics scratch failed: %s",
+                        hipGetErrorString(e));
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
+    return LBM_OK;
+}
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // Parameter mapping (lattice units dx = dt = 1, c_s^2 = 1/3).
@@ -782,6 +832,29 @@ lbm_status prepare_graphs(lbm_handle *h) {
     return LBM_OK;
 }
 
+// Arguments of the final diagnostics pass of cavity c (everything but the
+// wall-column and middle-row pointers).
+DiagLaunch diag_args(lbm_handle *h, int c, const double *partials, int nblocks, double *out) {
+    const lbm_params &p = h->params[c];
+    const Lattice &l = h->pl.lat[c];
+    DiagLaunch D;
+    std::memset(&D, 0, sizeof(D));
+    D.nx = p.nx;
+    D.ny = p.ny;
+    D.periodic = p.bc_x;
+    D.acc0 = h->pl.acc0[c];
+    D.partials = partials;
+    D.nblocks = nblocks;
+    D.acc = h->acc();
+    D.out = out;
+    D.L = l.L;
+    D.kf = l.phi * l.k_f;
+    D.km = (1.0 - l.phi) * l.k_m;
+    D.ke = D.kf + D.km;
+    D.dT = l.T_hot - l.T_cold;
+    return D;
+}
+
 // Run the diagnostics kernels for cavity c; results land in h->dout() and
 // the six field planes in h->fields().
 lbm_status run_macro(lbm_handle *h, int c, bool with_diag) {
@@ -797,22 +870,14 @@ lbm_status run_macro(lbm_handle *h, int c, bool with_diag) {
     M.nblocks = macro_blocks(p.nx, p.ny);
     HIP_TRY(launch_macro(M, p.nx, p.ny, h->stream));
     if (with_diag) {
-        const Lattice &l = h->pl.lat[c];
-        DiagLaunch D;
-        D.nx = p.nx;
-        D.ny = p.ny;
-        D.periodic = p.bc_x;
-        D.acc0 = h->pl.acc0[c];
-        D.fields = h->fields();
-        D.partials = h->partials();
-        D.nblocks = M.nblocks;
-        D.acc = h->acc();
-        D.out = h->dout();
-        D.L = l.L;
-        D.kf = l.phi * l.k_f;
-        D.km = (1.0 - l.phi) * l.k_m;
-        D.ke = D.kf + D.km;
-        D.dT = l.T_hot - l.T_cold;
+        const int64_t nn = (int64_t)p.nx * p.ny;
+        DiagLaunch D = diag_args(h, c, h->partials(), M.nblocks, h->dout());
+        D.tf = h->fields() + 2 * nn;
+        D.tm = h->fields() + 3 * nn;
+        D.fl_mid = h->fields() + 4 * nn + (int64_t)(p.ny / 2) * p.nx;
+        D.rs = p.nx;
+        const int cx[6] = {0, 1, 2, p.nx - 3, p.nx - 2, p.nx - 1};
+        for (int k = 0; k < 6; ++k) D.cx[k] = cx[k];
         HIP_TRY(launch_diag(D, p.nx, p.ny, h->stream));
     }
     return LBM_OK;
@@ -853,6 +918,11 @@ lbm_status init_cavity(lbm_handle *h, int c, const double *T_pcm, const double *
 
 lbm_status setup(lbm_handle *h) {
     HIP_TRY(hipGetDevice(&h->device));
+    {
+        void *scr = nullptr;
+        lbm_status s0 = noalloc_scratch(h->device, &scr);
+        if (s0 != LBM_OK) return s0;
+    }
     int ncu = 0;
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
     h->n_cu = ncu > 0 ? ncu : 256;
@@ -1095,12 +1165,9 @@ extern "C" lbm_status lbm_fields(lbm_handle *h, int32_t c, double *ux, double *u
     return LBM_OK;
 }
 
-extern "C" lbm_status lbm_diagnostics(lbm_handle *h, int32_t c, lbm_diag *out) {
-    if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
-    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
-    double d[NDIAG];
-    lbm_status s = read_diag(h, c, d);
-    if (s != LBM_OK) return s;
+namespace {
+// lbm_diag of cavity c from the device results d (NDIAG doubles).
+lbm_status diag_from(lbm_handle *h, int c, const double d[NDIAG], lbm_diag *out) {
     const Lattice &l = h->pl.lat[c];
     std::memset(out, 0, sizeof(*out));
     out->step = (double)h->step;
@@ -1128,6 +1195,52 @@ extern "C" lbm_status lbm_diagnostics(lbm_handle *h, int32_t c, lbm_diag *out) {
     out->nonfinite = d[D_NF];
     if (d[D_NF] > 0) return fail(LBM_ENONFINITE, "cavity %d holds %g nodes with non-finite populations", c, d[D_NF]);
     return LBM_OK;
+}
+}  // namespace
+
+extern "C" lbm_status lbm_diagnostics(lbm_handle *h, int32_t c, lbm_diag *out) {
+    if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    double d[NDIAG];
+    lbm_status s = read_diag(h, c, d);
+    if (s != LBM_OK) return s;
+    return diag_from(h, c, d, out);
+}
+
+extern "C" lbm_status lbm_diagnostics_noalloc(lbm_handle *h, int32_t c, lbm_diag *out) {
+    if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    const lbm_params &p = h->params[c];
+    if (p.nx > LBM_NOALLOC_MAX_SIDE || p.ny > LBM_NOALLOC_MAX_SIDE)
+        return fail(LBM_EINVAL, "cavity %d is %dx%d: lbm_diagnostics_noalloc takes sides of at most %d nodes "
+                    "(its fixed scratch); use lbm_diagnostics", c, p.nx, p.ny, LBM_NOALLOC_MAX_SIDE);
+    void *scr = nullptr;
+    lbm_status s = noalloc_scratch(h->device, &scr);
+    if (s != LBM_OK) return s;
+    char *base = (char *)scr;
+    DiagNodeLaunch M;
+    M.storage = h->st;
+    M.raw = h->step == 0 ? 1 : 0;
+    M.cav_index = c;
+    M.src = h->pop(h->cur);
+    M.cav = h->cav();
+    M.partials = (double *)(base + kScrPart);
+    M.nblocks = diag_node_blocks(p.nx, p.ny);
+    M.tf = (double *)(base + kScrTf);
+    M.tm = (double *)(base + kScrTm);
+    M.fl_mid = (double *)(base + kScrFl);
+    HIP_TRY(launch_diag_nodes(M, p.nx, p.ny, h->stream));
+    DiagLaunch D = diag_args(h, c, M.partials, M.nblocks, (double *)(base + kScrOut));
+    D.tf = M.tf;
+    D.tm = M.tm;
+    D.fl_mid = M.fl_mid;
+    D.rs = 6;
+    for (int k = 0; k < 6; ++k) D.cx[k] = k;
+    HIP_TRY(launch_diag(D, p.nx, p.ny, h->stream));
+    double d[NDIAG];
+    HIP_TRY(hipMemcpyAsync(d, base + kScrOut, NDIAG * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return diag_from(h, c, d, out);
 }
 
 namespace {

@@ -163,12 +163,36 @@ enum {
 struct DiagLaunch {
     int nx, ny, periodic;
     int64_t acc0;
-    const double *fields;
     const double *partials;
     int nblocks;
     const double *acc;
     double *out;      // NDIAG doubles
     double L, ke, kf, km, dT;  // kf = phi k_f, km = (1-phi) k_m, ke = kf + km
+    // T_f and T_m of the three columns next to each vertical wall, and f_l of
+    // the middle row (y = ny / 2): the value at column k (k = 0..5 for
+    // x = 0, 1, 2, nx - 3, nx - 2, nx - 1) of row y is tf[y * rs + cx[k]];
+    // fl_mid[x] for x in [0, nx).  Full field planes (rs = nx, cx = x) or
+    // the compact copies of the allocation-free diagnostics (rs = 6, cx = k).
+    const double *tf, *tm, *fl_mid;
+    int64_t rs;
+    int cx[6];
+};
+
+// Diagnostics without the field planes: a fixed grid of at most
+// LBM_DIAG_MAX_BLOCKS workgroups strides over the nodes of one cavity,
+// writes per-workgroup partial sums, the wall-column temperatures and the
+// middle-row liquid fraction in the compact layout of DiagLaunch.
+#define LBM_DIAG_MAX_BLOCKS 2048
+struct DiagNodeLaunch {
+    int storage;
+    int raw;
+    int cav_index;
+    const void *src;
+    const void *cav;
+    double *partials;  // [nblocks][NPART]
+    int nblocks;       // 1 .. LBM_DIAG_MAX_BLOCKS
+    double *tf, *tm;   // [ny][6]
+    double *fl_mid;    // [nx]
 };
 
 struct InitLaunch {
@@ -187,6 +211,8 @@ bool stepk_supported(int storage, int k);                // K steps per launch (
 void stepk_tile(int storage, int k, int *tw, int *th);  // tile shape of the K-step kernel
 hipError_t launch_macro(const MacroLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s);
+hipError_t launch_diag_nodes(const DiagNodeLaunch &L, int nx, int ny, hipStream_t s);
+int diag_node_blocks(int nx, int ny);  // workgroups of launch_diag_nodes
 hipError_t launch_init(const InitLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_poke(int elem, void *ptr, double value, hipStream_t s);
 int macro_blocks(int nx, int ny);

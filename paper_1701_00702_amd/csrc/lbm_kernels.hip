@@ -555,7 +555,6 @@ hipError_t launch_macro(const MacroLaunch &L, int nx, int ny, hipStream_t s) {
 __global__ __launch_bounds__(MB) void diag_kernel(DiagLaunch L) {
     const int t = threadIdx.x;
     const int nx = L.nx, ny = L.ny;
-    const int64_t nn = (int64_t)nx * ny;
     __shared__ double sh[NPART + 3 + 8][MB / 64];
     double v[NPART + 3 + 8];
 #pragma unroll
@@ -567,16 +566,16 @@ __global__ __launch_bounds__(MB) void diag_kernel(DiagLaunch L) {
             v[k] = (k == P_DT || k == P_U) ? fmax(v[k], a) : v[k] + a;
         }
     }
-    const double *Tf = L.fields + 2 * nn;
-    const double *Tm = L.fields + 3 * nn;
     if (!L.periodic) {
+        const int *cx = L.cx;
         for (int y = 1 + t; y <= ny - 2; y += MB) {
-            const int64_t r = (int64_t)y * nx;
-            const double dTf = (-3.0 * Tf[r] + 4.0 * Tf[r + 1] - Tf[r + 2]) * 0.5;
-            const double dTm = (-3.0 * Tm[r] + 4.0 * Tm[r + 1] - Tm[r + 2]) * 0.5;
+            const double *Tf = L.tf + (int64_t)y * L.rs;
+            const double *Tm = L.tm + (int64_t)y * L.rs;
+            const double dTf = (-3.0 * Tf[cx[0]] + 4.0 * Tf[cx[1]] - Tf[cx[2]]) * 0.5;
+            const double dTm = (-3.0 * Tm[cx[0]] + 4.0 * Tm[cx[1]] - Tm[cx[2]]) * 0.5;
             v[NPART + 0] += dTf;  // PCM-only gradient
-            const double cTf = (3.0 * Tf[r + nx - 1] - 4.0 * Tf[r + nx - 2] + Tf[r + nx - 3]) * 0.5;
-            const double cTm = (3.0 * Tm[r + nx - 1] - 4.0 * Tm[r + nx - 2] + Tm[r + nx - 3]) * 0.5;
+            const double cTf = (3.0 * Tf[cx[5]] - 4.0 * Tf[cx[4]] + Tf[cx[3]]) * 0.5;
+            const double cTm = (3.0 * Tm[cx[5]] - 4.0 * Tm[cx[4]] + Tm[cx[3]]) * 0.5;
             v[NPART + 1] += L.kf * dTf + L.km * dTm;
             v[NPART + 2] += L.kf * cTf + L.km * cTm;
         }
@@ -612,7 +611,7 @@ __global__ __launch_bounds__(MB) void diag_kernel(DiagLaunch L) {
         // melt front: first f_l = 0.5 crossing on row ny/2 seen from x = 0
         double xf = 1.0;
         if (!L.periodic) {
-            const double *fl = L.fields + 4 * nn + (int64_t)(ny / 2) * nx;
+            const double *fl = L.fl_mid;
             if (fl[0] < 0.5) {
                 xf = 0.0;
             } else {
@@ -639,6 +638,70 @@ hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s) {
     if (L.nx != nx || L.ny != ny) return hipErrorInvalidValue;
     hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(MB), 0, s, L);
     return hipGetLastError();
+}
+
+// The per-node part of the diagnostics without the field planes: a fixed
+// grid strides over the cavity's nodes; each thread folds its nodes'
+// contributions (the same per-node values as macro_kernel) in node order,
+// the block reduction then runs as in macro_kernel.  The temperatures of
+// the three columns next to each vertical wall and the middle row's liquid
+// fraction go to compact arrays (tf/tm: [ny][6], column k for x = 0, 1, 2,
+// nx - 3, nx - 2, nx - 1; fl_mid: [nx]).  Every element of the partials and
+// of the compact arrays is written, so nothing needs clearing beforehand.
+int diag_node_blocks(int nx, int ny) {
+    const int64_t b = ((int64_t)nx * ny + MB - 1) / MB;
+    return (int)(b < LBM_DIAG_MAX_BLOCKS ? b : LBM_DIAG_MAX_BLOCKS);
+}
+
+template <class Lay, typename R, typename RH>
+__global__ __launch_bounds__(MB) void diag_node_kernel(const void *__restrict__ src,
+                                                       const CavityConst<R> *__restrict__ cav, int ci, int raw,
+                                                       double *__restrict__ partials, double *__restrict__ tf,
+                                                       double *__restrict__ tm, double *__restrict__ fl_mid) {
+    const CavityConst<R> &c = cav[ci];
+    const int nx = c.nx, ny = c.ny;
+    const int64_t nn = (int64_t)nx * ny;
+    double tot[NPART];
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) tot[k] = 0.0;
+    for (int64_t kk = (int64_t)blockIdx.x * MB + threadIdx.x; kk < nn; kk += (int64_t)gridDim.x * MB) {
+        const int x = (int)(kk % nx), y = (int)(kk / nx);
+        double out[6], v[NPART];
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) v[k] = 0.0;
+        macro_node<Lay, R, RH>(c, src, raw != 0, x, y, out, v);
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) tot[k] = (k == P_DT || k == P_U) ? fmax(tot[k], v[k]) : tot[k] + v[k];
+        const int cols[6] = {0, 1, 2, nx - 3, nx - 2, nx - 1};
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (x == cols[k]) {
+                tf[(int64_t)y * 6 + k] = out[2];
+                tm[(int64_t)y * 6 + k] = out[3];
+            }
+        if (y == ny / 2) fl_mid[x] = out[4];
+    }
+    __shared__ double sh[NPART][MB / 64];
+    block_reduce<NPART>(tot, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) partials[(int64_t)blockIdx.x * NPART + k] = tot[k];
+    }
+}
+
+template <int ST>
+static hipError_t launch_diag_nodes_s(const DiagNodeLaunch &L, hipStream_t s) {
+    using Lay = typename LayoutOf<ST>::L;
+    using R = typename LayoutOf<ST>::R;
+    using RH = typename LayoutOf<ST>::RH;
+    hipLaunchKernelGGL((diag_node_kernel<Lay, R, RH>), dim3(L.nblocks), dim3(MB), 0, s, L.src,
+                       (const CavityConst<R> *)L.cav, L.cav_index, L.raw, L.partials, L.tf, L.tm, L.fl_mid);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_nodes(const DiagNodeLaunch &L, int nx, int ny, hipStream_t s) {
+    if (L.nblocks != diag_node_blocks(nx, ny)) return hipErrorInvalidValue;
+    LBM_DISPATCH(L.storage, launch_diag_nodes_s, L, s)
 }
 
 // ---------------------------------------------------------------------------

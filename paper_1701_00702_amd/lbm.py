@@ -110,6 +110,7 @@ def _load():
         "lbm_step_count": ([H], ctypes.c_int64),
         "lbm_fields": ([H, ctypes.c_int32, dp, dp, dp, dp, dp, dp], st),
         "lbm_diagnostics": ([H, ctypes.c_int32, ctypes.POINTER(lbm_diag)], st),
+        "lbm_diagnostics_noalloc": ([H, ctypes.c_int32, ctypes.POINTER(lbm_diag)], st),
         "lbm_get_lattice": ([H, ctypes.c_int32, ctypes.POINTER(lbm_lattice)], st),
         "lbm_lattice_of": ([PP, ctypes.c_int, ctypes.POINTER(lbm_lattice)], st),
         "lbm_get_launch": ([H, ctypes.POINTER(lbm_launch_config)], st),
@@ -133,7 +134,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("lbm_create", "lbm_create_batch", "lbm_workspace_bytes", "lbm_create_ext",
             "lbm_set_stream", "lbm_set_initial", "lbm_step", "lbm_step_per_cavity",
-            "lbm_synchronize", "lbm_step_count", "lbm_fields", "lbm_diagnostics",
+            "lbm_synchronize", "lbm_step_count", "lbm_fields", "lbm_diagnostics", "lbm_diagnostics_noalloc",
             "lbm_get_lattice", "lbm_lattice_of", "lbm_get_launch", "lbm_set_launch", "lbm_autotune", "lbm_save",
             "lbm_load", "lbm_copy_state", "lbm_debug_poke", "lbm_destroy", "lbm_last_error")
 
@@ -239,6 +240,17 @@ def lbm_fields(h: int, cavity: int, shape) -> dict:
 def lbm_diagnostics(h: int, cavity: int = 0, allow_nonfinite: bool = False) -> dict:
     d = lbm_diag()
     st = _lib.lbm_diagnostics(h, cavity, ctypes.byref(d))
+    if not (allow_nonfinite and st == LBM_ENONFINITE):
+        _check(st)
+    out = {n: (list(getattr(d, n)) if n in ("flux_E", "flux_M") else float(getattr(d, n)))
+           for n in DIAG_NAMES}
+    out["status"] = st
+    return out
+
+
+def lbm_diagnostics_noalloc(h: int, cavity: int = 0, allow_nonfinite: bool = False) -> dict:
+    d = lbm_diag()
+    st = _lib.lbm_diagnostics_noalloc(h, cavity, ctypes.byref(d))
     if not (allow_nonfinite and st == LBM_ENONFINITE):
         _check(st)
     out = {n: (list(getattr(d, n)) if n in ("flux_E", "flux_M") else float(getattr(d, n)))
