@@ -47,7 +47,8 @@ PEAK_HBM_GBPS = 8000.0
 PEAK_VALU_GIPS = 256 * 64 * 2.4
 METRIC = "MLUPS (3 coupled MRT fields) + achieved HBM GB/s vs peak; FP16-store vs FP32"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1701_00702_amd", "csrc", n)
-                  for n in ("lbm_kernels.hip", "lbm_node.h", "lbm_internal.h", "lbm_api.hip")] + \
+                  for n in ("lbm_kernels.hip", "lbm_node.h", "lbm_internal.h", "lbm_api.hip", "lbm_plan.h",
+                            "lbm_tiles.h")] + \
     [os.path.join(ROOT, "paper_1701_00702_amd", "build.py")]
 
 

@@ -479,19 +479,39 @@ LBM_HD void eos(const ThermalConst<RH> &t, RH H, RH &T, RH &fl) {
 // Moments of the three fields' post-streaming offsets, Eq. (13) (D2Q5
 // thermal fields: Eq. B1).  Their zeroth moments are delta rho, delta H
 // (Eq. 37) and c_pm delta T_m (Eq. 48).
+//
+// Split enthalpy arithmetic (RH wider than R, the form with the FP64 rest
+// enthalpy population): the rest population q_0 carries H, O(1), while the
+// moving ones are small.  The moments g are then taken in R of the moving
+// populations alone (q_0 read as zero) and q_0 is kept in RH as `rest`.
+// Column 0 of the transform is (1, -4, 4, 0, ..., 0) (D2Q5: (1, 0, ..., 0)),
+// and the enthalpy equilibrium moves with H along the same column (Eq. 34:
+// n_1^eq = -4 H + ..., n_2^eq = 4 H - ...; Eq. B2: only n_0^eq), so the
+// collision of the moving part yields every post-collision population, and
+// the rest one is q_0 plus the moving part's rest result: q_0 enters no
+// rounding but that of one addition in RH.
 template <typename R, typename RH>
 struct Moments {
+    static constexpr bool SPLIT = !std::is_same<R, RH>::value;
+    using RG = typename std::conditional<SPLIT, R, RH>::type;
     R f[9], h[9];
-    RH g[9];
+    RG g[9];
+    RH rest;  // SPLIT: the rest enthalpy population q_0
 };
 template <int QT, typename R, typename RH>
 LBM_HD void field_moments(const R qf[9], const RH qg[9], const R qh[9], Moments<R, RH> &mo) {
+    using Mo = Moments<R, RH>;
+    using RG = typename Mo::RG;
     to_moments(qf, mo.f);
+    RG qs[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) qs[i] = Mo::SPLIT && i == 0 ? RG(0) : (RG)qg[i];
+    mo.rest = Mo::SPLIT ? qg[0] : RH(0);
     if (QT == 9) {
-        to_moments(qg, mo.g);
+        to_moments(qs, mo.g);
         to_moments(qh, mo.h);
     } else {
-        to_moments5(qg, mo.g);
+        to_moments5(qs, mo.g);
         to_moments5(qh, mo.h);
     }
 }
@@ -505,7 +525,7 @@ template <int QT, typename R, typename RH>
 LBM_HD void macros_of(const CavityConst<R> &c, Moments<R, RH> &mo, Thermo<RH> &th, Macro<R> &m) {
     const ThermalConst<RH> &t = thermal<RH>(c);
     // Eq. (37), Eqs. (38)-(39)
-    th.dH = mo.g[0];
+    th.dH = Moments<R, RH>::SPLIT ? (RH)mo.g[0] + mo.rest : (RH)mo.g[0];
     th.H = t.H_ref + th.dH;
     eos(t, th.H, th.Tf, th.fl);
     m.Tf = (R)th.Tf;
@@ -603,31 +623,45 @@ LBM_HD void collide_flow(const CavityConst<R> &c, const Macro<R> &m, R d[9], R q
     from_scaled(a, q);
 }
 
-// PCM enthalpy collision, Eqs. (32), (34)-(35).
-template <typename R, typename RH>
+// Post-collision enthalpy offsets from the collision's output qs (in the
+// moment type RG): the rest population adds q_0 back in the split form.
+template <typename RG, typename RH>
+LBM_HD void pcm_out(const RG qs[9], RH rest, RH q[9]) {
+    constexpr bool SPLIT = !std::is_same<RG, RH>::value;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) q[i] = SPLIT && i == 0 ? rest + (RH)qs[0] : (RH)qs[i];
+}
+
+// PCM enthalpy collision, Eqs. (32), (34)-(35), from the moments d (in RG,
+// of the moving populations alone in the split form, where rest is q_0; d_0
+// is then delta H - q_0, and the equilibrium of Eq. 34 is taken at it).
+template <typename R, typename RH, typename RG>
 LBM_HD void collide_pcm(const CavityConst<R> &c, const Thermo<RH> &th, const Macro<R> &m, RH S_pcm,
-                        RH d[9], RH q[9]) {
-    const ThermalConst<RH> &t = thermal<RH>(c);
-    const RH dT = th.Tf - t.T_ref;
-    const RH jT = t.c_pl * th.Tf * t.inv_phi;
-    RH eq[7];  // eq_0 = delta H; eq_7 = eq_8 = 0
-    eq[1] = -RH(4) * th.dH + RH(2) * t.c_fref * dT;
-    eq[2] = RH(4) * th.dH - RH(3) * t.c_fref * dT;
-    eq[3] = jT * (RH)m.ux;
+                        RG d[9], RH rest, RH q[9]) {
+    const ThermalConst<RG> &t = thermal<RG>(c);
+    const RG dT = (RG)(th.Tf - thermal<RH>(c).T_ref);
+    const RG jT = t.c_pl * (RG)th.Tf * t.inv_phi;
+    const RG S = (RG)S_pcm;
+    RG eq[7];  // eq_0 = d_0; eq_7 = eq_8 = 0
+    eq[1] = -RG(4) * d[0] + RG(2) * t.c_fref * dT;
+    eq[2] = RG(4) * d[0] - RG(3) * t.c_fref * dT;
+    eq[3] = jT * (RG)m.ux;
     eq[4] = -eq[3];
-    eq[5] = jT * (RH)m.uy;
+    eq[5] = jT * (RG)m.uy;
     eq[6] = -eq[5];
     // scaled moments ((1 - zeta) d + zeta eq + S (1, -2, 1, 0, ...)) / |M_k|^2;
-    // the zeroth moment is conserved (d_0 = eq_0 = delta H), only S moves it
-    RH a[9];
-    a[0] = (d[0] + S_pcm) * moment_norm<RH>(0);
-    a[1] = fma_of(RH(-2) * moment_norm<RH>(1), S_pcm, fma_of(t.zB[1], eq[1], t.zA[1] * d[1]));
-    a[2] = fma_of(moment_norm<RH>(2), S_pcm, fma_of(t.zB[2], eq[2], t.zA[2] * d[2]));
+    // the zeroth moment is conserved (d_0 = eq_0), only S moves it
+    RG a[9];
+    a[0] = (d[0] + S) * moment_norm<RG>(0);
+    a[1] = fma_of(RG(-2) * moment_norm<RG>(1), S, fma_of(t.zB[1], eq[1], t.zA[1] * d[1]));
+    a[2] = fma_of(moment_norm<RG>(2), S, fma_of(t.zB[2], eq[2], t.zA[2] * d[2]));
 #pragma unroll
     for (int k = 3; k < 7; ++k) a[k] = fma_of(t.zB[k], eq[k], t.zA[k] * d[k]);
     a[7] = t.zA[7] * d[7];
     a[8] = t.zA[8] * d[8];
-    from_scaled(a, q);
+    RG qs[9];
+    from_scaled(a, qs);
+    pcm_out(qs, rest, q);
 }
 
 // Metal-foam collision, Eqs. (43), (45)-(46).
@@ -651,20 +685,24 @@ LBM_HD void collide_metal(const CavityConst<R> &c, const Macro<R> &m, R S_metal,
 // offsets, Theta in the moment order of Eq. (B1), source S (1, 0, 0, varpi, 0);
 // scaled moments e_k = g_k ((1 - zeta_k) d_k + zeta_k eq_k + S_k), the
 // zeroth moment conserved (d_0 = eq_0 = delta H) so only S moves it.
-template <typename R, typename RH>
+template <typename R, typename RH, typename RG>
 LBM_HD void collide_pcm5(const CavityConst<R> &c, const Thermo<RH> &th, const Macro<R> &m, RH S_pcm,
-                         RH d[9], RH q[9]) {
-    const ThermalConst<RH> &t = thermal<RH>(c);
-    const RH jT = t.c_pl * th.Tf * t.inv_phi;
-    const RH eq1 = jT * (RH)m.ux, eq2 = jT * (RH)m.uy;  // eq_4 = 0
-    const RH eq3 = t.varpi * t.c_fref * (th.Tf - t.T_ref);
-    RH e[5];
-    e[0] = d[0] + S_pcm;
+                         RG d[9], RH rest, RH q[9]) {
+    const ThermalConst<RG> &t = thermal<RG>(c);
+    const RG jT = t.c_pl * (RG)th.Tf * t.inv_phi;
+    const RG eq1 = jT * (RG)m.ux, eq2 = jT * (RG)m.uy;  // eq_4 = 0
+    const RG eq3 = t.varpi * t.c_fref * (RG)(th.Tf - thermal<RH>(c).T_ref);
+    const RG S = (RG)S_pcm;
+    RG e[5];
+    e[0] = d[0] + S;
     e[1] = fma_of(t.zB[1], eq1, t.zA[1] * d[1]);
     e[2] = fma_of(t.zB[2], eq2, t.zA[2] * d[2]);
-    e[3] = fma_of(t.varpi * RH(0.25), S_pcm, fma_of(t.zB[3], eq3, t.zA[3] * d[3]));
+    e[3] = fma_of(t.varpi * RG(0.25), S, fma_of(t.zB[3], eq3, t.zA[3] * d[3]));
     e[4] = t.zA[4] * d[4];
-    from_scaled5(e, q);
+    RG qs[9];
+    from_scaled5(e, qs);
+    qs[5] = qs[6] = qs[7] = qs[8] = RG(0);
+    pcm_out(qs, rest, q);
 }
 
 // D2Q5 metal-foam collision (Appendix B): Eq. (B4), Q, S (1, 0, 0, varpi, 0),
@@ -914,10 +952,10 @@ LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, 
     const RH S_pcm = srf + RH(0.5) * (srf - (RH)sr_prev);
     const R S_metal = srm + R(0.5) * (srm - srm_prev);
     if (QT == 9) {
-        collide_pcm(c, th, m, S_pcm, mo.g, qg);
+        collide_pcm(c, th, m, S_pcm, mo.g, mo.rest, qg);
         collide_metal(c, m, S_metal, mo.h, qh);
     } else {
-        collide_pcm5(c, th, m, S_pcm, mo.g, qg);
+        collide_pcm5(c, th, m, S_pcm, mo.g, mo.rest, qg);
         collide_metal5(c, m, S_metal, mo.h, qh);
     }
 
@@ -1066,6 +1104,11 @@ struct LdsCodec<PlainH64<QT_>> {
         if (f == 1 && i == 0) ((double *)((char *)lds + f64_offset(nslot)))[slot] = (double)v;
         else ((float *)lds)[PlainH64<QT_>::plane(f, i) * nslot + slot] = (float)v;
     }
+    template <typename V, typename R>
+    LBM_HD static void put1(void *lds, int nslot, int f, int i, int slot, V v, const CavityConst<R> &c) {
+        (void)c;
+        put1(lds, nslot, f, i, slot, v);
+    }
     template <typename R, typename RH>
     LBM_HD static void put_node(void *lds, int nslot, int slot, const CavityConst<R> &c, const R qf[9],
                                 const RH qg[9], const R qh[9], R bf, RH bg, R bh) {
@@ -1143,6 +1186,13 @@ struct PushLds {
 template <>
 struct PushLds<Plain<E32, false, 9>, 3> {
     static constexpr bool value = LBM_PUSH_F32_K3;
+};
+#ifndef LBM_PUSH_F32H_K3
+#define LBM_PUSH_F32H_K3 1
+#endif
+template <>
+struct PushLds<PlainH64<9>, 3> {
+    static constexpr bool value = LBM_PUSH_F32H_K3;
 };
 #ifndef LBM_PUSH_F64_K2
 #define LBM_PUSH_F64_K2 1
