@@ -35,6 +35,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BYTES_PER_NODE = {"f64": 448, "f32": 224, "f32h64": 232, "f16split": 152, "f16": 116, "bf16": 116}
+# The storage form the FP32 configurations are timed in: FP32 populations
+# with the rest enthalpy population (which carries H) in FP64, the only
+# FP32 form that holds every field within 1e-4 of the FP64 oracle over the
+# 256^2 A/B run.
+FP32_FORM = "f32h64"
+# Algorithmic VALU instructions per node update of the timed forms: those of
+# the one-step kernel (no multi-step ring), counted with rocprofv3
+# (SQ_INSTS_VALU x 64 / node updates) on the 8192^2 cavity.
+ALG_VALU_PER_NODE_STEP = {"f32": 463.3, "f32h64": 485.7}
+# The paper's own timings (Table I, present scheme, quad-core 2.33 GHz CPU;
+# precision and thread count not stated): context only.
+PAPER_TABLE_I = [
+    {"grid": "150x150", "Ra": 1e6, "steps": 90000, "cpu_s": 423.79, "steps_per_s": 212.37,
+     "MLUPS": 150 * 150 * 212.37 / 1e6},
+    {"grid": "300x300", "Ra": 1e8, "steps": 360000, "cpu_s": 11611.81, "steps_per_s": 31.0,
+     "MLUPS": 300 * 300 * 31.0 / 1e6},
+]
 BYTES_PER_NODE_D2Q5 = {"f64": 320, "f32": 160, "f32h64": 168}
 
 
@@ -108,9 +125,9 @@ def valu_from_profile(sha: str, workload_name: str, precision: str, thermal_latt
                       steps_per_launch: int):
     """VALU instructions per node and step of the timed kernel, counted with
     rocprofv3 (SQ_INSTS_VALU) on the current kernel source, if profiled."""
-    if (workload_name, precision, thermal_lattice) != ("c3", "f32", 9):
+    if thermal_lattice != 9:
         return None
-    path = os.path.join(ROOT, "profiles", "valu_step_kernels_c3_f32.md")
+    path = os.path.join(ROOT, "profiles", f"valu_step_kernels_{workload_name}_{precision}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -144,13 +161,15 @@ def time_steps(lbm, torch, s, stream, steps, warmup, looped=False):
     return e0.elapsed_time(e1)  # ms
 
 
-def cpu_baseline(params, seed, budget_s=15.0):
-    """The FP64 oracle on a 384 x 384 window of the same cavity (hot-wall
-    corner), OpenMP over rows on the host cores."""
+def cpu_baseline(params, seed, budget_s=15.0, side=1536):
+    """The FP64 oracle on a side x side window of the same cavity (hot-wall
+    corner), OpenMP over rows on the host cores.  At 1536^2 its two FP64
+    population sets (27 x 8 B x 2 per node) take 1.0 GB, far beyond the
+    host's caches, as the GPU workload's state is beyond the GPU's."""
     import oracle
     import lbm_workloads as W
     p = params[0]
-    win = (0, 0, min(384, p["nx"]), min(384, p["ny"]))
+    win = (0, 0, min(side, p["nx"]), min(side, p["ny"]))
     d = W.perturbation(seed, win[3], win[2])
     Tf = np.full((win[3], win[2]), p["T_init"])
     Tf[1:, 1:] += d[1:, 1:]
@@ -183,9 +202,10 @@ def cpu_baseline(params, seed, budget_s=15.0):
                 break
     except OSError:
         pass
+    state_gb = nodes * 27 * 8 * 2 / 1e9
     return {"value": nodes * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{win[2]}x{win[3]} window at the hot-wall corner of the same cavity, "
-                      f"{n} steps, {dt:.1f} s, FP64",
+                      f"{n} steps, {dt:.1f} s, FP64, {state_gb:.2f} GB of populations (not cache-resident)",
             "single_thread_value": nodes * n1 / dt1 / 1e6, "single_thread_sample": f"{n1} steps, {dt1:.1f} s",
             "host_cpu": model}
 
@@ -263,6 +283,8 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--forms", action="store_true", help="also time the 16-bit and batched forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp16-store", action="store_true",
+                    help="skip the 4096^2 FP16-store vs FP32 timing the default run adds")
     ap.add_argument("--accuracy", default=None, choices=["c2", "c4"],
                     help="only run the full-length error report of the 1024^2 (c2) or 4096^2 (c4) cavity")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -300,7 +322,7 @@ def main():
     import lbm_workloads as W
 
     params, seed, prec, desc = workload(args.workload)
-    prec = args.precision or prec
+    prec = args.precision or (FP32_FORM if prec == "f32" else prec)
     qt = args.thermal_lattice
     if qt == 5:
         if prec not in BYTES_PER_NODE_D2Q5:
@@ -324,14 +346,42 @@ def main():
     ms_step = ms / args.steps
     mlups = nodes / (ms_step * 1e-3) / 1e6
     # A launch reads and writes the state once, whether it advances one step
-    # or several (through LDS); the roofline is per launch.
+    # or several (through LDS): bytes are per launch.
     spl = launch["steps_per_launch"]
     alg = bytes_per_node(prec, qt) * nodes
     launch_ms = ms_step * spl
-    achieved = alg / (launch_ms * 1e-3) / 1e9
+    launch_s = launch_ms * 1e-3
     sha = kernel_sha()
     traffic = traffic_from_profile(sha, args.workload, prec, qt, spl)
-    valu = valu_from_profile(sha, args.workload, prec, qt, spl)
+    valu_k = valu_from_profile(sha, args.workload, prec, qt, spl)
+    valu_1 = valu_from_profile(sha, args.workload, prec, qt, 1)
+    hbm = {"algorithmic_bytes_per_launch": alg,
+           "algorithmic_GBps": alg / launch_s / 1e9, "algorithmic_frac": alg / launch_s / 1e9 / PEAK_HBM_GBPS,
+           "counted_bytes_per_launch": traffic,
+           "counted_GBps": None if traffic is None else traffic / launch_s / 1e9,
+           "counted_frac": None if traffic is None else traffic / launch_s / 1e9 / PEAK_HBM_GBPS,
+           "peak_GBps": PEAK_HBM_GBPS}
+    alg_instr = ALG_VALU_PER_NODE_STEP.get(prec) if qt == 9 else None
+    if spl > 1 and alg_instr:
+        # Several steps per launch through LDS: the launch moves the state
+        # once for spl steps and is bound by instruction issue.  Algorithmic
+        # work: the one-step update's VALU instructions per node x the node
+        # updates of the launch (the ring's redundant updates excluded);
+        # peak: one 64-lane VALU instruction per CU and clock.
+        alg_ti = alg_instr * nodes * spl / launch_s / 1e12
+        roof = {"bound": "alu", "achieved": alg_ti, "peak": PEAK_VALU_GIPS / 1e3, "unit": "T lane-instr/s",
+                "frac": alg_ti / (PEAK_VALU_GIPS / 1e3), "traffic": traffic,
+                "algorithmic_instructions_per_node_step": alg_instr}
+        if valu_k is not None:
+            issued = valu_k * nodes * spl / launch_s / 1e12
+            roof["issued"] = {"instructions_per_node_step": valu_k, "achieved": issued,
+                              "frac": issued / (PEAK_VALU_GIPS / 1e3)}
+        if valu_1 is not None:
+            roof["counted_one_step_instructions_per_node_step"] = valu_1
+    else:
+        roof = {"bound": "hbm", "achieved": alg / launch_s / 1e9, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                "frac": alg / launch_s / 1e9 / PEAK_HBM_GBPS, "traffic": traffic}
+    roof.update({"hbm": hbm, "steps_per_launch": spl, "launch_ms": launch_ms, "kernel_sha": sha})
     single = None
     if spl > 1:
         # the one-step kernel on the same state, for reference
@@ -341,38 +391,51 @@ def main():
         single = {"MLUPS": nodes / (t1 * 1e-3) / 1e6, "ms_per_step": t1,
                   "achieved_GBps": alg / (t1 * 1e-3) / 1e9,
                   "frac": alg / (t1 * 1e-3) / 1e9 / PEAK_HBM_GBPS}
+    storage_desc = {"f32h64": "FP32 populations, FP64 rest enthalpy population",
+                    "f32": "FP32 populations", "f64": "FP64 populations",
+                    "f16split": "FP32 rest populations and bases, FP16 remainders",
+                    "f16": "FP16 offsets", "bf16": "BF16 offsets"}[prec]
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
-        "config": {"workload": desc, "nodes": nodes, "storage": prec, "thermal_lattice": qt, "launch": launch,
-                   "seed": seed,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "nodes": nodes, "storage": prec, "storage_detail": storage_desc,
+                   "thermal_lattice": qt, "launch": launch, "seed": seed,
                    "step_kernel": (f"lbm::stepk_kernel ({launch['steps_per_launch']} fused steps per launch "
                                    "through LDS tiles)" if launch["steps_per_launch"] > 1 else
                                    "lbm::step_kernel (fused pull-stream + NEE walls + 3 MRT collisions)")},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBPS,
-                     "traffic": None if traffic is None else traffic,
-                     "algorithmic_bytes_per_launch": alg, "steps_per_launch": spl,
-                     "launch_ms": launch_ms, "kernel_sha": sha,
-                     # the bytes a one-step sweep would move per step, over the
-                     # measured time per step (above peak: temporal blocking)
-                     "per_step_equivalent_GBps": alg / (ms_step * 1e-3) / 1e9,
-                     "per_step_equivalent_frac": alg / (ms_step * 1e-3) / 1e9 / PEAK_HBM_GBPS,
-                     # the same kernel against the VALU issue rate: counted
-                     # instructions per node-step x node-steps per second
-                     "valu": None if valu is None else {
-                         "instructions_per_node_step": valu,
-                         "achieved_Ginstr_per_s": valu * mlups / 1e3, "peak_Ginstr_per_s": PEAK_VALU_GIPS,
-                         "frac": valu * mlups / 1e3 / PEAK_VALU_GIPS}},
+        "roofline": roof,
         "check": {"nonfinite": d["nonfinite"], "liquid_fraction": d["liquid_fraction"],
                   "energy_residual_rel": d["energy_residual"] / max(abs(d["E_int"]), 1e-300)},
+        "paper_context": {"table_I_present_scheme": PAPER_TABLE_I,
+                          "hardware": "quad-core 2.33 GHz CPU (precision and threads not stated)"},
     }
     if single is not None:
         out["one_step_kernel"] = single
     s.close()
     del ws
     torch.cuda.empty_cache()
+
+    if args.workload == "c3" and qt == 9 and not args.no_fp16_store:
+        # The metric's FP16-store vs FP32 comparison on the 4096^2 precision
+        # workload: the split FP16 form against the FP32 forms, default launch.
+        fp16 = {"workload": workload("c4")[3]}
+        for pr in ("f16split", "f32h64", "f32"):
+            ps, sd, _, _ = workload("c4")
+            s2, ws2 = make_solver(lbm, torch, ps, pr, stream)
+            s2.set_initial(0, *W.initial_temperatures(ps[0], sd))
+            n2 = ps[0]["nx"] * ps[0]["ny"]
+            sp2 = lbm.lbm_get_launch(s2.h)["steps_per_launch"]
+            t = time_steps(lbm, torch, s2, stream, 96, 12) / 96
+            fp16[pr] = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t, "steps_per_launch": sp2,
+                        "bytes_per_node_step": bytes_per_node(pr),
+                        "alg_GBps_per_launch": bytes_per_node(pr) * n2 / (t * sp2 * 1e-3) / 1e9}
+            s2.close()
+            del ws2
+            torch.cuda.empty_cache()
+        fp16["f16split_over_f32h64"] = fp16["f16split"]["MLUPS"] / fp16["f32h64"]["MLUPS"]
+        out["fp16_store_vs_fp32"] = fp16
 
     if args.forms:
         forms = {}
