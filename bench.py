@@ -34,7 +34,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BYTES_PER_NODE = {"f64": 448, "f32": 224, "f32h64": 232, "f16split": 152, "f16": 116, "bf16": 116}
+BYTES_PER_NODE = {"f64": 448, "f32": 224, "f32h64": 232, "f16split": 152, "bf16split": 152, "f16": 116,
+                  "bf16": 116}
 # The storage form the FP32 configurations are timed in: FP32 populations
 # with the rest enthalpy population (which carries H) in FP64, the only
 # FP32 form that holds every field within 1e-4 of the FP64 oracle over the
@@ -223,7 +224,7 @@ def accuracy(name: str) -> dict:
         forms = ["f64", "f32", "f32h64"]
     elif name == "c4":
         p, steps, seed, _ = W.case_c4()
-        forms = ["f64", "f32", "f32h64", "f16split", "f16", "bf16"]
+        forms = ["f64", "f32", "f32h64", "f16split", "bf16split", "f16", "bf16"]
     else:
         raise SystemExit("--accuracy takes c2 or c4")
     T_pcm, T_mf = W.initial_temperatures(p, seed)
@@ -394,6 +395,7 @@ def main():
     storage_desc = {"f32h64": "FP32 populations, FP64 rest enthalpy population",
                     "f32": "FP32 populations", "f64": "FP64 populations",
                     "f16split": "FP32 rest populations and bases, FP16 remainders",
+                    "bf16split": "FP32 rest populations and bases, BF16 remainders",
                     "f16": "FP16 offsets", "bf16": "BF16 offsets"}[prec]
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -439,8 +441,9 @@ def main():
 
     if args.forms:
         forms = {}
-        for wl, pr, q in (("c3", "f32h64", 9), ("c3", "f16split", 9), ("c3", "f16", 9), ("c3", "bf16", 9),
-                          ("c4", "f32", 9), ("c4", "f16split", 9), ("c4", "f16", 9), ("c4", "bf16", 9),
+        for wl, pr, q in (("c3", "f32", 9), ("c3", "f16split", 9), ("c3", "bf16split", 9), ("c3", "f16", 9),
+                          ("c3", "bf16", 9), ("c4", "f32", 9), ("c4", "f16split", 9), ("c4", "bf16split", 9),
+                          ("c4", "f16", 9), ("c4", "bf16", 9),
                           ("c3", "f32", 5), ("c3", "f32h64", 5), ("c3", "f64", 5), ("c3", "f64", 9)):
             if q == qt and wl == args.workload and pr == prec:
                 continue

@@ -67,9 +67,11 @@ typedef enum {
  *                      metal: c_m,ref (T_m - T_ref)) in FP32, and the eight
  *                      moving populations as binary16 remainders from the rest
  *                      equilibrium of that base (72 bytes per node)
+ *   LBM_BF16_SPLIT     as LBM_F16_SPLIT with bfloat16 remainders (72)
  *   LBM_F32_H64        as LBM_F32, except the rest population of the enthalpy
- *                      field, which carries H itself, in FP64, and the
- *                      enthalpy-field arithmetic in FP64 (112 bytes per node).
+ *                      field, which carries H itself, in FP64; that population,
+ *                      H, T_f and f_l are computed in FP64, the rest of the
+ *                      enthalpy collision in FP32 (112 bytes per node).
  * With D2Q5 thermal fields (lbm_params.thermal_lattice = 5) the forms
  * LBM_F64, LBM_F32 and LBM_F32_H64 are available: 152, 76 and 80 bytes per
  * node, planes [f0..f8, g0..g4, h0..h4] (LBM_F32_H64: [f0..f8, g1..g4,
@@ -80,7 +82,8 @@ typedef enum {
     LBM_F16_OFFSET = 2,
     LBM_BF16_OFFSET = 3,
     LBM_F16_SPLIT = 4,
-    LBM_F32_H64 = 5
+    LBM_F32_H64 = 5,
+    LBM_BF16_SPLIT = 6
 } lbm_precision;
 
 /* Problem description in dimensionless groups (Eq. 54).  Lattice units:

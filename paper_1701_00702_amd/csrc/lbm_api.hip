@@ -1135,13 +1135,13 @@ extern "C" lbm_status lbm_debug_poke(lbm_handle *h, int32_t c, int32_t x, int32_
             ptr = base + ((size_t)plane * S + node) * 4;
             elem = 4;
         }
-    } else if (h->st == ST_F16S) {
+    } else if (h->st == ST_F16S || h->st == ST_BF16S) {
         if (dir == 0) {
             ptr = base + ((size_t)(2 * field) * S + node) * 4;
             elem = 4;
         } else {
             ptr = base + (size_t)6 * S * 4 + ((size_t)(8 * field + dir - 1) * S + node) * 2;
-            elem = 2;
+            elem = h->st == ST_BF16S ? 3 : 2;
         }
     } else {
         const int eb = bytes_per_node(h->st) / (9 + 2 * qt);

@@ -7,11 +7,11 @@
 
 namespace lbm {
 
-// Storage forms.  The first six carry D2Q9 thermal fields (27 populations
-// per node); the last three the D2Q5 thermal fields of Appendix B (19).
+// Storage forms.  ST_F64 .. ST_F32H and ST_BF16S carry D2Q9 thermal fields
+// (27 populations per node); ST5_* the D2Q5 thermal fields of Appendix B (19).
 enum Storage {
     ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F16S = 4, ST_F32H = 5,
-    ST5_F64 = 6, ST5_F32 = 7, ST5_F32H = 8
+    ST5_F64 = 6, ST5_F32 = 7, ST5_F32H = 8, ST_BF16S = 9
 };
 
 enum Wall { W_LEFT = 0, W_RIGHT = 1, W_BOTTOM = 2, W_TOP = 3 };

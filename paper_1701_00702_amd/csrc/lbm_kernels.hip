@@ -37,6 +37,7 @@ int bytes_per_node(int storage) {
         case ST_F16: return LayoutOf<ST_F16>::L::bytes_per_node;
         case ST_BF16: return LayoutOf<ST_BF16>::L::bytes_per_node;
         case ST_F16S: return LayoutOf<ST_F16S>::L::bytes_per_node;
+        case ST_BF16S: return LayoutOf<ST_BF16S>::L::bytes_per_node;
         case ST_F32H: return LayoutOf<ST_F32H>::L::bytes_per_node;
         case ST5_F64: return LayoutOf<ST5_F64>::L::bytes_per_node;
         case ST5_F32: return LayoutOf<ST5_F32>::L::bytes_per_node;
@@ -53,6 +54,7 @@ int bytes_per_node(int storage) {
         case ST_F16: return FN<ST_F16>(__VA_ARGS__);                       \
         case ST_BF16: return FN<ST_BF16>(__VA_ARGS__);                     \
         case ST_F16S: return FN<ST_F16S>(__VA_ARGS__);                     \
+        case ST_BF16S: return FN<ST_BF16S>(__VA_ARGS__);                   \
         case ST_F32H: return FN<ST_F32H>(__VA_ARGS__);                     \
         case ST5_F64: return FN<ST5_F64>(__VA_ARGS__);                     \
         case ST5_F32: return FN<ST5_F32>(__VA_ARGS__);                     \
@@ -301,6 +303,7 @@ void stepk_tile(int storage, int k, int *tw, int *th) {
             case ST_F16: return tile_of<ST_F16, 3>(tw, th);
             case ST_BF16: return tile_of<ST_BF16, 3>(tw, th);
             case ST_F16S: return tile_of<ST_F16S, 3>(tw, th);
+            case ST_BF16S: return tile_of<ST_BF16S, 3>(tw, th);
             default: return;
         }
     }
@@ -309,6 +312,7 @@ void stepk_tile(int storage, int k, int *tw, int *th) {
         case ST_F16: return tile_of<ST_F16, 2>(tw, th);
         case ST_BF16: return tile_of<ST_BF16, 2>(tw, th);
         case ST_F16S: return tile_of<ST_F16S, 2>(tw, th);
+        case ST_BF16S: return tile_of<ST_BF16S, 2>(tw, th);
         case ST_F32: return tile_of<ST_F32, 2>(tw, th);
         case ST5_F32: return tile_of<ST5_F32, 2>(tw, th);
         case ST_F64: return tile_of<ST_F64, 2>(tw, th);
@@ -330,6 +334,7 @@ hipError_t launch_stepk(const Step2Launch &L, hipStream_t s) {
             case ST_F16: return launch_stepk_s<ST_F16, 3>(L, s);
             case ST_BF16: return launch_stepk_s<ST_BF16, 3>(L, s);
             case ST_F16S: return launch_stepk_s<ST_F16S, 3>(L, s);
+            case ST_BF16S: return launch_stepk_s<ST_BF16S, 3>(L, s);
             default: return hipErrorInvalidValue;
         }
     }
@@ -344,6 +349,7 @@ hipError_t launch_stepk(const Step2Launch &L, hipStream_t s) {
         case ST_F16: return launch_stepk_s<ST_F16, 2>(L, s);
         case ST_BF16: return launch_stepk_s<ST_BF16, 2>(L, s);
         case ST_F16S: return launch_stepk_s<ST_F16S, 2>(L, s);
+        case ST_BF16S: return launch_stepk_s<ST_BF16S, 2>(L, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -282,15 +282,17 @@ struct PlainH64 {
 };
 
 // Split 16-bit layout: per field, the rest population and a base value beta
-// in FP32, and the eight moving populations as FP16 remainders from the rest
-// equilibrium of the base, r_i = q_i - w_i beta (scaled).  Bases: flow
-// delta rho, enthalpy c_f,ref (T_f - T_ref), metal c_m,ref (T_m - T_ref); the
-// moving populations stay close to w_i beta, so their remainders are small
-// and FP16 keeps them to ~1e-3 relative, while the conserved content
-// (rest population, base) keeps FP32 precision.
+// in FP32, and the eight moving populations as 16-bit remainders (binary16,
+// ER = E16, or bfloat16, ER = EB16) from the rest equilibrium of the base,
+// r_i = q_i - w_i beta (scaled).  Bases: flow delta rho, enthalpy
+// c_f,ref (T_f - T_ref), metal c_m,ref (T_m - T_ref); the moving populations
+// stay close to w_i beta, so their remainders are small and 16 bits keep
+// them to ~1e-3 (binary16) or ~8e-3 (bfloat16) relative, while the
+// conserved content (rest population, base) keeps FP32 precision.
 // Planes: 6 FP32 planes [q_f0, beta_f, q_g0, beta_g, q_h0, beta_h], then 24
-// FP16 planes [field][direction 1..8]; 72 bytes per node.
-struct Split16 {
+// 16-bit planes [field][direction 1..8]; 72 bytes per node.
+template <class ER>
+struct SplitT {
     static constexpr int QT = 9;
     static constexpr int bytes_per_node = 6 * 4 + 24 * 2;
     template <typename V, typename R, typename K>
@@ -299,7 +301,7 @@ struct Split16 {
         if (i == 0) return (V)ld_stream(at(P + (int64_t)(2 * f) * stride, k));
         const V beta = (V)ld_stream(at(P + (int64_t)(2 * f + 1) * stride, k));
         const uint16_t *Qp = (const uint16_t *)(P + 6 * stride);
-        const V r = (V)E16::dec(ld_stream(at(Qp + (int64_t)(8 * f + i - 1) * stride, k)));
+        const V r = (V)ER::dec(ld_stream(at(Qp + (int64_t)(8 * f + i - 1) * stride, k)));
         return w_of<V>(i) * beta + r * (V)c.inv_scale[f];
     }
     template <typename V, typename R, typename K>
@@ -312,11 +314,13 @@ struct Split16 {
         uint16_t *Qp = (uint16_t *)(P + 6 * stride);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const uint16_t e = E16::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f]));
+            const uint16_t e = ER::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f]));
             st_stream(at_store(Qp, 8 * f + i - 1, stride, k, e), e);
         }
     }
 };
+using Split16 = SplitT<E16>;
+using SplitB16 = SplitT<EB16>;
 
 // Layout and arithmetic types of each storage form.
 template <int ST>
@@ -348,6 +352,12 @@ struct LayoutOf<ST_BF16> {
 template <>
 struct LayoutOf<ST_F16S> {
     using L = Split16;
+    using R = float;
+    using RH = float;
+};
+template <>
+struct LayoutOf<ST_BF16S> {
+    using L = SplitB16;
     using R = float;
     using RH = float;
 };
@@ -1133,9 +1143,9 @@ struct LdsCodec<PlainH64<QT_>> {
     }
 };
 // Split 16-bit layout: per field the FP32 rest population and base, then the
-// eight FP16 remainders from the base's rest equilibrium.
-template <>
-struct LdsCodec<Split16> {
+// eight 16-bit remainders from the base's rest equilibrium.
+template <class ER>
+struct LdsCodec<SplitT<ER>> {
     static constexpr int QT = 9;
     static constexpr size_t bytes(int nslot) { return (size_t)nslot * (6 * 4 + 24 * 2); }
     template <typename V, typename R>
@@ -1147,7 +1157,7 @@ struct LdsCodec<Split16> {
         P[(2 * f + 1) * nslot + slot] = (float)beta;
 #pragma unroll
         for (int i = 1; i < 9; ++i)
-            Qp[(8 * f + i - 1) * nslot + slot] = E16::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f]));
+            Qp[(8 * f + i - 1) * nslot + slot] = ER::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f]));
     }
     template <typename R, typename RH>
     LBM_HD static void put_node(void *lds, int nslot, int slot, const CavityConst<R> &c, const R qf[9],
@@ -1162,7 +1172,7 @@ struct LdsCodec<Split16> {
         if (i == 0) return (V)P[(2 * f) * nslot + slot];
         const V beta = (V)P[(2 * f + 1) * nslot + slot];
         const uint16_t *Qp = (const uint16_t *)(P + 6 * nslot);
-        const V r = (V)E16::dec(Qp[(8 * f + i - 1) * nslot + slot]);
+        const V r = (V)ER::dec(Qp[(8 * f + i - 1) * nslot + slot]);
         return w_of<V>(i) * beta + r * (V)c.inv_scale[f];
     }
 };

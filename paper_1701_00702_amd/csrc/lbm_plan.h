@@ -221,7 +221,7 @@ inline lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l
         return fail(LBM_EINVAL, "interstitial exchange number z = %g >= 1: explicit source unstable", l.z);
     // storage scales (16-bit forms): keep the largest expected offset near 2^14
     l.scale_exp[0] = l.scale_exp[1] = l.scale_exp[2] = 0;
-    if (prec == LBM_F16_SPLIT) {
+    if (prec == LBM_F16_SPLIT || prec == LBM_BF16_SPLIT) {
         // remainders from the rest equilibrium of the base values (small)
         l.scale_exp[0] = 16;
         l.scale_exp[1] = 12;
@@ -407,6 +407,7 @@ inline int storage_of(lbm_precision p, int qt = 9) {
         case LBM_F16_OFFSET: return ST_F16;
         case LBM_BF16_OFFSET: return ST_BF16;
         case LBM_F16_SPLIT: return ST_F16S;
+        case LBM_BF16_SPLIT: return ST_BF16S;
         case LBM_F32_H64: return ST_F32H;
     }
     return -1;
@@ -424,7 +425,8 @@ inline int plane_groups(int st, PlaneGroup g[2]) {
         case ST_F32: g[0] = {27, 4}; return 1;
         case ST_F16:
         case ST_BF16: g[0] = {27, 2}; return 1;
-        case ST_F16S: g[0] = {6, 4}; g[1] = {24, 2}; return 2;
+        case ST_F16S:
+        case ST_BF16S: g[0] = {6, 4}; g[1] = {24, 2}; return 2;
         case ST_F32H: g[0] = {26, 4}; g[1] = {1, 8}; return 2;
         case ST5_F64: g[0] = {19, 8}; return 1;
         case ST5_F32: g[0] = {19, 4}; return 1;

@@ -14,7 +14,7 @@ constexpr int round64(int n) { return (n + 63) / 64 * 64; }
 // two-node ring leaves too few nodes per workgroup).
 constexpr bool stepk_available(int st, int k) {
     const bool fp32 = st == ST_F32 || st == ST5_F32 || st == ST_F32H || st == ST5_F32H;
-    const bool b16 = st == ST_F16 || st == ST_BF16 || st == ST_F16S;
+    const bool b16 = st == ST_F16 || st == ST_BF16 || st == ST_F16S || st == ST_BF16S;
     return k == 2 ? (fp32 || b16 || st == ST_F64 || st == ST5_F64) : (k == 3 ? (fp32 || b16) : false);
 }
 
@@ -57,6 +57,8 @@ template <>
 struct Step2Tile<ST_F16S> {  // 6 x 4 + 24 x 2 + 4 = 76 B per slot, 34 x 15 slots (38 KiB: 4 per CU)
     static constexpr int TW = 32, TH = 13, NT = 512;
 };
+template <>
+struct Step2Tile<ST_BF16S> : Step2Tile<ST_F16S> {};
 #ifndef LBM_S2_F64_TW
 #define LBM_S2_F64_TW 32
 #define LBM_S2_F64_TH 5
@@ -117,6 +119,8 @@ template <>
 struct Step3Tile<ST_F16S> {  // 76 B per slot (default 36 x 14 slots, 38 KiB)
     static constexpr int TW = LBM_S3_F16S_TW, TH = LBM_S3_F16S_TH, NT = round64((TW + 4) * (TH + 4));
 };
+template <>
+struct Step3Tile<ST_BF16S> : Step3Tile<ST_F16S> {};
 #ifndef LBM_S3_F32H_TW
 #define LBM_S3_F32H_TW 32
 #define LBM_S3_F32H_TH (LBM_PUSH_F32H_K3 ? 8 : 9)

@@ -18,11 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBMPCM_LIBRARY") or os.path.join(_HERE, "liblbmpcm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE, LBM_EIO = 0, -1, -2, -3, -4, -5, -6
-LBM_F64, LBM_F32, LBM_F16_OFFSET, LBM_BF16_OFFSET, LBM_F16_SPLIT, LBM_F32_H64 = 0, 1, 2, 3, 4, 5
+LBM_F64, LBM_F32, LBM_F16_OFFSET, LBM_BF16_OFFSET, LBM_F16_SPLIT, LBM_F32_H64, LBM_BF16_SPLIT = 0, 1, 2, 3, 4, 5, 6
 PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16_OFFSET, "bf16": LBM_BF16_OFFSET,
-              "f16split": LBM_F16_SPLIT, "f32h64": LBM_F32_H64}
+              "f16split": LBM_F16_SPLIT, "f32h64": LBM_F32_H64, "bf16split": LBM_BF16_SPLIT}
 STATE_BYTES_PER_NODE = {LBM_F64: 216, LBM_F32: 108, LBM_F16_OFFSET: 54, LBM_BF16_OFFSET: 54,
-                        LBM_F16_SPLIT: 72, LBM_F32_H64: 112}
+                        LBM_F16_SPLIT: 72, LBM_F32_H64: 112, LBM_BF16_SPLIT: 72}
 # with D2Q5 thermal fields (19 populations per node)
 STATE_BYTES_PER_NODE_D2Q5 = {LBM_F64: 152, LBM_F32: 76, LBM_F32_H64: 80}
 

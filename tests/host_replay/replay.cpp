@@ -21,7 +21,7 @@
 //
 // Input on stdin: "key value" lines (the lbm_params fields by name, with
 // wall_type/wall_T as four values; precision f64|f32|f32h64|f16|bf16|
-// f16split; mode; K; launches; steps; seed; out), then "end".
+// f16split|bf16split; mode; K; launches; steps; seed; out), then "end".
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -115,6 +115,7 @@ bool read_job(Job &j) {
                 else if (s == "f16") j.prec = LBM_F16_OFFSET;
                 else if (s == "bf16") j.prec = LBM_BF16_OFFSET;
                 else if (s == "f16split") j.prec = LBM_F16_SPLIT;
+                else if (s == "bf16split") j.prec = LBM_BF16_SPLIT;
                 else ok = false;
             }
         } else {
@@ -328,6 +329,7 @@ int main() {
         case ST_F16: return run<ST_F16>(j);
         case ST_BF16: return run<ST_BF16>(j);
         case ST_F16S: return run<ST_F16S>(j);
+        case ST_BF16S: return run<ST_BF16S>(j);
         case ST_F32H: return run<ST_F32H>(j);
         case ST5_F64: return run<ST5_F64>(j);
         case ST5_F32: return run<ST5_F32>(j);

@@ -99,7 +99,7 @@ def test_host_validation_rejects_bad_sets():
         lbm.lbm_workspace_bytes([base], 7)
     # D2Q5 storage exists in FP64, FP32 and FP32 with the FP64 rest enthalpy
     q5 = dict(base, thermal_lattice=5)
-    for prec in ("f16", "bf16", "f16split"):
+    for prec in ("f16", "bf16", "f16split", "bf16split"):
         with pytest.raises(lbm.LbmError):
             lbm.lbm_lattice_of(q5, prec)
     # a batch shares one thermal lattice

@@ -103,7 +103,7 @@ def test_fullsize_c2_sampled_windows(lbm):
         assert max(e.values()) < 1e-4, e
 
 
-@pytest.mark.parametrize("precision", ["f16split", "f16", "bf16"])
+@pytest.mark.parametrize("precision", ["f16split", "bf16split", "f16", "bf16"])
 def test_fullsize_c4_16bit_sampled_windows(lbm, precision):
     # 4096^2, the 16-bit forms in the benchmark's launch.  The split form is
     # held to the bars of its full-length test; the fixed-offset forms are
@@ -113,11 +113,18 @@ def test_fullsize_c4_16bit_sampled_windows(lbm, precision):
     errs = sampled_windows(lbm, p, seed, precision, 8)
     worst = {k: max(e[k] for e in errs) for k in errs[0]}
     print(precision, worst)
+    # measured (8 steps): T 3.4e-6 (split FP16), 1.8e-5 (split BF16),
+    # 5.4e-4 (FP16 offsets), 6.9e-3 (BF16 offsets)
     if precision == "f16split":
-        assert worst["T_pcm"] < 1e-4 and worst["T_mf"] < 1e-4 and worst["f_l"] < 1e-3, worst
-        assert worst["ux"] < 5e-3 and worst["uy"] < 5e-3, worst
+        assert worst["T_pcm"] < 1e-5 and worst["T_mf"] < 5e-5 and worst["f_l"] < 2e-5, worst
+        assert worst["ux"] < 3e-4 and worst["uy"] < 3e-4, worst
+    elif precision == "bf16split":
+        assert worst["T_pcm"] < 5e-5 and worst["T_mf"] < 4e-4 and worst["f_l"] < 2e-4, worst
+        assert worst["ux"] < 1e-3 and worst["uy"] < 1.5e-3, worst
+    elif precision == "f16":
+        assert worst["T_pcm"] < 1.5e-3 and worst["T_mf"] < 2e-4, worst
     else:
-        assert worst["T_pcm"] < 0.05 and worst["T_mf"] < 0.05, worst
+        assert worst["T_pcm"] < 1.5e-2 and worst["T_mf"] < 2e-3, worst
 
 
 def test_fullsize_c5_bench_launch(lbm):
@@ -181,16 +188,18 @@ def test_fp32_c2_ab_full_length(lbm, precision):
     for k in ("T_pcm", "T_mf", "ux", "uy", "rho"):
         assert e[k] < 1e-4, (k, e)
     if precision == "f32h64":
+        # the form the FP32 configurations are timed in: every field < 1e-4
         assert e["f_l"] < 1e-4, e
     else:
-        # Pure FP32 storage rounds the rest enthalpy population (which
-        # carries H ~ 1) every step; the front integrates that error, so f_l
-        # on the few front nodes drifts to ~2-5e-4 by the end of the run while
-        # every other field, the liquid fraction and the front stay < 1e-4.
-        assert e["f_l"] < 1e-3, e
+        # Plain FP32 storage (not the timed form) rounds the rest enthalpy
+        # population (which carries H ~ 1) every step; the front integrates
+        # that error, so f_l on the few front nodes drifts to 2.2e-4 by the
+        # end of the run while every other field, the liquid fraction and
+        # the front stay < 1e-4.  Pinned as measured.
+        assert e["f_l"] < 3e-4, e
 
 
-@pytest.mark.parametrize("precision", ["f16split", "f16", "bf16"])
+@pytest.mark.parametrize("precision", ["f16split", "bf16split", "f16", "bf16"])
 def test_16bit_storage_error_vs_fp64(lbm, precision):
     p = W.scaled_cavity(W.case_c4()[0], 256)
     steps = 3000
@@ -201,18 +210,39 @@ def test_16bit_storage_error_vs_fp64(lbm, precision):
            "Nu_hot": abs(gd["Nu_hot"] - rd["Nu_hot"]) / abs(rd["Nu_hot"])}
     print(precision, "fields", e, "diag", err, "fl", gd["liquid_fraction"], rd["liquid_fraction"])
     assert gd["nonfinite"] == 0
+    u = max(e["ux"], e["uy"])
     if precision == "f16split":
         # FP32 rest populations and bases carry the conserved content; the
-        # FP16 remainders are small, so the fields stay FP32-like
-        assert e["T_pcm"] < 1e-4 and e["T_mf"] < 1e-4 and e["f_l"] < 1e-3, e
-        assert err["liquid_fraction"] < 1e-4 and err["Nu_hot"] < 1e-3, err
-        assert e["ux"] < 5e-3 and e["uy"] < 5e-3, e
+        # FP16 remainders are small, so the fields stay FP32-like (measured:
+        # T 1.6e-5, f_l 8.4e-5, u 7.2e-4, liquid fraction 3.5e-6, Nu 1.3e-4)
+        assert e["T_pcm"] < 5e-5 and e["T_mf"] < 6e-5 and e["f_l"] < 2e-4, e
+        assert err["liquid_fraction"] < 1e-5 and err["x_front_mid"] < 1e-5 and err["Nu_hot"] < 3e-4, err
+        assert u < 2e-3, e
+    elif precision == "bf16split":
+        # the same layout with bfloat16 remainders: eight bits of mantissa
+        # (measured: T 4.5e-4, f_l 1.6e-3, u 9.6e-3, liquid fraction 2.4e-5,
+        # front 2.1e-5, Nu 1.4e-4)
+        assert e["T_pcm"] < 1e-3 and e["T_mf"] < 6e-4 and e["f_l"] < 4e-3, e
+        assert err["liquid_fraction"] < 6e-5 and err["x_front_mid"] < 6e-5 and err["Nu_hot"] < 4e-4, err
+        assert u < 2.5e-2, e
+    elif precision == "f16":
+        # Fixed-reference offsets: the enthalpy offsets are O(1), so each
+        # step rounds them at ~5e-4 relative, above the per-step change; the
+        # run stays finite but drifts.  Characterised, within a factor of
+        # about two of the measured errors (T 0.167 of dT, f_l 0.50,
+        # liquid fraction 0.0151 of 0.0632, front 0.0095, Nu 0.43): the form
+        # fails the run, and a change in how it fails is caught.
+        assert 0.08 < e["T_pcm"] < 0.3 and e["f_l"] > 0.25, e
+        assert 0.007 < err["liquid_fraction"] < 0.03 and 0.004 < err["x_front_mid"] < 0.02, err
+        assert 0.2 < err["Nu_hot"] < 0.9, err
     else:
-        # Fixed-reference 16-bit offsets: the enthalpy populations are O(1)
-        # offsets, so each step rounds them at ~1e-3 (FP16) or ~8e-3 (BF16),
-        # far above the per-step physical change; the run stays finite but
-        # drifts.  Characterised, not parity: the errors are reported.
-        assert e["T_pcm"] < 1.0 and 0 <= gd["liquid_fraction"] <= 1
+        # bfloat16 offsets (~4e-3 relative): measured T 0.74, f_l 1.0,
+        # liquid fraction 0.046, front 0.041, Nu 1.9
+        assert 0.4 < e["T_pcm"] < 1.0 and e["f_l"] > 0.5, e
+        assert 0.025 < err["liquid_fraction"] < 0.063 and 0.02 < err["x_front_mid"] < 0.08, err
+        assert 1.0 < err["Nu_hot"] < 4.0, err
+
+
 def test_batched_cavities_bitwise(lbm):
     ps, _, _, _ = W.case_c5()
     pick = sorted(range(len(ps)), key=lambda c: ps[c]["nx"] * ps[c]["ny"])[:5] + [0]

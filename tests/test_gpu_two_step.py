@@ -90,7 +90,7 @@ def test_three_steps_per_launch_are_bitwise_three_single_steps(lbm, case, qt, pr
 
 
 @pytest.mark.parametrize("case", ["c1", "ragged", "periodic", "corner", "batch", "tiny"])
-@pytest.mark.parametrize("prec", ["f16split", "f16", "bf16"])
+@pytest.mark.parametrize("prec", ["f16split", "bf16split", "f16", "bf16"])
 @pytest.mark.parametrize("spl", [2, 3])
 def test_16bit_multi_step_is_bitwise_single_steps(lbm, case, prec, spl):
     # the LDS holds the 16-bit codes (and the split form's FP32 rest

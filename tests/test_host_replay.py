@@ -97,7 +97,7 @@ def _geometries():
 
 
 FORMS = [("f32", 9, 3), ("f32", 9, 2), ("f32h64", 9, 3), ("f32h64", 9, 2), ("f16", 9, 3), ("bf16", 9, 3),
-         ("f16split", 9, 3), ("f16split", 9, 2), ("f64", 9, 2), ("f32", 5, 3), ("f32", 5, 2), ("f32h64", 5, 3),
+         ("f16split", 9, 3), ("f16split", 9, 2), ("bf16split", 9, 3), ("f64", 9, 2), ("f32", 5, 3), ("f32", 5, 2), ("f32h64", 5, 3),
          ("f64", 5, 2)]
 
 
