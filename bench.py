@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=0, choices=[0, 1, 2, 3],
                     help="0: the library's default (several steps per launch through LDS where available)")
+    ap.add_argument("--tile-shape", type=int, default=None, choices=[0, 1, 2],
+                    help="tile shape of the multi-step kernel (0 default, 1 wide, 2 tall)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--forms", action="store_true", help="also time the 16-bit and batched forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -339,7 +341,7 @@ def main():
         launch = lbm.lbm_autotune(s.h, 5, os.path.join(tempfile.gettempdir(), "lbmpcm_autotune_cache.txt"))
     else:
         lbm.lbm_set_launch(s.h, args.block, args.npt, args.xcd, args.persistent,
-                           steps_per_launch=args.steps_per_launch or None)
+                           steps_per_launch=args.steps_per_launch or None, tile_shape=args.tile_shape)
         launch = lbm.lbm_get_launch(s.h)
     nodes = sum(p["nx"] * p["ny"] for p in params)
     ms = time_steps(lbm, torch, s, stream, args.steps, args.warmup)
@@ -387,7 +389,7 @@ def main():
     if spl > 1:
         # the one-step kernel on the same state, for reference
         lbm.lbm_set_launch(s.h, launch["block"], launch["nodes_per_thread"], launch["xcd_remap"],
-                           launch["persistent"], steps_per_launch=1)
+                           launch["persistent"], steps_per_launch=1, tile_shape=0)
         t1 = time_steps(lbm, torch, s, stream, 100, 10) / 100
         single = {"MLUPS": nodes / (t1 * 1e-3) / 1e6, "ms_per_step": t1,
                   "achieved_GBps": alg / (t1 * 1e-3) / 1e9,
@@ -474,8 +476,11 @@ def main():
         n2 = sum(q["nx"] * q["ny"] for q in ps)
         t1 = time_steps(lbm, torch, s2, stream, 200, 10) / 200
         t2 = time_steps(lbm, torch, s2, stream, 20, 2, looped=True) / 20
+        tuned = lbm.lbm_autotune(s2.h, 3, None)
+        t3 = time_steps(lbm, torch, s2, stream, 198, 12) / 198
         forms["c5_batched_f32"] = {"MLUPS": n2 / (t1 * 1e-3) / 1e6, "ms_per_step": t1,
-                                   "looped_single_cavity_MLUPS": n2 / (t2 * 1e-3) / 1e6}
+                                   "looped_single_cavity_MLUPS": n2 / (t2 * 1e-3) / 1e6,
+                                   "autotuned_MLUPS": n2 / (t3 * 1e-3) / 1e6, "autotuned_launch": tuned}
         s2.close()
         del ws2
         torch.cuda.empty_cache()

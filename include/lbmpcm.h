@@ -196,6 +196,14 @@ typedef struct lbm_launch_config {
                                  LDS; every form but LBM_F64).  Default: the
                                  most the form has.
                                  block and nodes_per_thread then do not apply. */
+    int32_t tile_shape;       /* tile shape of the multi-step kernel: 0 the
+                                 default; 1 about twice as wide and half as
+                                 tall; 2 about half as wide and twice as tall
+                                 (multi-step launches without a persistent
+                                 grid).  Every shape gives the same bits.     */
+    int32_t tile_w, tile_h;   /* reported by lbm_get_launch and lbm_autotune:
+                                 the tile of the multi-step kernel (0 with
+                                 one step per launch); ignored on input       */
 } lbm_launch_config;
 
 /* Create a single-cavity solver.  Maps the groups to lattice units (Eq. 54,
@@ -303,11 +311,13 @@ lbm_status lbm_lattice_of(const lbm_params *p, lbm_precision prec, lbm_lattice *
 lbm_status lbm_get_launch(const lbm_handle *h, lbm_launch_config *out);
 lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg);
 
-/* Time every supported launch shape for steps_per_trial steps on the live
- * state (reads the current buffer, writes only scratch), keep the fastest,
- * and report it in *chosen (may be NULL).  With a non-NULL cache_path the
- * choice is looked up in / appended to that text file, keyed by device,
- * precision and cavity sizes.  Synchronises the stream. */
+/* Time every supported launch shape (one-step launch shapes; two and three
+ * steps per launch in every tile shape) for steps_per_trial launches on
+ * the live state (reads the current buffer, writes only scratch), keep the
+ * fastest, and report it in *chosen (may be NULL).  With a non-NULL
+ * cache_path the choice is looked up in / appended to that text file, keyed
+ * by device, precision, number of cavities, total nodes and the first
+ * cavity's sizes.  Synchronises the stream. */
 lbm_status lbm_autotune(lbm_handle *h, int32_t steps_per_trial, const char *cache_path,
                         lbm_launch_config *chosen);
 

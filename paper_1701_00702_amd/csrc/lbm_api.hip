@@ -104,7 +104,8 @@ struct Plan {
     // nodes: packed index range of the flat per-node arrays (stride each)
     int64_t nodes = 0, stride = 0, slots = 0, max_nodes = 0;
     int max_tiles = 0;
-    // tiles of the K-step kernels, K = 2, 3 (0: not available for this storage)
+    // tiles of the K-step kernels, K = 2, 3: room for the largest count over
+    // the tile shapes (0: not available for this storage)
     int64_t tilesk[4] = {0, 0, 0, 0};
     size_t off_tilesk[4] = {0, 0, 0, 0};
     size_t off_pop[2], off_sr[2], off_acc, off_accs, off_cav, off_tiles, off_fields, off_part,
@@ -173,9 +174,13 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     off = align256(off + (size_t)pl.max_tiles * sizeof(Tile));
     for (int k = 2; k <= 3; ++k) {
         if (!stepk_supported(st, k)) continue;
-        int tw, th;
-        stepk_tile(st, k, &tw, &th);
-        for (int c = 0; c < n; ++c) pl.tilesk[k] += count_tiles2(p[c].nx, p[c].ny, tw, th);
+        for (int shape = 0; shape < LBM_TILE_SHAPES; ++shape) {
+            int tw, th;
+            stepk_tile(st, k, shape, &tw, &th);
+            int64_t count = 0;
+            for (int c = 0; c < n; ++c) count += count_tiles2(p[c].nx, p[c].ny, tw, th);
+            pl.tilesk[k] = std::max(pl.tilesk[k], count);
+        }
         if (pl.tilesk[k] >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "too many tiles");
         pl.off_tilesk[k] = off;
         off = align256(off + (size_t)pl.tilesk[k] * sizeof(Tile2));
@@ -212,7 +217,9 @@ struct lbm_handle {
     int cur = 0;
     int64_t step = 0;
     std::vector<double> E0, M0;
-    lbm_launch_config lc{512, 1, 1, 0, 1};
+    lbm_launch_config lc{512, 1, 1, 0, 1, 0, 0, 0};
+    int ntk[4] = {0, 0, 0, 0};     // tiles in the K-step tables (K = 2, 3)
+    int shapek[4] = {0, 0, 0, 0};  // tile shape the K-step tables were built for
     std::vector<Tile> tiles;             // host copy, sorted by cavity: interior, then ring
     std::vector<int> cav_tile0, cav_ntiles;
     int graph_chunk = 32;  // launches per captured graph
@@ -250,18 +257,32 @@ void drop_graphs(lbm_handle *h) {
     }
 }
 
-// Tile tables of the K-step kernels (fixed per storage form).
-lbm_status build_tilesk(lbm_handle *h) {
+// Tile table of the K-step kernel in tile shape `shape`.
+lbm_status build_tilesk(lbm_handle *h, int k, int shape) {
+    if (!h->pl.tilesk[k]) return LBM_OK;
+    int tw, th;
+    stepk_tile(h->st, k, shape, &tw, &th);
+    if (!tw) return fail(LBM_EINVAL, "no tile shape %d for %d steps per launch", shape, k);
+    std::vector<Tile2> t;
+    for (int c = 0; c < h->n; ++c) cavity_tiles2(c, h->params[c].nx, h->params[c].ny, tw, th, t);
+    if ((int64_t)t.size() > h->pl.tilesk[k]) return fail(LBM_EINVAL, "K-step tile table overflow");
+    HIP_TRY(hipMemcpyAsync(h->dtilesk(k), t.data(), t.size() * sizeof(Tile2), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->ntk[k] = (int)t.size();
+    h->shapek[k] = shape;
+    return LBM_OK;
+}
+
+// The K-step tables a launch shape needs: its own K in its tile shape, and
+// with three steps per launch the two-step table (default shape) for a
+// remainder of two steps.
+lbm_status tables_for(lbm_handle *h, const lbm_launch_config &lc) {
     for (int k = 2; k <= 3; ++k) {
-        if (!h->pl.tilesk[k]) continue;
-        int tw, th;
-        stepk_tile(h->st, k, &tw, &th);
-        std::vector<Tile2> t;
-        for (int c = 0; c < h->n; ++c) cavity_tiles2(c, h->params[c].nx, h->params[c].ny, tw, th, t);
-        if ((int64_t)t.size() != h->pl.tilesk[k]) return fail(LBM_EINVAL, "K-step tile table mismatch");
-        HIP_TRY(hipMemcpyAsync(h->dtilesk(k), t.data(), t.size() * sizeof(Tile2), hipMemcpyHostToDevice,
-                               h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
+        const int shape = lc.steps_per_launch == k ? lc.tile_shape : 0;
+        if (h->pl.tilesk[k] && (h->ntk[k] == 0 || h->shapek[k] != shape)) {
+            lbm_status s = build_tilesk(h, k, shape);
+            if (s != LBM_OK) return s;
+        }
     }
     return LBM_OK;
 }
@@ -300,14 +321,28 @@ bool valid_launch(const lbm_launch_config &lc, const Plan &pl) {
     const bool b = lc.block == 64 || lc.block == 128 || lc.block == 256 || lc.block == 512;
     const bool n = lc.nodes_per_thread == 1 || lc.nodes_per_thread == 2 || lc.nodes_per_thread == 4;
     const bool t = has_k(pl, lc.steps_per_launch);
-    return b && n && t && (lc.xcd_remap == 0 || lc.xcd_remap == 1) && lc.persistent >= 0 && lc.persistent <= 64;
+    // alternative tile shapes: multi-step launches without a persistent grid
+    const bool sh = lc.tile_shape == 0 ||
+                    (lc.tile_shape > 0 && lc.tile_shape < LBM_TILE_SHAPES && lc.steps_per_launch > 1 &&
+                     lc.persistent == 0);
+    return b && n && t && sh && (lc.xcd_remap == 0 || lc.xcd_remap == 1) && lc.persistent >= 0 &&
+           lc.persistent <= 64;
+}
+
+// The launch shape as reported: the tile dimensions of the multi-step
+// kernel filled in.
+lbm_launch_config reported(const lbm_handle *h, lbm_launch_config lc) {
+    lc.tile_w = lc.tile_h = 0;
+    if (lc.steps_per_launch > 1) stepk_tile(h->st, lc.steps_per_launch, lc.tile_shape, &lc.tile_w, &lc.tile_h);
+    return lc;
 }
 
 Step2Launch stepk_args(lbm_handle *h, int k, int src_buf, double *acc, const lbm_launch_config &lc) {
     Step2Launch L;
     L.storage = h->st;
     L.steps = k;
-    const int nt = (int)h->pl.tilesk[k];
+    L.shape = h->shapek[k];
+    const int nt = h->ntk[k];
     L.grid = lc.persistent > 0 ? std::min(nt, h->n_cu * lc.persistent) : nt;
     L.xcd_remap = lc.xcd_remap;
     L.src = h->pop(src_buf);
@@ -503,7 +538,7 @@ lbm_status setup(lbm_handle *h) {
     h->lc.steps_per_launch = h->pl.tilesk[3] > 0 ? 3 : (h->pl.tilesk[2] > 0 ? 2 : 1);
     lbm_status s = build_tiles(h, h->lc);
     if (s != LBM_OK) return s;
-    s = build_tilesk(h);
+    s = tables_for(h, h->lc);
     if (s != LBM_OK) return s;
     h->E0.assign(h->n, 0.0);
     h->M0.assign(h->n, 0.0);
@@ -859,19 +894,23 @@ extern "C" lbm_status lbm_lattice_of(const lbm_params *p, lbm_precision prec, lb
 
 extern "C" lbm_status lbm_get_launch(const lbm_handle *h, lbm_launch_config *out) {
     if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
-    *out = h->lc;
+    *out = reported(h, h->lc);
     return LBM_OK;
 }
 
 extern "C" lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg) {
     if (!h || !cfg) return fail(LBM_EINVAL, "NULL argument");
     if (!valid_launch(*cfg, h->pl))
-        return fail(LBM_EINVAL, "unsupported launch shape block=%d npt=%d xcd=%d persistent=%d steps=%d",
-                    cfg->block, cfg->nodes_per_thread, cfg->xcd_remap, cfg->persistent, cfg->steps_per_launch);
+        return fail(LBM_EINVAL,
+                    "unsupported launch shape block=%d npt=%d xcd=%d persistent=%d steps=%d tile_shape=%d",
+                    cfg->block, cfg->nodes_per_thread, cfg->xcd_remap, cfg->persistent, cfg->steps_per_launch,
+                    cfg->tile_shape);
     HIP_TRY(hipStreamSynchronize(h->stream));
     lbm_status s = build_tiles(h, *cfg);
     if (s != LBM_OK) return s;
-    h->lc = *cfg;
+    s = tables_for(h, *cfg);
+    if (s != LBM_OK) return s;
+    h->lc = reported(h, *cfg);
     drop_graphs(h);
     return prepare_graphs(h);
 }
@@ -900,12 +939,13 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
         if (f) {
             char k[256];
             lbm_launch_config lc;
-            while (fscanf(f, "%255s %d %d %d %d %d", k, &lc.block, &lc.nodes_per_thread, &lc.xcd_remap,
-                          &lc.persistent, &lc.steps_per_launch) == 6) {
+            std::memset(&lc, 0, sizeof(lc));
+            while (fscanf(f, "%255s %d %d %d %d %d %d", k, &lc.block, &lc.nodes_per_thread, &lc.xcd_remap,
+                          &lc.persistent, &lc.steps_per_launch, &lc.tile_shape) == 7) {
                 if (key == k && valid_launch(lc, h->pl)) {
                     fclose(f);
                     lbm_status s = lbm_set_launch(h, &lc);
-                    if (s == LBM_OK && chosen) *chosen = lc;
+                    if (s == LBM_OK && chosen) *chosen = h->lc;
                     return s;
                 }
             }
@@ -926,6 +966,8 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
     // scratch tallies; times are per step.
     auto trial = [&](const lbm_launch_config &lc, float *ms_per_step) -> lbm_status {
         if (lc.steps_per_launch > 1) {
+            lbm_status s = tables_for(h, lc);
+            if (s != LBM_OK) return s;
             Step2Launch L = stepk_args(h, lc.steps_per_launch, h->cur, h->acc_scratch(), lc);
             HIP_TRY(launch_stepk(L, h->stream));
             HIP_TRY(hipEventRecord(e0, h->stream));
@@ -945,47 +987,58 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
         *ms_per_step = ms / (float)(steps * lc.steps_per_launch);
         return LBM_OK;
     };
+    // On a failed trial the handle goes back to the shape it had.
+    auto abandon = [&](lbm_status s) -> lbm_status {
+        const std::string msg = g_err;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)lbm_set_launch(h, &saved);
+        return fail(s, "%s", msg.c_str());
+    };
     for (int b : blocks)
         for (int np : npts)
             for (int xr : xcds)
                 for (int pp : pers) {
-                    lbm_launch_config lc{b, np, xr, pp, 1};
+                    lbm_launch_config lc{b, np, xr, pp, 1, 0, 0, 0};
                     float ms;
                     lbm_status s = trial(lc, &ms);
-                    if (s != LBM_OK) return s;
+                    if (s != LBM_OK) return abandon(s);
                     if (ms < best_ms) {
                         best_ms = ms;
                         best = lc;
                     }
                 }
+    // multi-step launches: every tile shape, XCD remap on and off, and the
+    // persistent grid for the default shape
     const lbm_launch_config one = best;
     for (int kk = 2; kk <= 3; ++kk) {
         if (!has_k(h->pl, kk)) continue;
-        for (int xr : xcds)
-            for (int pp : pers) {
-                lbm_launch_config lc{one.block, one.nodes_per_thread, xr, pp, kk};
-                float ms;
-                lbm_status s = trial(lc, &ms);
-                if (s != LBM_OK) return s;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = lc;
+        for (int shape = 0; shape < LBM_TILE_SHAPES; ++shape)
+            for (int xr : xcds)
+                for (int pp : pers) {
+                    if (shape != 0 && pp != 0) continue;
+                    lbm_launch_config lc{one.block, one.nodes_per_thread, xr, pp, kk, shape, 0, 0};
+                    float ms;
+                    lbm_status s = trial(lc, &ms);
+                    if (s != LBM_OK) return abandon(s);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = lc;
+                    }
                 }
-            }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)saved;
     // The trials wrote the inactive buffer; when the live state is the raw
     // initial state the inactive buffer is not part of the state either.
     lbm_status s = lbm_set_launch(h, &best);
     if (s != LBM_OK) return s;
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = h->lc;
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), best.block, best.nodes_per_thread, best.xcd_remap,
-                    best.persistent, best.steps_per_launch);
+            fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), best.block, best.nodes_per_thread, best.xcd_remap,
+                    best.persistent, best.steps_per_launch, best.tile_shape);
             fclose(f);
         }
     }

@@ -265,60 +265,77 @@ __global__ __launch_bounds__(NT, WPE) void stepk_kernel(const void *__restrict__
     }
 }
 
-template <int ST, int K>
-static hipError_t launch_stepk_s(const Step2Launch &L, hipStream_t s) {
+template <int ST, int K, int I>
+static hipError_t launch_stepk_i(const Step2Launch &L, hipStream_t s) {
     using Lay = typename LayoutOf<ST>::L;
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
-    using Tl = StepKTile<ST, K>;
-    if (L.grid >= L.ntiles)
+    using Tl = StepKTileI<ST, K, I>;
+    if (L.grid >= L.ntiles) {
         hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, false,
                                          stepk_wpe<ST, Lay, R, Tl::TW, Tl::TH, Tl::NT, K>()>),
                            dim3(L.grid), dim3(Tl::NT),
                            0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
                            (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
-    else
-        hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, true, 1>), dim3(L.grid), dim3(Tl::NT),
-                           0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
-                           (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
+    } else {
+        // persistent grids exist for the default shape only
+        if constexpr (I == 0)
+            hipLaunchKernelGGL((stepk_kernel<Lay, R, RH, Tl::TW, Tl::TH, Tl::NT, K, true, 1>), dim3(L.grid),
+                               dim3(Tl::NT), 0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
+                               (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
+        else
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
+}
+
+template <int ST, int K>
+static hipError_t launch_stepk_s(const Step2Launch &L, hipStream_t s) {
+    switch (L.shape) {
+        case 0: return launch_stepk_i<ST, K, 0>(L, s);
+        case 1: return launch_stepk_i<ST, K, 1>(L, s);
+        case 2: return launch_stepk_i<ST, K, 2>(L, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 bool stepk_supported(int storage, int k) { return stepk_available(storage, k); }
 
 template <int ST, int K>
-static void tile_of(int *tw, int *th) {
-    *tw = StepKTile<ST, K>::TW;
-    *th = StepKTile<ST, K>::TH;
+static void tile_of(int shape, int *tw, int *th) {
+    const TileDims d = dims_of<ST, K>(shape);
+    *tw = d.tw;
+    *th = d.th;
 }
 
-void stepk_tile(int storage, int k, int *tw, int *th) {
+void stepk_tile(int storage, int k, int shape, int *tw, int *th) {
     *tw = *th = 0;
+    if (shape < 0 || shape >= kTileShapes) return;
     if (k == 3) {
         switch (storage) {
-            case ST_F32: return tile_of<ST_F32, 3>(tw, th);
-            case ST5_F32: return tile_of<ST5_F32, 3>(tw, th);
-            case ST_F32H: return tile_of<ST_F32H, 3>(tw, th);
-            case ST5_F32H: return tile_of<ST5_F32H, 3>(tw, th);
-            case ST_F16: return tile_of<ST_F16, 3>(tw, th);
-            case ST_BF16: return tile_of<ST_BF16, 3>(tw, th);
-            case ST_F16S: return tile_of<ST_F16S, 3>(tw, th);
-            case ST_BF16S: return tile_of<ST_BF16S, 3>(tw, th);
+            case ST_F32: return tile_of<ST_F32, 3>(shape, tw, th);
+            case ST5_F32: return tile_of<ST5_F32, 3>(shape, tw, th);
+            case ST_F32H: return tile_of<ST_F32H, 3>(shape, tw, th);
+            case ST5_F32H: return tile_of<ST5_F32H, 3>(shape, tw, th);
+            case ST_F16: return tile_of<ST_F16, 3>(shape, tw, th);
+            case ST_BF16: return tile_of<ST_BF16, 3>(shape, tw, th);
+            case ST_F16S: return tile_of<ST_F16S, 3>(shape, tw, th);
+            case ST_BF16S: return tile_of<ST_BF16S, 3>(shape, tw, th);
             default: return;
         }
     }
     if (k != 2) return;
     switch (storage) {
-        case ST_F16: return tile_of<ST_F16, 2>(tw, th);
-        case ST_BF16: return tile_of<ST_BF16, 2>(tw, th);
-        case ST_F16S: return tile_of<ST_F16S, 2>(tw, th);
-        case ST_BF16S: return tile_of<ST_BF16S, 2>(tw, th);
-        case ST_F32: return tile_of<ST_F32, 2>(tw, th);
-        case ST5_F32: return tile_of<ST5_F32, 2>(tw, th);
-        case ST_F64: return tile_of<ST_F64, 2>(tw, th);
-        case ST5_F64: return tile_of<ST5_F64, 2>(tw, th);
-        case ST_F32H: return tile_of<ST_F32H, 2>(tw, th);
-        case ST5_F32H: return tile_of<ST5_F32H, 2>(tw, th);
+        case ST_F16: return tile_of<ST_F16, 2>(shape, tw, th);
+        case ST_BF16: return tile_of<ST_BF16, 2>(shape, tw, th);
+        case ST_F16S: return tile_of<ST_F16S, 2>(shape, tw, th);
+        case ST_BF16S: return tile_of<ST_BF16S, 2>(shape, tw, th);
+        case ST_F32: return tile_of<ST_F32, 2>(shape, tw, th);
+        case ST5_F32: return tile_of<ST5_F32, 2>(shape, tw, th);
+        case ST_F64: return tile_of<ST_F64, 2>(shape, tw, th);
+        case ST5_F64: return tile_of<ST5_F64, 2>(shape, tw, th);
+        case ST_F32H: return tile_of<ST_F32H, 2>(shape, tw, th);
+        case ST5_F32H: return tile_of<ST5_F32H, 2>(shape, tw, th);
         default: return;
     }
 }

@@ -291,6 +291,19 @@ struct PlainH64 {
 // conserved content (rest population, base) keeps FP32 precision.
 // Planes: 6 FP32 planes [q_f0, beta_f, q_g0, beta_g, q_h0, beta_h], then 24
 // 16-bit planes [field][direction 1..8]; 72 bytes per node.
+// The split codec's arithmetic, shared by the global layout and its LDS
+// copy: a population is w_i beta + r / s (r the 16-bit remainder, s the
+// field's power-of-two scale), decoded with one fused multiply-add, and
+// encoded as the remainder q s - (w_i s) beta, one fused multiply-add.
+template <typename V>
+LBM_HD V split_dec(int i, V beta, V r, V inv_scale) {
+    return fma_of(r, inv_scale, w_of<V>(i) * beta);
+}
+template <typename V>
+LBM_HD float split_rem(int i, V q, V beta, V scale) {
+    return (float)fma_of(q, scale, -(w_of<V>(i) * scale) * beta);
+}
+
 template <class ER>
 struct SplitT {
     static constexpr int QT = 9;
@@ -302,7 +315,7 @@ struct SplitT {
         const V beta = (V)ld_stream(at(P + (int64_t)(2 * f + 1) * stride, k));
         const uint16_t *Qp = (const uint16_t *)(P + 6 * stride);
         const V r = (V)ER::dec(ld_stream(at(Qp + (int64_t)(8 * f + i - 1) * stride, k)));
-        return w_of<V>(i) * beta + r * (V)c.inv_scale[f];
+        return split_dec<V>(i, beta, r, (V)c.inv_scale[f]);
     }
     template <typename V, typename R, typename K>
     LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, K k,
@@ -314,7 +327,7 @@ struct SplitT {
         uint16_t *Qp = (uint16_t *)(P + 6 * stride);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const uint16_t e = ER::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f]));
+            const uint16_t e = ER::enc(split_rem<V>(i, q[i], beta, (V)c.scale[f]));
             st_stream(at_store(Qp, 8 * f + i - 1, stride, k, e), e);
         }
     }
@@ -841,6 +854,9 @@ struct BandOrigin {
         return y < y_next ? NodeRef{(uint32_t)((y - y_first) * pitch + x), 0u}
                           : NodeRef{(uint32_t)((y - y_next) * pitch + x), band_bytes};
     }
+    // row y resolved to its band once; node x of it by at_row
+    LBM_HD NodeRef row(int y) const { return (*this)(0, y); }
+    LBM_HD static NodeRef at_row(NodeRef r, int x) { return NodeRef{r.rel + (uint32_t)x, r.jump}; }
 };
 struct AnyBand {
     int band_rows, pitch;
@@ -849,6 +865,8 @@ struct AnyBand {
         const int b = y / band_rows;
         return FarRef{(int64_t)(y - b * band_rows) * pitch + x, (int64_t)b * band_bytes};
     }
+    LBM_HD FarRef row(int y) const { return (*this)(0, y); }
+    LBM_HD static FarRef at_row(FarRef r, int x) { return FarRef{r.rel + x, r.jump}; }
 };
 template <typename R>
 LBM_HD BandOrigin band_origin(const CavityConst<R> &c, int y) {  // from the band of row y
@@ -878,6 +896,24 @@ LBM_HD void gather_at(const CavityConst<R> &c, const void *src, const NodeGeom &
                       R qf[9], RH qg[9], R qh[9]) {
     const int nx = c.nx;
     const int64_t stride = c.band_nodes;
+    if (PULL && !c.periodic) {
+        // no wrap: the three rows the pulls read are resolved to their bands
+        // once, and each pull is an offset within its row
+        const auto row_up = addr.row(g.sy + 1), row_mid = addr.row(g.sy), row_down = addr.row(g.sy - 1);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const auto k = A::at_row(ey_of(i) > 0 ? row_down : (ey_of(i) < 0 ? row_up : row_mid), g.sx - ex_of(i));
+            qf[i] = Lay::template load<R>(src, stride, 0, i, k, c);
+            if (i < Lay::QT) {
+                qg[i] = Lay::template load<RH>(src, stride, 1, i, k, c);
+                qh[i] = Lay::template load<R>(src, stride, 2, i, k, c);
+            } else {
+                qg[i] = RH(0);
+                qh[i] = R(0);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int px = x, py = y;
@@ -1157,7 +1193,7 @@ struct LdsCodec<SplitT<ER>> {
         P[(2 * f + 1) * nslot + slot] = (float)beta;
 #pragma unroll
         for (int i = 1; i < 9; ++i)
-            Qp[(8 * f + i - 1) * nslot + slot] = ER::enc((float)((q[i] - w_of<V>(i) * beta) * (V)c.scale[f]));
+            Qp[(8 * f + i - 1) * nslot + slot] = ER::enc(split_rem<V>(i, q[i], beta, (V)c.scale[f]));
     }
     template <typename R, typename RH>
     LBM_HD static void put_node(void *lds, int nslot, int slot, const CavityConst<R> &c, const R qf[9],
@@ -1173,7 +1209,7 @@ struct LdsCodec<SplitT<ER>> {
         const V beta = (V)P[(2 * f + 1) * nslot + slot];
         const uint16_t *Qp = (const uint16_t *)(P + 6 * nslot);
         const V r = (V)ER::dec(Qp[(8 * f + i - 1) * nslot + slot]);
-        return w_of<V>(i) * beta + r * (V)c.inv_scale[f];
+        return split_dec<V>(i, beta, r, (V)c.inv_scale[f]);
     }
 };
 

@@ -141,4 +141,42 @@ struct StepKTile<ST, 2> : Step2Tile<ST> {};
 template <int ST>
 struct StepKTile<ST, 3> : Step3Tile<ST> {};
 
+// Tile shapes chosen at run time (lbm_launch_config.tile_shape): 0 is the
+// default above; 1 is about twice as wide and half as tall, 2 about half as
+// wide and twice as tall, each within 64 KiB of LDS, 1024 threads and the
+// band rule (TH + 2K <= LBM_MIN_BAND_ROWS).  The autotuner times them: a
+// cavity whose width leaves a narrow last tile in one shape fits another.
+constexpr int kTileShapes = 3;
+struct TileDims {
+    int tw, th;
+};
+constexpr TileDims alt_dims(int st, int k, int i) {
+    if (k == 3) {
+        if (st == ST_F32 || st == ST_F32H) return i == 1 ? TileDims{64, 4} : TileDims{16, 16};
+        return i == 1 ? TileDims{64, 5} : TileDims{16, 20};  // D2Q5 FP32 forms, 16-bit forms
+    }
+    switch (st) {
+        case ST_F32: return i == 1 ? TileDims{64, 6} : TileDims{16, 24};
+        case ST_F32H: return i == 1 ? TileDims{64, 5} : TileDims{16, 22};
+        case ST5_F32:
+        case ST5_F32H: return i == 1 ? TileDims{32, 10} : TileDims{128, 3};
+        case ST_F64: return i == 1 ? TileDims{64, 3} : TileDims{16, 10};
+        case ST5_F64: return i == 1 ? TileDims{64, 4} : TileDims{16, 16};
+        default: return i == 1 ? TileDims{64, 6} : TileDims{16, 26};  // 16-bit forms
+    }
+}
+template <int ST, int K, int I>
+struct StepKTileI {
+    static constexpr TileDims d = alt_dims(ST, K, I);
+    static constexpr int TW = d.tw, TH = d.th, NT = round64((TW + 2 * (K - 1)) * (TH + 2 * (K - 1)));
+};
+template <int ST, int K>
+struct StepKTileI<ST, K, 0> : StepKTile<ST, K> {};
+
+// Width and height of tile shape i of the K-step kernel of storage st.
+template <int ST, int K>
+constexpr TileDims dims_of(int i) {
+    return i == 0 ? TileDims{StepKTile<ST, K>::TW, StepKTile<ST, K>::TH} : alt_dims(ST, K, i);
+}
+
 }  // namespace lbm

@@ -84,7 +84,8 @@ class lbm_diag(ctypes.Structure):
 class lbm_launch_config(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("nodes_per_thread", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("steps_per_launch", ctypes.c_int32)]
+                ("steps_per_launch", ctypes.c_int32), ("tile_shape", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
 
 
 def _load():
@@ -285,11 +286,15 @@ def lbm_get_launch(h: int) -> dict:
     return {n: int(getattr(c, n)) for n, _ in lbm_launch_config._fields_}
 
 
-def lbm_set_launch(h: int, block=256, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=None):
-    """steps_per_launch None keeps the handle's current setting."""
+def lbm_set_launch(h: int, block=256, nodes_per_thread=1, xcd_remap=1, persistent=0, steps_per_launch=None,
+                   tile_shape=None):
+    """steps_per_launch and tile_shape None keep the handle's current setting."""
+    cur = lbm_get_launch(h)
     if steps_per_launch is None:
-        steps_per_launch = lbm_get_launch(h)["steps_per_launch"]
-    c = lbm_launch_config(block, nodes_per_thread, xcd_remap, persistent, steps_per_launch)
+        steps_per_launch = cur["steps_per_launch"]
+    if tile_shape is None:
+        tile_shape = cur["tile_shape"] if steps_per_launch == cur["steps_per_launch"] else 0
+    c = lbm_launch_config(block, nodes_per_thread, xcd_remap, persistent, steps_per_launch, tile_shape, 0, 0)
     _check(_lib.lbm_set_launch(h, ctypes.byref(c)))
 
 

@@ -21,7 +21,8 @@
 //
 // Input on stdin: "key value" lines (the lbm_params fields by name, with
 // wall_type/wall_T as four values; precision f64|f32|f32h64|f16|bf16|
-// f16split|bf16split; mode; K; launches; steps; seed; out), then "end".
+// f16split|bf16split; mode; K; shape (tile shape index); launches; steps;
+// seed; out), then "end".
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -51,7 +52,7 @@ struct Job {
     lbm_params p;
     lbm_precision prec = LBM_F32;
     std::string mode = "kstep", out;
-    int K = 3, launches = 2, steps = 10;
+    int K = 3, launches = 2, steps = 10, shape = 0;
     uint64_t seed = 1;
 };
 
@@ -99,6 +100,7 @@ bool read_job(Job &j) {
         else if (k == "solid_treatment") ok = ri(p.solid_treatment);
         else if (k == "band_rows") ok = ri(p.band_rows);
         else if (k == "K") ok = scanf("%d", &j.K) == 1;
+        else if (k == "shape") ok = scanf("%d", &j.shape) == 1;
         else if (k == "launches") ok = scanf("%d", &j.launches) == 1;
         else if (k == "steps") ok = scanf("%d", &j.steps) == 1;
         else if (k == "seed") ok = scanf("%llu", (unsigned long long *)&j.seed) == 1;
@@ -162,14 +164,15 @@ void one_step_all(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, 
         }
 }
 
-// One K-step launch over every tile, each tile an emulated workgroup.
-template <int ST, int K>
+// One K-step launch over every tile, each tile an emulated workgroup (tile
+// shape I).
+template <int ST, int K, int I>
 void k_step_all(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, int cur,
                 const std::vector<Tile2> &tiles) {
     using Lay = typename LayoutOf<ST>::L;
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
-    using Tl = StepKTile<ST, K>;
+    using Tl = StepKTileI<ST, K, I>;
     constexpr int TW = Tl::TW, TH = Tl::TH, NT = Tl::NT;
     using Sh = StepKShape<Lay, TW, TH, K>;
     static_assert(NT >= Sh::NFIRST, "one thread per node of the first update");
@@ -252,16 +255,17 @@ int run(const Job &j) {
     one_step_all<ST>(c, S, 0, false);
     int cur = 1;
     int tw = 0, th = 0;
+    if (j.shape < 0 || j.shape >= kTileShapes) return 2;
     if constexpr (stepk_available(ST, 2)) {
         if (j.K == 2) {
-            tw = StepKTile<ST, 2>::TW;
-            th = StepKTile<ST, 2>::TH;
+            tw = dims_of<ST, 2>(j.shape).tw;
+            th = dims_of<ST, 2>(j.shape).th;
         }
     }
     if constexpr (stepk_available(ST, 3)) {
         if (j.K == 3) {
-            tw = StepKTile<ST, 3>::TW;
-            th = StepKTile<ST, 3>::TH;
+            tw = dims_of<ST, 3>(j.shape).tw;
+            th = dims_of<ST, 3>(j.shape).th;
         }
     }
     if (!tw) return 2;
@@ -274,10 +278,16 @@ int run(const Job &j) {
             one_step_all<ST>(c, A, ca, true);
             ca ^= 1;
         }
-        if constexpr (stepk_available(ST, 2))
-            if (j.K == 2) k_step_all<ST, 2>(c, B, cb, tiles);
-        if constexpr (stepk_available(ST, 3))
-            if (j.K == 3) k_step_all<ST, 3>(c, B, cb, tiles);
+        if constexpr (stepk_available(ST, 2)) {
+            if (j.K == 2 && j.shape == 0) k_step_all<ST, 2, 0>(c, B, cb, tiles);
+            if (j.K == 2 && j.shape == 1) k_step_all<ST, 2, 1>(c, B, cb, tiles);
+            if (j.K == 2 && j.shape == 2) k_step_all<ST, 2, 2>(c, B, cb, tiles);
+        }
+        if constexpr (stepk_available(ST, 3)) {
+            if (j.K == 3 && j.shape == 0) k_step_all<ST, 3, 0>(c, B, cb, tiles);
+            if (j.K == 3 && j.shape == 1) k_step_all<ST, 3, 1>(c, B, cb, tiles);
+            if (j.K == 3 && j.shape == 2) k_step_all<ST, 3, 2>(c, B, cb, tiles);
+        }
         cb ^= 1;
     }
     // compare the live buffers (A advanced by K launches of one step swaps K

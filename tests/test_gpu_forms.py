@@ -299,3 +299,31 @@ def test_autotune_keeps_state(lbm, tmp_path):
     assert lbm.lbm_autotune(b.h, 3, cache) == cfg
     a.close()
     b.close()
+
+
+def test_autotune_batch_picks_a_tile_shape_and_keeps_state(lbm, tmp_path):
+    # a batch of uneven cavities (the first twelve of the 256-cavity set):
+    # the tuner times every launch shape, tile shapes included, on the live
+    # state, keeps it, and stepping on is bitwise the same as without tuning
+    ps = W.case_c5()[0][:12]
+    temps = [W.initial_temperatures(q, 7 + c) for c, q in enumerate(ps)]
+    a = lbm.Solver(ps, "f32h64")
+    b = lbm.Solver(ps, "f32h64")
+    for c, t in enumerate(temps):
+        a.set_initial(c, *t)
+        b.set_initial(c, *t)
+    a.step(31)
+    before = [a.state(c).copy() for c in range(len(ps))]
+    cfg = lbm.lbm_autotune(a.h, 2, str(tmp_path / "tune.txt"))
+    print("batch autotune", cfg)
+    assert cfg["steps_per_launch"] in (1, 2, 3) and cfg["tile_shape"] in (0, 1, 2)
+    if cfg["steps_per_launch"] > 1:
+        assert cfg["tile_w"] > 0 and cfg["tile_h"] > 0
+    for c in range(len(ps)):
+        assert np.array_equal(a.state(c).view(np.uint32), before[c].view(np.uint32))
+    a.step(30)
+    b.step(61)
+    for c in range(len(ps)):
+        assert np.array_equal(a.state(c).view(np.uint32), b.state(c).view(np.uint32)), c
+    a.close()
+    b.close()

@@ -45,11 +45,11 @@ CASES = {
 }
 
 
-def _run(lbm, ps, prec, steps, spl, chunks):
+def _run(lbm, ps, prec, steps, spl, chunks, shape=0):
     s = lbm.Solver(ps, prec)
     cfg = lbm.lbm_get_launch(s.h)
     lbm.lbm_set_launch(s.h, cfg["block"], cfg["nodes_per_thread"], cfg["xcd_remap"], cfg["persistent"],
-                       steps_per_launch=spl)
+                       steps_per_launch=spl, tile_shape=shape if spl > 1 else 0)
     for c, q in enumerate(ps):
         s.set_initial(c, *W.initial_temperatures(q, 20 + c))
     for n in chunks(steps):
@@ -122,3 +122,40 @@ def test_smallest_cavities_against_oracle(lbm):
         o.step(61)
         e = field_errors(g, o.fields(), p)
         assert max(e.values()) < 1e-10, (nx, ny, e)
+
+
+@pytest.mark.parametrize("spl", [2, 3])
+@pytest.mark.parametrize("form", [("f32", 9), ("f32h64", 9), ("f32", 5), ("f32h64", 5), ("f64", 9), ("f64", 5),
+                                  ("f16split", 9), ("bf16split", 9), ("f16", 9)])
+@pytest.mark.parametrize("shape", [1, 2])
+def test_every_tile_shape_is_bitwise_single_steps(lbm, spl, form, shape):
+    # the alternative tile shapes the autotuner chooses from: the same bits
+    # as single steps on ragged, tiny, periodic and batched geometries
+    prec, qt = form
+    if prec == "f64" and spl == 3:
+        pytest.skip("FP64 has two steps per launch at most")
+    for case in ("ragged", "tiny", "periodic", "batch", "corner"):
+        ps = [dict(q, thermal_lattice=qt) for q in CASES[case]()]
+        steps = 101
+        ref = _run(lbm, ps, prec, steps, 1, lambda n: [1] * n)
+        got = _run(lbm, ps, prec, steps, spl, lambda n: [n], shape)
+        for (a, da), (b, db) in zip(ref, got):
+            assert np.array_equal(a, b), case
+            for k in ("flux_E", "flux_M", "E_int", "M_int", "liquid_fraction"):
+                assert (da[k] == db[k]) or (np.isnan(da[k]) and np.isnan(db[k])), (case, k)
+
+
+def test_tile_shape_reported_and_validated(lbm):
+    s = lbm.Solver(W.scaled_cavity(_c1(), 50, 40), "f32h64")
+    cfg = lbm.lbm_get_launch(s.h)
+    assert (cfg["steps_per_launch"], cfg["tile_shape"], cfg["tile_w"], cfg["tile_h"]) == (3, 0, 32, 8)
+    lbm.lbm_set_launch(s.h, 512, 1, 1, 0, steps_per_launch=3, tile_shape=1)
+    cfg = lbm.lbm_get_launch(s.h)
+    assert (cfg["tile_shape"], cfg["tile_w"], cfg["tile_h"]) == (1, 64, 4)
+    for bad in (dict(steps_per_launch=3, tile_shape=3), dict(steps_per_launch=1, tile_shape=1),
+                dict(steps_per_launch=3, tile_shape=2, persistent=4)):
+        kw = dict(dict(persistent=0), **bad)
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_set_launch(s.h, 512, 1, 1, kw.pop("persistent"), **kw)
+        assert e.value.status == lbm.LBM_EINVAL
+    s.close()

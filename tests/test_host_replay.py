@@ -1,8 +1,8 @@
 """CPU replay of the step kernels (tests/host_replay/replay.cpp): the GPU
 kernels' own headers built with a host compiler under AddressSanitizer.
 
-* Multi-step launches: the K-step kernel's workgroups are emulated tile by
-  tile (first update of every thread, the middle update's pulls of every
+* Multi-step launches, in every tile shape: the K-step kernel's workgroups
+  are emulated tile by tile (first update of every thread, the middle update's pulls of every
   thread before any of its writes, the last update) with LDS arrays of the
   kernel's exact sizes filled with NaN bit patterns and the headers' bounds
   checks on; the result must equal K one-step updates bit for bit
@@ -106,8 +106,9 @@ def test_multi_step_launch_replays_single_steps(replay, form):
     prec, qt, K = form
     for name, p in _geometries().items():
         q = dict(p, thermal_lattice=qt)
-        code, out = _run(replay, _job(q, precision=prec, K=K, launches=2, mode="kstep", seed=7))
-        assert code == 0 and "identical" in out, f"{name}: {out}"
+        for shape in range(3):      # every tile shape the launch can take
+            code, out = _run(replay, _job(q, precision=prec, K=K, shape=shape, launches=2, mode="kstep", seed=7))
+            assert code == 0 and "identical" in out, f"{name}, tile shape {shape}: {out}"
 
 
 @pytest.mark.parametrize("prec,qt,tol", [("f64", 9, 1e-12), ("f64", 5, 1e-12), ("f32", 9, 1e-5),
