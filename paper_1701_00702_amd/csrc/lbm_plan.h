@@ -440,6 +440,7 @@ inline int plane_groups(int st, PlaneGroup g[2]) {
 // pulls from outside the K-step kernels' LDS region.
 inline void split_runs(int n, int t, std::vector<std::pair<int, int>> &out) {
     out.clear();
+    if (t < 2) return;
     int start = 0;
     while (start < n) {
         int w = std::min(t, n - start);
