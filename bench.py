@@ -281,8 +281,8 @@ def main():
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=0, choices=[0, 1, 2, 3],
                     help="0: the library's default (several steps per launch through LDS where available)")
-    ap.add_argument("--tile-shape", type=int, default=None, choices=[0, 1, 2, 3, 4],
-                    help="tile shape of the multi-step kernel (0 default, 1 wide, 2 tall, 3 LDS-marching strips, 4 wavefront-marching strips)")
+    ap.add_argument("--tile-shape", type=int, default=None, choices=[0, 1, 2],
+                    help="tile shape of the multi-step kernel (0 default, 1 wide, 2 tall)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--forms", action="store_true", help="also time the 16-bit and batched forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -198,13 +198,9 @@ typedef struct lbm_launch_config {
                                  block and nodes_per_thread then do not apply. */
     int32_t tile_shape;       /* tile shape of the multi-step kernel: 0 the
                                  default; 1 about twice as wide and half as
-                                 tall; 2 about half as wide and twice as tall;
-                                 3 (three steps per launch) strips 32 columns
-                                 wide marched along y a few rows at a time,
-                                 rows kept in LDS between chunks so only the
-                                 ring in x is advanced twice.  Shapes other
-                                 than 0 take no persistent grid.  Every shape
-                                 gives the same bits.                         */
+                                 tall; 2 about half as wide and twice as tall
+                                 (multi-step launches without a persistent
+                                 grid).  Every shape gives the same bits.     */
     int32_t tile_w, tile_h;   /* reported by lbm_get_launch and lbm_autotune:
                                  the tile of the multi-step kernel (0 with
                                  one step per launch); ignored on input       */

@@ -177,7 +177,6 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
         for (int shape = 0; shape < LBM_TILE_SHAPES; ++shape) {
             int tw, th;
             stepk_tile(st, k, shape, &tw, &th);
-            if (!tw) continue;  // no such shape for this K
             int64_t count = 0;
             for (int c = 0; c < n; ++c) count += count_tiles2(p[c].nx, p[c].ny, tw, th);
             pl.tilesk[k] = std::max(pl.tilesk[k], count);
@@ -318,16 +317,14 @@ lbm_status build_tiles(lbm_handle *h, const lbm_launch_config &lc) {
 // whether the plan has the tiles of K steps per launch
 bool has_k(const Plan &pl, int k) { return k == 1 || ((k == 2 || k == 3) && pl.tilesk[k] > 0); }
 
-bool valid_launch(const lbm_launch_config &lc, const Plan &pl, int st) {
+bool valid_launch(const lbm_launch_config &lc, const Plan &pl) {
     const bool b = lc.block == 64 || lc.block == 128 || lc.block == 256 || lc.block == 512;
     const bool n = lc.nodes_per_thread == 1 || lc.nodes_per_thread == 2 || lc.nodes_per_thread == 4;
     const bool t = has_k(pl, lc.steps_per_launch);
-    // alternative tile shapes: multi-step launches without a persistent grid,
-    // in a shape the storage form has for that many steps
-    int tw = 0, th = 0;
-    if (lc.tile_shape > 0 && lc.tile_shape < LBM_TILE_SHAPES && lc.steps_per_launch > 1)
-        stepk_tile(st, lc.steps_per_launch, lc.tile_shape, &tw, &th);
-    const bool sh = lc.tile_shape == 0 || (tw > 0 && lc.persistent == 0);
+    // alternative tile shapes: multi-step launches without a persistent grid
+    const bool sh = lc.tile_shape == 0 ||
+                    (lc.tile_shape > 0 && lc.tile_shape < LBM_TILE_SHAPES && lc.steps_per_launch > 1 &&
+                     lc.persistent == 0);
     return b && n && t && sh && (lc.xcd_remap == 0 || lc.xcd_remap == 1) && lc.persistent >= 0 &&
            lc.persistent <= 64;
 }
@@ -903,7 +900,7 @@ extern "C" lbm_status lbm_get_launch(const lbm_handle *h, lbm_launch_config *out
 
 extern "C" lbm_status lbm_set_launch(lbm_handle *h, const lbm_launch_config *cfg) {
     if (!h || !cfg) return fail(LBM_EINVAL, "NULL argument");
-    if (!valid_launch(*cfg, h->pl, h->st))
+    if (!valid_launch(*cfg, h->pl))
         return fail(LBM_EINVAL,
                     "unsupported launch shape block=%d npt=%d xcd=%d persistent=%d steps=%d tile_shape=%d",
                     cfg->block, cfg->nodes_per_thread, cfg->xcd_remap, cfg->persistent, cfg->steps_per_launch,
@@ -945,7 +942,7 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
             std::memset(&lc, 0, sizeof(lc));
             while (fscanf(f, "%255s %d %d %d %d %d %d", k, &lc.block, &lc.nodes_per_thread, &lc.xcd_remap,
                           &lc.persistent, &lc.steps_per_launch, &lc.tile_shape) == 7) {
-                if (key == k && valid_launch(lc, h->pl, h->st)) {
+                if (key == k && valid_launch(lc, h->pl)) {
                     fclose(f);
                     lbm_status s = lbm_set_launch(h, &lc);
                     if (s == LBM_OK && chosen) *chosen = h->lc;
@@ -1021,7 +1018,6 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
                 for (int pp : pers) {
                     if (shape != 0 && pp != 0) continue;
                     lbm_launch_config lc{one.block, one.nodes_per_thread, xr, pp, kk, shape, 0, 0};
-                    if (!valid_launch(lc, h->pl, h->st)) continue;  // no such shape for this K
                     float ms;
                     lbm_status s = trial(lc, &ms);
                     if (s != LBM_OK) return abandon(s);

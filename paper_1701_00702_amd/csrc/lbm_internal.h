@@ -126,7 +126,7 @@ struct Tile2 {
 struct Step2Launch {
     int storage;
     int steps;  // K: 2 or 3 steps per launch
-    int shape;  // tile shape index (0 default; 3, 4 marching strips; see stepk_tile)
+    int shape;  // tile shape index (0 default; see stepk_tile)
     int grid, xcd_remap;
     const void *src;
     void *dst;
@@ -211,7 +211,7 @@ hipError_t launch_stepk(const Step2Launch &L, hipStream_t s);
 bool stepk_supported(int storage, int k);  // K steps per launch (K = 2, 3)
 // Tile shape `shape` (0 .. LBM_TILE_SHAPES - 1) of the K-step kernel; 0 x 0
 // when it does not exist.
-#define LBM_TILE_SHAPES 5
+#define LBM_TILE_SHAPES 3
 void stepk_tile(int storage, int k, int shape, int *tw, int *th);
 hipError_t launch_macro(const MacroLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s);

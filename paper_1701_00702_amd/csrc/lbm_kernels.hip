@@ -27,7 +27,6 @@
 
 #include "lbm_node.h"
 #include "lbm_tiles.h"
-#include "lbm_wave.h"
 
 namespace lbm {
 
@@ -191,41 +190,28 @@ hipError_t launch_step(const StepLaunch &L, hipStream_t s) {
 // the persistent launch.  Without the loop nothing in the tile's code is
 // loop-invariant, so the compiler does not keep the 27 plane addresses live
 // across iterations (they would spill to vector registers).
-template <class Lay, typename R, typename RH, int TW, int TH, int NT, int K, bool WALLS>
-__device__ __forceinline__ void stepk_advance_w(const void *__restrict__ src, void *__restrict__ dst,
-                                                const R *__restrict__ sr_src, R *__restrict__ sr_dst,
-                                                double *__restrict__ acc, const CavityConst<R> &c, const Tile2 &tl,
-                                                void *lds_q, R *lds_sr) {
-    using Sh = StepKShape<Lay, TW, TH, K>;
-    // NT >= NFIRST: each thread advances at most one node per update
-    const int s = (int)threadIdx.x;
-    if (s < Sh::LW * (tl.h + 2 * Sh::RING))
-        stepk_first<Lay, R, RH, TW, TH, K, WALLS>(c, tl, src, sr_src, acc, lds_q, lds_sr, s);
-    __syncthreads();
-#pragma unroll
-    for (int j = K - 2; j >= 1; --j) {
-        MidNode<R, RH> n;
-        const bool act = s < (TW + 2 * j) * (tl.h + 2 * j) &&
-                         stepk_mid_load<Lay, R, RH, TW, TH, K, WALLS>(c, tl, j, lds_q, lds_sr, s, n);
-        __syncthreads();  // every pull of this update is in registers
-        if (act) stepk_mid_store<Lay, R, RH, TW, TH, K, WALLS>(c, tl, acc, lds_q, lds_sr, n);
-        __syncthreads();
-    }
-    if (s < TW * tl.h) stepk_last<Lay, R, RH, TW, TH, K, WALLS>(c, tl, dst, sr_dst, acc, lds_q, lds_sr, s);
-}
-// A tile whose updated nodes are all away from the walls takes the
-// instantiation without the wall code (the branch is the same for the whole
-// workgroup).
 template <class Lay, typename R, typename RH, int TW, int TH, int NT, int K>
 __device__ __forceinline__ void stepk_advance(const void *__restrict__ src, void *__restrict__ dst,
                                               const R *__restrict__ sr_src, R *__restrict__ sr_dst,
                                               double *__restrict__ acc, const CavityConst<R> *__restrict__ cav,
                                               const Tile2 &tl, void *lds_q, R *lds_sr) {
+    using Sh = StepKShape<Lay, TW, TH, K>;
     const CavityConst<R> &c = cav[tl.cav];
-    if (tile_interior<R, K>(c, tl))
-        stepk_advance_w<Lay, R, RH, TW, TH, NT, K, false>(src, dst, sr_src, sr_dst, acc, c, tl, lds_q, lds_sr);
-    else
-        stepk_advance_w<Lay, R, RH, TW, TH, NT, K, true>(src, dst, sr_src, sr_dst, acc, c, tl, lds_q, lds_sr);
+    // NT >= NFIRST: each thread advances at most one node per update
+    const int s = (int)threadIdx.x;
+    if (s < Sh::LW * (tl.h + 2 * Sh::RING))
+        stepk_first<Lay, R, RH, TW, TH, K>(c, tl, src, sr_src, acc, lds_q, lds_sr, s);
+    __syncthreads();
+#pragma unroll
+    for (int j = K - 2; j >= 1; --j) {
+        MidNode<R, RH> n;
+        const bool act = s < (TW + 2 * j) * (tl.h + 2 * j) &&
+                         stepk_mid_load<Lay, R, RH, TW, TH, K>(c, tl, j, lds_q, lds_sr, s, n);
+        __syncthreads();  // every pull of this update is in registers
+        if (act) stepk_mid_store<Lay, R, RH, TW, TH, K>(c, tl, acc, lds_q, lds_sr, n);
+        __syncthreads();
+    }
+    if (s < TW * tl.h) stepk_last<Lay, R, RH, TW, TH, K>(c, tl, dst, sr_dst, acc, lds_q, lds_sr, s);
 }
 
 // Waves per SIMD a multi-step kernel is built for: as many workgroups per
@@ -303,188 +289,12 @@ static hipError_t launch_stepk_i(const Step2Launch &L, hipStream_t s) {
     return hipGetLastError();
 }
 
-// The marching three-step kernel (MarchShape): one strip per workgroup,
-// chunk by chunk, two barriers per chunk; the global loads of a chunk's
-// first update are issued during the chunk before.  The LDS of one strip
-// sets how many workgroups share a CU; the kernel is built for that
-// occupancy.
-template <class Lay, typename R, int TW, int RR, int NT>
-constexpr int stepm_waves_per_eu() {
-    using Sh = MarchShape<Lay, TW, RR>;
-    constexpr int lds = (int)(Sh::LDS_BYTES + Sh::NSR * sizeof(R));
-    constexpr int by_lds = (160 * 1024) / lds;
-    constexpr int by_waves = 32 / (NT / 64);
-    constexpr int wgs = by_lds < by_waves ? by_lds : by_waves;
-    return (wgs * (NT / 64) + 3) / 4;
-}
-
-template <class Lay, typename R, typename RH, int TW, int RR, int NT, int WPE>
-__global__ __launch_bounds__(NT, WPE) void stepm_kernel(const void *__restrict__ src, void *__restrict__ dst,
-                                                        const R *__restrict__ sr_src, R *__restrict__ sr_dst,
-                                                        double *__restrict__ acc,
-                                                        const CavityConst<R> *__restrict__ cav,
-                                                        const Tile2 *__restrict__ tiles, int ntiles,
-                                                        int xcd_remap) {
-    using Sh = MarchShape<Lay, TW, RR>;
-    static_assert(NT >= Sh::NFIRST && NT % 64 == 0, "one thread per node of the first update");
-    static_assert(Sh::LDS_BYTES + Sh::NSR * sizeof(R) <= 160 * 1024, "strip exceeds the LDS of a CU");
-    __shared__ __align__(16) unsigned char lds_q[Sh::LDS_BYTES];
-    __shared__ R lds_sr[Sh::NSR];
-    const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
-    if (b >= ntiles) return;
-    const Tile2 tl = tiles[b];
-    const CavityConst<R> &c = cav[tl.cav];
-    const int s = (int)threadIdx.x;
-    const int end = tl.y0 + tl.h;
-    int Y = tl.y0 - 2 * (Sh::K - 1);
-    MarchIn<R, RH> in;  // update 1's inputs, loaded a chunk ahead
-    if (s < Sh::width(1) * RR) march_load<Lay, R, RH, TW, RR>(c, tl, Y, src, sr_src, s, in);
-    for (; Y < end; Y += RR) {
-        if (s < Sh::width(1) * RR) {
-            march_update<Lay, R, RH, TW, RR, 1>(c, tl, Y, dst, sr_dst, acc, lds_q, lds_sr, s, in);
-            if (Y + RR < end) march_load<Lay, R, RH, TW, RR>(c, tl, Y + RR, src, sr_src, s, in);
-        }
-        __syncthreads();
-        if (s < Sh::width(2) * RR) {
-            MarchIn<R, RH> n2;
-            march_update<Lay, R, RH, TW, RR, 2>(c, tl, Y, dst, sr_dst, acc, lds_q, lds_sr, s, n2);
-        }
-        __syncthreads();
-        if (s < TW * RR) {
-            MarchIn<R, RH> n3;
-            march_update<Lay, R, RH, TW, RR, 3>(c, tl, Y, dst, sr_dst, acc, lds_q, lds_sr, s, n3);
-        }
-    }
-}
-
-template <int ST>
-static hipError_t launch_stepm(const Step2Launch &L, hipStream_t s) {
-    using Lay = typename LayoutOf<ST>::L;
-    using R = typename LayoutOf<ST>::R;
-    using RH = typename LayoutOf<ST>::RH;
-    using Tm = MarchTile<ST>;
-    if (L.grid < L.ntiles) return hipErrorInvalidValue;  // no persistent grid
-    hipLaunchKernelGGL((stepm_kernel<Lay, R, RH, Tm::TW, Tm::RR, Tm::NT,
-                                     stepm_waves_per_eu<Lay, R, Tm::TW, Tm::RR, Tm::NT>()>),
-                       dim3(L.grid), dim3(Tm::NT), 0, s, L.src, L.dst, (const R *)L.sr_src, (R *)L.sr_dst, L.acc,
-                       (const CavityConst<R> *)L.cav, L.tiles, L.ntiles, L.xcd_remap);
-    return hipGetLastError();
-}
-
-// The wavefront-marching three-step kernel (lbm_wave.h): NW wavefronts per
-// workgroup, one strip each, no barriers.
-// Value of lane l - d (d = +1: the lane before, -1: the lane after) of a
-// 64-lane wavefront, by a DPP wavefront shift; a lane with no such
-// neighbour keeps its own value.  Every lane must be active.
-__device__ __forceinline__ int lane_from_i(int v, int d) {
-    return d > 0 ? __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false)   // wave_shr:1
-                 : __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
-}
-__device__ __forceinline__ float lane_from(float v, int d) { return __int_as_float(lane_from_i(__float_as_int(v), d)); }
-__device__ __forceinline__ double lane_from(double v, int d) {
-    const long long b = __double_as_longlong(v);
-    const unsigned lo = (unsigned)lane_from_i((int)(b & 0xffffffffll), d);
-    const unsigned hi = (unsigned)lane_from_i((int)(b >> 32), d);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-template <typename R, typename RH>
-struct WaveDev {
-    WLane<R, RH> L;
-    // this iteration's values: uninitialised, nothing carried over
-    __device__ __forceinline__ WTemp<R, RH> temps() {
-        WTemp<R, RH> t;
-        return t;
-    }
-    template <class F>
-    __device__ __forceinline__ void each(WTemp<R, RH> &t, F f) {
-        f(L, t);
-    }
-    template <int QT, class A>
-    __device__ __forceinline__ void shift(WTemp<R, RH> &t, A a) {
-        WNode<R, RH> &n = a(L, t);
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            if (ex_of(i) == 0) continue;
-            n.f[i] = lane_from(n.f[i], ex_of(i));
-            if (i < QT) {
-                n.g[i] = lane_from(n.g[i], ex_of(i));
-                n.h[i] = lane_from(n.h[i], ex_of(i));
-            }
-        }
-    }
-    template <int QT, int D, class A, class P>
-    __device__ __forceinline__ void take(WTemp<R, RH> &t, A a, P pred) {
-        WNode<R, RH> &n = a(L, t);
-        const bool mine = pred(L);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const R f = lane_from(n.f[i], D);
-            n.f[i] = mine ? f : n.f[i];
-            if (i < QT) {
-                const RH g = lane_from(n.g[i], D);
-                const R h = lane_from(n.h[i], D);
-                n.g[i] = mine ? g : n.g[i];
-                n.h[i] = mine ? h : n.h[i];
-            }
-        }
-    }
-};
-
-template <class Lay, typename R, typename RH, int NW>
-__global__ __launch_bounds__(64 * NW) void stepw_kernel(const void *__restrict__ src, void *__restrict__ dst,
-                                                        const R *__restrict__ sr_src, R *__restrict__ sr_dst,
-                                                        double *__restrict__ acc,
-                                                        const CavityConst<R> *__restrict__ cav,
-                                                        const Tile2 *__restrict__ tiles, int ntiles,
-                                                        int xcd_remap) {
-    __shared__ WStash<R, RH> stash[NW];
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap) * NW + wv;
-    if (b >= ntiles) return;  // the whole wavefront
-    const Tile2 tl = tiles[b];
-    const CavityConst<R> &c = cav[tl.cav];
-    WaveArgs<R> a;
-    a.c = &c;
-    a.tl = tl;
-    a.src = src;
-    a.dst = dst;
-    a.sr_src = sr_src;
-    a.sr_dst = sr_dst;
-    a.acc = acc;
-    a.left_wall = !c.periodic && tl.x0 - 2 <= 0;
-    a.right_wall = !c.periodic && tl.x0 - 2 <= c.nx - 1 && c.nx - 1 <= tl.x0 - 2 + kWaveLanes - 1;
-    WaveDev<R, RH> e;
-    e.L.lane = (int)(threadIdx.x & 63);
-    wave_sweep<Lay, R, RH>(e, a, &stash[wv]);
-}
-
-template <int ST>
-static hipError_t launch_stepw(const Step2Launch &L, hipStream_t s) {
-    using Lay = typename LayoutOf<ST>::L;
-    using R = typename LayoutOf<ST>::R;
-    using RH = typename LayoutOf<ST>::RH;
-    constexpr int NW = LBM_WAVE_NW;
-    if (L.grid < L.ntiles) return hipErrorInvalidValue;  // no persistent grid
-    const int grid = (L.ntiles + NW - 1) / NW;
-    hipLaunchKernelGGL((stepw_kernel<Lay, R, RH, NW>), dim3(grid), dim3(64 * NW), 0, s, L.src, L.dst,
-                       (const R *)L.sr_src, (R *)L.sr_dst, L.acc, (const CavityConst<R> *)L.cav, L.tiles,
-                       L.ntiles, L.xcd_remap);
-    return hipGetLastError();
-}
-
 template <int ST, int K>
 static hipError_t launch_stepk_s(const Step2Launch &L, hipStream_t s) {
     switch (L.shape) {
         case 0: return launch_stepk_i<ST, K, 0>(L, s);
         case 1: return launch_stepk_i<ST, K, 1>(L, s);
         case 2: return launch_stepk_i<ST, K, 2>(L, s);
-        case kMarchShape:
-            if constexpr (K == 3) return launch_stepm<ST>(L, s);
-            return hipErrorInvalidValue;
-        case kWaveShape:
-            if constexpr (K == 3) return launch_stepw<ST>(L, s);
-            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

@@ -36,20 +36,6 @@
 
 #define LBM_HD __host__ __device__ __forceinline__
 
-// Bounds checks of the host builds of this file (the CPU replay of the step
-// kernels); nothing in device code.
-#if defined(__HIP_DEVICE_COMPILE__)
-#define LBM_HOST_CHECK(cond) ((void)0)
-#else
-#define LBM_HOST_CHECK(cond)                                                              \
-    do {                                                                                  \
-        if (!(cond)) {                                                                    \
-            fprintf(stderr, "lbm: check failed: %s (%s:%d)\n", #cond, __FILE__, __LINE__); \
-            abort();                                                                      \
-        }                                                                                 \
-    } while (0)
-#endif
-
 namespace lbm {
 
 // ---------------------------------------------------------------------------
@@ -825,18 +811,9 @@ struct NodeGeom {
     int sx, sy;
 };
 
-// WALLS = false: the caller knows the node is neither a wall node nor
-// next to one (an interior block of nodes).
-template <bool WALLS = true, typename R>
+template <typename R>
 LBM_HD NodeGeom geometry(const CavityConst<R> &c, int x, int y, bool pull) {
     NodeGeom g;
-    if constexpr (!WALLS) {
-        LBM_HOST_CHECK((c.periodic || (x > 1 && x < c.nx - 2)) && y > 1 && y < c.ny - 2);
-        g.wall = g.near_x = g.near_y = false;
-        g.sx = x;
-        g.sy = y;
-        return g;
-    }
     const int nx = c.nx, ny = c.ny;
     const bool vwall = !c.periodic && (x == 0 || x == nx - 1);
     const bool hwall = (y == 0 || y == ny - 1);
@@ -978,16 +955,15 @@ LBM_HD void link_content(const CavityConst<R> &c, int i, const R qf[9], const RH
 // reconstruction, macroscopic values, the three collisions and the
 // interstitial sources.  On return q* hold the post-collision offsets and
 // m, th the values the split layout stores as bases; the result is the
-// new PCM source Sr_f.  WALLS = false drops the wall code for a node known
-// to be neither a wall node nor next to one.
-template <int QT, typename R, typename RH, bool PULL, bool WALLS = true>
+// new PCM source Sr_f.
+template <int QT, typename R, typename RH, bool PULL>
 LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, R qf[9], RH qg[9], R qh[9],
                       R sr_prev, bool tally, double *__restrict__ acc, Thermo<RH> &th, Macro<R> &m) {
     const int nx = c.nx, ny = c.ny;
     // Wall tallies: an interior node next to a wall owns one slot per wall it
     // touches (x: the vertical wall, y: the horizontal one).
     double xE = 0.0, xM = 0.0, yE = 0.0, yM = 0.0;
-    if (WALLS && PULL && tally && (g.near_x || g.near_y)) {
+    if (PULL && tally && (g.near_x || g.near_y)) {
         // inflow: populations pulled from wall nodes (post-collision of the
         // previous step)
 #pragma unroll
@@ -1009,7 +985,7 @@ LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, 
         }
     }
 
-    if (WALLS && PULL && g.wall) reconstruct_wall<QT>(c, x, y, qf, qg, qh);
+    if (PULL && g.wall) reconstruct_wall<QT>(c, x, y, qf, qg, qh);
 
     Moments<R, RH> mo;
     field_moments<QT>(qf, qg, qh, mo);
@@ -1029,7 +1005,7 @@ LBM_HD RH update_node(const CavityConst<R> &c, const NodeGeom &g, int x, int y, 
         collide_metal5(c, m, S_metal, mo.h, qh);
     }
 
-    if (WALLS && tally && (g.near_x || g.near_y)) {
+    if (tally && (g.near_x || g.near_y)) {
         // outflow: post-collision populations aimed at wall nodes
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
@@ -1110,6 +1086,17 @@ LBM_HD void step_node(const CavityConst<R> &c, const void *src, void *dst, const
 // layout with the FP64 rest enthalpy population: the LDS holds each
 // population in the type it is stored in.
 // ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LBM_HOST_CHECK(cond) ((void)0)
+#else
+#define LBM_HOST_CHECK(cond)                                                              \
+    do {                                                                                  \
+        if (!(cond)) {                                                                    \
+            fprintf(stderr, "lbm: check failed: %s (%s:%d)\n", #cond, __FILE__, __LINE__); \
+            abort();                                                                      \
+        }                                                                                 \
+    } while (0)
+#endif
 
 // How a layout keeps its populations in LDS for the K-step kernels: encoded
 // exactly as it stores them (element type, 16-bit scale, split base), so
@@ -1276,19 +1263,6 @@ struct StepKShape {
     static_assert(TH + 2 * K <= LBM_MIN_BAND_ROWS, "a tile's rows must span at most two bands");
 };
 
-// Whether every node of columns [x_lo, x_hi] and rows [y_lo, y_hi] is
-// neither a wall node nor next to one: the nodes a multi-step launch
-// updates within one tile or strip, whose updates then skip the wall code.
-template <typename R>
-LBM_HD bool block_interior(const CavityConst<R> &c, int x_lo, int x_hi, int y_lo, int y_hi) {
-    const bool xin = c.periodic || (x_lo >= 2 && x_hi <= c.nx - 3);
-    return xin && y_lo >= 2 && y_hi <= c.ny - 3;
-}
-template <typename R, int K>
-LBM_HD bool tile_interior(const CavityConst<R> &c, const Tile2 &tl) {
-    return block_interior(c, tl.x0 - (K - 1), tl.x0 + tl.w + K - 2, tl.y0 - (K - 1), tl.y0 + tl.h + K - 2);
-}
-
 // Global accesses of a tile go through 32-bit offsets from the block of the
 // band of the first row any update touches, y0 - K (the first update's ring
 // and its pulls), clipped to the cavity: at most TH + 2K <= LBM_MIN_BAND_ROWS
@@ -1331,7 +1305,7 @@ LBM_HD void lds_push(const CavityConst<R> &c, const Tile2 &tl, int x, int y, voi
 // First update: slot s of R_(K-1) (row-major with the fixed pitch LW, so the
 // decode divides by a constant; columns beyond w + 2 RING idle).  Reads the
 // global state, writes the slot's post-collision populations and Sr_f to LDS.
-template <class Lay, typename R, typename RH, int TW, int TH, int K, bool WALLS = true>
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
 LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *src,
                         const R *__restrict__ sr_src, double *__restrict__ acc, void *lds_q, R *lds_sr, int s) {
     using Sh = StepKShape<Lay, TW, TH, K>;
@@ -1346,7 +1320,7 @@ LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *sr
     else if (x < 0 || x >= c.nx) return;
     LBM_HOST_CHECK(xx >= 0 && xx < c.nx);
     const bool owned = x >= tl.x0 && x < tl.x0 + tl.w && y >= tl.y0 && y < tl.y0 + tl.h;
-    const NodeGeom g = geometry<WALLS>(c, xx, y, true);
+    const NodeGeom g = geometry(c, xx, y, true);
     const int yb = tile_first_row<R, K>(c, tl);
     const BandOrigin org = band_origin(c, yb);
     LBM_HOST_CHECK(g.sy - 1 >= yb && g.sy + 1 < yb + TH + 2 * K);
@@ -1357,7 +1331,7 @@ LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *sr
     Thermo<RH> th;
     Macro<R> m;
     const R sr_prev = sr_src[flat_index(c, xx, y)];
-    const RH srf = update_node<Sh::QT, R, RH, true, WALLS>(c, g, xx, y, qf, qg, qh, sr_prev, owned, acc, th, m);
+    const RH srf = update_node<Sh::QT, R, RH, true>(c, g, xx, y, qf, qg, qh, sr_prev, owned, acc, th, m);
     if constexpr (Sh::PUSH) {
         lds_push<Sh, R, RH>(c, tl, x, y, lds_q, lds_sr, qf, qg, qh, srf);
     } else {
@@ -1426,7 +1400,7 @@ struct MidNode {
     R qf[9], qh[9], sr_prev;
     RH qg[9];
 };
-template <class Lay, typename R, typename RH, int TW, int TH, int K, bool WALLS = true>
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
 LBM_HD bool stepk_mid_load(const CavityConst<R> &c, const Tile2 &tl, int j, const void *lds_q, const R *lds_sr,
                            int t, MidNode<R, RH> &n) {
     using Sh = StepKShape<Lay, TW, TH, K>;
@@ -1441,20 +1415,20 @@ LBM_HD bool stepk_mid_load(const CavityConst<R> &c, const Tile2 &tl, int j, cons
     else if (n.x < 0 || n.x >= c.nx) return false;
     LBM_HOST_CHECK(n.xx >= 0 && n.xx < c.nx);
     n.owned = n.x >= tl.x0 && n.x < tl.x0 + tl.w && n.y >= tl.y0 && n.y < tl.y0 + tl.h;
-    n.g = geometry<WALLS>(c, n.xx, n.y, true);
+    n.g = geometry(c, n.xx, n.y, true);
     n.slot = lds_slot<Sh>(tl, n.x, n.y);
     LBM_HOST_CHECK(n.slot >= 0 && n.slot < Sh::NSLOT);
     lds_gather<Sh, R, RH>(c, tl, n.g, n.x, n.xx, tl.h + 2 * Sh::RING, lds_q, n.qf, n.qg, n.qh);
     n.sr_prev = lds_sr[n.slot];
     return true;
 }
-template <class Lay, typename R, typename RH, int TW, int TH, int K, bool WALLS = true>
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
 LBM_HD void stepk_mid_store(const CavityConst<R> &c, const Tile2 &tl, double *__restrict__ acc, void *lds_q,
                             R *lds_sr, MidNode<R, RH> &n) {
     using Sh = StepKShape<Lay, TW, TH, K>;
     Thermo<RH> th;
     Macro<R> m;
-    const RH srf = update_node<Sh::QT, R, RH, true, WALLS>(c, n.g, n.xx, n.y, n.qf, n.qg, n.qh, n.sr_prev, n.owned, acc,
+    const RH srf = update_node<Sh::QT, R, RH, true>(c, n.g, n.xx, n.y, n.qf, n.qg, n.qh, n.sr_prev, n.owned, acc,
                                                    th, m);
     if constexpr (Sh::PUSH) {
         lds_push<Sh, R, RH>(c, tl, n.x, n.y, lds_q, lds_sr, n.qf, n.qg, n.qh, srf);
@@ -1468,7 +1442,7 @@ LBM_HD void stepk_mid_store(const CavityConst<R> &c, const Tile2 &tl, double *__
 
 // Last update: node n of the tile (row-major with pitch TW; columns beyond
 // w idle).  Pulls from LDS, writes the global state.
-template <class Lay, typename R, typename RH, int TW, int TH, int K, bool WALLS = true>
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
 LBM_HD void stepk_last(const CavityConst<R> &c, const Tile2 &tl, void *dst, R *__restrict__ sr_dst,
                        double *__restrict__ acc, const void *lds_q, const R *lds_sr, int n) {
     using Sh = StepKShape<Lay, TW, TH, K>;
@@ -1476,7 +1450,7 @@ LBM_HD void stepk_last(const CavityConst<R> &c, const Tile2 &tl, void *dst, R *_
     if (n % TW >= tl.w) return;
     const int x = tl.x0 + n % TW, y = tl.y0 + n / TW;
     LBM_HOST_CHECK(x >= 0 && x < c.nx && y >= 0 && y < c.ny);
-    const NodeGeom g = geometry<WALLS>(c, x, y, true);
+    const NodeGeom g = geometry(c, x, y, true);
     R qf[9], qh[9];
     RH qg[9];
     lds_gather<Sh, R, RH>(c, tl, g, x, x, tl.h + 2 * Sh::RING, lds_q, qf, qg, qh);
@@ -1486,197 +1460,13 @@ LBM_HD void stepk_last(const CavityConst<R> &c, const Tile2 &tl, void *dst, R *_
     void *blk = band_block(c, dst, yb / c.band_rows);
     Thermo<RH> th;
     Macro<R> m;
-    const RH srf = update_node<Sh::QT, R, RH, true, WALLS>(c, g, x, y, qf, qg, qh, lds_sr[self], true, acc, th, m);
+    const RH srf = update_node<Sh::QT, R, RH, true>(c, g, x, y, qf, qg, qh, lds_sr[self], true, acc, th, m);
     const ThermalConst<RH> &t = thermal<RH>(c);
     const int64_t stride = c.band_nodes;
     Lay::template store<R>(blk, stride, 0, qf, m.drho, k, c);
     Lay::template store<RH>(blk, stride, 1, qg, t.c_fref * (th.Tf - t.T_ref), k, c);
     Lay::template store<R>(blk, stride, 2, qh, c.c_mref * m.dTm, k, c);
     sr_dst[flat_index(c, x, y)] = (R)srf;
-}
-
-// ---------------------------------------------------------------------------
-// Three steps per launch by marching.  A strip of w <= TW columns and h rows
-// at (x0, y0) advances K = 3 steps in chunks of RR rows, bottom to top.  In
-// chunk m, with Y = y0 - 2 (K - 1) + m RR, update j (j = 1 .. K, ring
-// G = K - j) advances rows [Y + G, Y + G + RR) of the strip grown by G nodes
-// on every side (clipped to the grown strip and to the cavity).  Update j
-// runs one row behind update j - 1, which is as far as its pulls reach, so
-// every value it pulls is already advanced.  A wall node pulls through its
-// partner: on the top wall that is a row behind; on the bottom wall (row 0,
-// partner row 1) two rows ahead, which the first chunk of a strip starting
-// at row 0 covers as long as RR >= 6.  Rows stay in LDS from one chunk to
-// the next, and only the ring in x is advanced more than once per step.  Updates 1 .. K - 1 keep their
-// results in buffers of RR + 2 rows (row y at y mod (RR + 2)), each node in
-// its own slot (pull placement); update j + 1 pulls from buffer j.  Update
-// 1 reads the global state, update K writes it.  A buffer row is rewritten
-// RR rows after the chunk that last read it, past the barrier that ends
-// that chunk's reads: updates K and 1 of consecutive chunks share a barrier
-// interval, but not a buffer.  Values are kept in their stored form (the
-// LDS codecs above), so the launch is bit-identical to K one-step launches,
-// wall tallies included (each node of the strip tallies its own updates,
-// in step order).  Every access of a chunk falls within rows [Y, Y + RR + 4)
-// of the cavity, two bands at most.
-// ---------------------------------------------------------------------------
-template <class Lay, int TW, int RR>
-struct MarchShape {
-    static constexpr int K = 3;
-    static constexpr int QT = Lay::QT;
-    static constexpr int CHUNK = RR;     // rows per chunk
-    static constexpr int ROWS = RR + 2;  // rows of each buffer
-    static constexpr int ring(int j) { return K - j; }
-    static constexpr int width(int j) { return TW + 2 * (K - j); }
-    static constexpr int NFIRST = (TW + 2 * (K - 1)) * RR;  // threads of update 1
-    using Codec = LdsCodec<Lay>;
-    static constexpr int nslot(int j) { return ROWS * width(j); }
-    // buffer j (1 .. K - 1): populations from byte qoff(j) of the population
-    // area, sources from element sroff(j) of the source area
-    static constexpr size_t qoff(int j) {
-        size_t o = 0;
-        for (int b = 1; b < j; ++b) o += (Codec::bytes(nslot(b)) + 15) & ~(size_t)15;
-        return o;
-    }
-    static constexpr int sroff(int j) {
-        int o = 0;
-        for (int b = 1; b < j; ++b) o += nslot(b);
-        return o;
-    }
-    static constexpr size_t LDS_BYTES = qoff(K);
-    static constexpr int NSR = sroff(K);
-    static_assert(RR >= 6, "the bottom wall's partner pulls two rows ahead");
-    static_assert(RR + 4 <= LBM_MIN_BAND_ROWS, "a chunk's rows must span at most two bands");
-};
-
-// Slot of node (x, y) (unwrapped x) in buffer j.
-template <class Sh, int J>
-LBM_HD int march_slot(const Tile2 &tl, int x, int y) {
-    return (int)((unsigned)y % (unsigned)Sh::ROWS) * Sh::width(J) + (x - (tl.x0 - Sh::ring(J)));
-}
-
-// A node's pulls from buffer J: the slots of the neighbours of the node (or
-// of its wall partner).  x is the node's unwrapped column, xx the wrapped
-// one.
-template <class Sh, int J, typename R, typename RH>
-LBM_HD void march_gather(const CavityConst<R> &c, const Tile2 &tl, const NodeGeom &g, int x, int xx,
-                         const void *lds_q, R qf[9], RH qg[9], R qh[9]) {
-    using Cd = typename Sh::Codec;
-    constexpr int W = Sh::width(J), NS = Sh::nslot(J);
-    const void *buf = (const char *)lds_q + Sh::qoff(J);
-    const int px = x + (g.sx - xx) - (tl.x0 - Sh::ring(J));  // partner column in the buffer
-    const int r0 = (int)((unsigned)g.sy % (unsigned)Sh::ROWS);
-    const int rmid = r0 * W;
-    const int rup = (r0 + 1 == Sh::ROWS ? 0 : r0 + 1) * W;      // row g.sy + 1
-    const int rdn = (r0 == 0 ? Sh::ROWS - 1 : r0 - 1) * W;      // row g.sy - 1
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int sl = (ey_of(i) > 0 ? rdn : (ey_of(i) < 0 ? rup : rmid)) + px - ex_of(i);
-        LBM_HOST_CHECK(px - ex_of(i) >= 0 && px - ex_of(i) < W);
-        LBM_HOST_CHECK(sl >= 0 && sl < NS);
-        qf[i] = Cd::template get<R>(buf, NS, 0, i, sl, c);
-        if (i < Sh::QT) {
-            qg[i] = Cd::template get<RH>(buf, NS, 1, i, sl, c);
-            qh[i] = Cd::template get<R>(buf, NS, 2, i, sl, c);
-        } else {
-            qg[i] = RH(0);
-            qh[i] = R(0);
-        }
-    }
-}
-
-// Node of thread s in update J of the chunk at Y (s < width(J) * RR;
-// row-major over the update's rows with the fixed pitch width(J), columns
-// beyond the grown strip idle): unwrapped column x, wrapped xx, row y, and
-// whether the node is the strip's own (it tallies its wall fluxes).
-struct MarchPos {
-    int x, xx, y;
-    bool owned;
-};
-template <class Sh, int J, typename R>
-LBM_HD bool march_pos(const CavityConst<R> &c, const Tile2 &tl, int Y, int s, MarchPos &p) {
-    constexpr int G = Sh::K - J, PW = Sh::width(J);
-    LBM_HOST_CHECK(s >= 0 && s < PW * Sh::CHUNK);
-    const int lx = s % PW, ly = s / PW;
-    if (lx >= tl.w + 2 * G) return false;
-    p.x = tl.x0 - G + lx;
-    p.y = Y + G + ly;  // unwrapped
-    if (p.y < tl.y0 - G || p.y >= tl.y0 + tl.h + G || p.y < 0 || p.y >= c.ny) return false;
-    p.xx = p.x;
-    if (G > 0) {
-        if (c.periodic) p.xx = p.x < 0 ? p.x + c.nx : (p.x >= c.nx ? p.x - c.nx : p.x);
-        else if (p.x < 0 || p.x >= c.nx) return false;
-    }
-    LBM_HOST_CHECK(p.xx >= 0 && p.xx < c.nx);
-    p.owned = G == 0 || (p.x >= tl.x0 && p.x < tl.x0 + tl.w && p.y >= tl.y0 && p.y < tl.y0 + tl.h);
-    return true;
-}
-
-// A node's inputs to an update: its pulled offsets and the previous-step
-// source Sr_f.
-template <typename R, typename RH>
-struct MarchIn {
-    R qf[9], qh[9], sr;
-    RH qg[9];
-};
-
-// First row of a chunk's global accesses.
-LBM_HD int march_first_row(int Y) { return Y > 0 ? Y : 0; }
-
-// The inputs of update 1 of thread s's node in the chunk at Y, from the
-// global state.  The kernel loads them a chunk ahead, so that they are in
-// flight while the current chunk's later updates run.
-template <class Lay, typename R, typename RH, int TW, int RR>
-LBM_HD void march_load(const CavityConst<R> &c, const Tile2 &tl, int Y, const void *src,
-                       const R *__restrict__ sr_src, int s, MarchIn<R, RH> &in) {
-    using Sh = MarchShape<Lay, TW, RR>;
-    MarchPos p;
-    if (!march_pos<Sh, 1>(c, tl, Y, s, p)) return;
-    const NodeGeom g = geometry(c, p.xx, p.y, true);
-    const int yb = march_first_row(Y);
-    const BandOrigin org = band_origin(c, yb);
-    LBM_HOST_CHECK(g.sy - 1 >= yb && g.sy + 1 < org.y_next + c.band_rows);
-    gather_at<Lay, R, RH, true>(c, band_block(c, src, yb / c.band_rows), g, p.xx, p.y, org, in.qf, in.qg, in.qh);
-    in.sr = sr_src[flat_index(c, p.xx, p.y)];
-}
-
-// Update J of thread s's node in the chunk at Y.  Update 1 takes the inputs
-// march_load gave for the same chunk and thread; later updates pull theirs
-// from buffer J - 1 (into in).  Updates before the last write buffer J,
-// the last writes the global state.
-template <class Lay, typename R, typename RH, int TW, int RR, int J>
-LBM_HD void march_update(const CavityConst<R> &c, const Tile2 &tl, int Y, void *dst, R *__restrict__ sr_dst,
-                         double *__restrict__ acc, void *lds_q, R *lds_sr, int s, MarchIn<R, RH> &in) {
-    using Sh = MarchShape<Lay, TW, RR>;
-    constexpr int K = Sh::K;
-    MarchPos p;
-    if (!march_pos<Sh, J>(c, tl, Y, s, p)) return;
-    const NodeGeom g = geometry(c, p.xx, p.y, true);
-    if constexpr (J > 1) {
-        march_gather<Sh, J - 1, R, RH>(c, tl, g, p.x, p.xx, lds_q, in.qf, in.qg, in.qh);
-        in.sr = lds_sr[Sh::sroff(J - 1) + march_slot<Sh, J - 1>(tl, p.x, p.y)];
-    }
-    Thermo<RH> th;
-    Macro<R> m;
-    const RH srf = update_node<Sh::QT, R, RH, true>(c, g, p.xx, p.y, in.qf, in.qg, in.qh, in.sr, p.owned, acc,
-                                                   th, m);
-    const ThermalConst<RH> &t = thermal<RH>(c);
-    if constexpr (J == K) {
-        const int yb = march_first_row(Y);
-        const BandOrigin org = band_origin(c, yb);
-        LBM_HOST_CHECK(p.y >= yb && p.y < org.y_next + c.band_rows);
-        const NodeRef k = org(p.x, p.y);
-        void *blk = band_block(c, dst, yb / c.band_rows);
-        const int64_t stride = c.band_nodes;
-        Lay::template store<R>(blk, stride, 0, in.qf, m.drho, k, c);
-        Lay::template store<RH>(blk, stride, 1, in.qg, t.c_fref * (th.Tf - t.T_ref), k, c);
-        Lay::template store<R>(blk, stride, 2, in.qh, c.c_mref * m.dTm, k, c);
-        sr_dst[flat_index(c, p.x, p.y)] = (R)srf;
-    } else {
-        const int sl = march_slot<Sh, J>(tl, p.x, p.y);
-        LBM_HOST_CHECK(sl >= 0 && sl < Sh::nslot(J));
-        Sh::Codec::put_node((char *)lds_q + Sh::qoff(J), Sh::nslot(J), sl, c, in.qf, in.qg, in.qh, m.drho,
-                            t.c_fref * (th.Tf - t.T_ref), c.c_mref * m.dTm);
-        lds_sr[Sh::sroff(J) + sl] = (R)srf;
-    }
 }
 
 // Macroscopic fields of one node (post-streaming state) plus its

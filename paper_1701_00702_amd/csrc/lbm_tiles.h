@@ -144,10 +144,9 @@ struct StepKTile<ST, 3> : Step3Tile<ST> {};
 // Tile shapes chosen at run time (lbm_launch_config.tile_shape): 0 is the
 // default above; 1 is about twice as wide and half as tall, 2 about half as
 // wide and twice as tall, each within 64 KiB of LDS, 1024 threads and the
-// band rule (TH + 2K <= LBM_MIN_BAND_ROWS); 3 and 4 (three steps per
-// launch only) march strips along y, through LDS (3) or in registers (4).  The autotuner times them: a
+// band rule (TH + 2K <= LBM_MIN_BAND_ROWS).  The autotuner times them: a
 // cavity whose width leaves a narrow last tile in one shape fits another.
-constexpr int kTileShapes = 5;
+constexpr int kTileShapes = 3;
 struct TileDims {
     int tw, th;
 };
@@ -174,63 +173,10 @@ struct StepKTileI {
 template <int ST, int K>
 struct StepKTileI<ST, K, 0> : StepKTile<ST, K> {};
 
-// Tile shape kMarchShape: the marching three-step kernel (MarchShape),
-// strips TW columns wide and at most LBM_MARCH_H rows tall advanced RR rows
-// per chunk, NT threads (one per node of the first update's chunk).  RR is
-// the most rows that leave two workgroups per CU (D2Q9 FP32 forms; three
-// for the 16-bit and D2Q5 forms) within the 160 KiB of LDS; build options
-// LBM_MARCH_* for tuning.
-constexpr int kMarchShape = 3;
-#ifndef LBM_MARCH_H
-#define LBM_MARCH_H 256
-#endif
-#ifndef LBM_MARCH_TW
-#define LBM_MARCH_TW 32
-#endif
-#ifndef LBM_MARCH_RR_F32
-#define LBM_MARCH_RR_F32 8
-#endif
-#ifndef LBM_MARCH_RR_F32H
-#define LBM_MARCH_RR_F32H 7
-#endif
-#ifndef LBM_MARCH_RR_Q5
-#define LBM_MARCH_RR_Q5 6
-#endif
-#ifndef LBM_MARCH_RR_16
-#define LBM_MARCH_RR_16 8
-#endif
-template <int ST>
-struct MarchTile {
-    static constexpr int TW = LBM_MARCH_TW;
-    static constexpr int RR = ST == ST_F32 ? LBM_MARCH_RR_F32
-                              : ST == ST_F32H ? LBM_MARCH_RR_F32H
-                              : (ST == ST5_F32 || ST == ST5_F32H) ? LBM_MARCH_RR_Q5
-                                                                  : LBM_MARCH_RR_16;
-    static constexpr int NT = round64((TW + 4) * RR);
-};
-
-// Tile shape kWaveShape: the wavefront-marching three-step kernel
-// (lbm_wave.h), strips 60 columns wide and at most LBM_WAVE_H rows tall,
-// one per wavefront, LBM_WAVE_NW wavefronts per workgroup.
-constexpr int kWaveShape = 4;
-#ifndef LBM_WAVE_H
-#define LBM_WAVE_H 128
-#endif
-#ifndef LBM_WAVE_NW
-#define LBM_WAVE_NW 2
-#endif
-
-// Width and height of tile shape i of the K-step kernel of storage st
-// (0 x 0: no such shape).
+// Width and height of tile shape i of the K-step kernel of storage st.
 template <int ST, int K>
 constexpr TileDims dims_of(int i) {
-    if (i == 0) return TileDims{StepKTile<ST, K>::TW, StepKTile<ST, K>::TH};
-    if (i < kMarchShape) return alt_dims(ST, K, i);
-    if constexpr (K == 3) {
-        if (i == kMarchShape) return TileDims{MarchTile<ST>::TW, LBM_MARCH_H};
-        if (i == kWaveShape) return TileDims{60, LBM_WAVE_H};
-    }
-    return TileDims{0, 0};
+    return i == 0 ? TileDims{StepKTile<ST, K>::TW, StepKTile<ST, K>::TH} : alt_dims(ST, K, i);
 }
 
 }  // namespace lbm

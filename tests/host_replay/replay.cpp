@@ -15,31 +15,24 @@
 // state buffers (populations, previous-step sources) and the wall tallies
 // must agree bit for bit.  Prints "identical" or the first difference.
 //
-// Tile shape kMarchShape (three steps per launch) emulates the marching
-// kernel strip by strip, chunk by chunk (march_all).
-//
 // Mode "fields": the one-step path only, then the macroscopic fields of
 // every node (u_x, u_y, T_f, T_m, f_l, rho as doubles, [field][ny][nx]) to
 // the given file, for comparison with the oracle.
 //
 // Input on stdin: "key value" lines (the lbm_params fields by name, with
 // wall_type/wall_T as four values; precision f64|f32|f32h64|f16|bf16|
-// f16split|bf16split; mode; K; shape (tile shape index); march_h (strip
-// height of the marching shape, default the library's); launches; steps;
+// f16split|bf16split; mode; K; shape (tile shape index); launches; steps;
 // seed; out), then "end".
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <limits>
-#include <memory>
 #include <string>
 #include <vector>
 
 #include "lbm_node.h"
 #include "lbm_plan.h"
 #include "lbm_tiles.h"
-#include "lbm_wave.h"
 
 static thread_local char g_err[512] = "";
 
@@ -59,7 +52,7 @@ struct Job {
     lbm_params p;
     lbm_precision prec = LBM_F32;
     std::string mode = "kstep", out;
-    int K = 3, launches = 2, steps = 10, shape = 0, march_h = 0;
+    int K = 3, launches = 2, steps = 10, shape = 0;
     uint64_t seed = 1;
 };
 
@@ -108,7 +101,6 @@ bool read_job(Job &j) {
         else if (k == "band_rows") ok = ri(p.band_rows);
         else if (k == "K") ok = scanf("%d", &j.K) == 1;
         else if (k == "shape") ok = scanf("%d", &j.shape) == 1;
-        else if (k == "march_h") ok = scanf("%d", &j.march_h) == 1;
         else if (k == "launches") ok = scanf("%d", &j.launches) == 1;
         else if (k == "steps") ok = scanf("%d", &j.steps) == 1;
         else if (k == "seed") ok = scanf("%llu", (unsigned long long *)&j.seed) == 1;
@@ -172,9 +164,11 @@ void one_step_all(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, 
         }
 }
 
-// One tile of a K-step launch (tile shape I) as an emulated workgroup.
-template <int ST, int K, int I, bool WALLS>
-void k_step_tile(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, int cur, const Tile2 &tl) {
+// One K-step launch over every tile, each tile an emulated workgroup (tile
+// shape I).
+template <int ST, int K, int I>
+void k_step_all(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, int cur,
+                const std::vector<Tile2> &tiles) {
     using Lay = typename LayoutOf<ST>::L;
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
@@ -182,189 +176,29 @@ void k_step_tile(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, i
     constexpr int TW = Tl::TW, TH = Tl::TH, NT = Tl::NT;
     using Sh = StepKShape<Lay, TW, TH, K>;
     static_assert(NT >= Sh::NFIRST, "one thread per node of the first update");
-    // LDS of the workgroup: exactly the kernel's sizes, NaN bit patterns
-    std::vector<unsigned char> lds(Sh::LDS_BYTES, 0xff);
-    std::vector<R> lds_sr(Sh::NSLOT);
-    std::memset(lds_sr.data(), 0xff, lds_sr.size() * sizeof(R));
-    for (int s = 0; s < NT; ++s)
-        if (s < Sh::LW * (tl.h + 2 * Sh::RING))
-            stepk_first<Lay, R, RH, TW, TH, K, WALLS>(c, tl, S.pop[cur].data(), S.sr[cur].data(), S.acc.data(),
-                                                      lds.data(), lds_sr.data(), s);
-    for (int j = K - 2; j >= 1; --j) {
-        std::vector<MidNode<R, RH>> nodes(NT);
-        std::vector<char> act(NT, 0);
-        for (int t = 0; t < NT; ++t)
-            act[t] = t < (TW + 2 * j) * (tl.h + 2 * j) &&
-                     stepk_mid_load<Lay, R, RH, TW, TH, K, WALLS>(c, tl, j, lds.data(), lds_sr.data(), t, nodes[t]);
-        for (int t = 0; t < NT; ++t)
-            if (act[t])
-                stepk_mid_store<Lay, R, RH, TW, TH, K, WALLS>(c, tl, S.acc.data(), lds.data(), lds_sr.data(),
-                                                              nodes[t]);
-    }
-    for (int n = 0; n < NT; ++n)
-        if (n < TW * tl.h)
-            stepk_last<Lay, R, RH, TW, TH, K, WALLS>(c, tl, S.pop[1 - cur].data(), S.sr[1 - cur].data(),
-                                                     S.acc.data(), lds.data(), lds_sr.data(), n);
-}
-
-// One K-step launch over every tile, each tile an emulated workgroup (tile
-// shape I), in the instantiation the kernel takes for it.
-template <int ST, int K, int I>
-void k_step_all(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, int cur,
-                const std::vector<Tile2> &tiles) {
-    using R = typename LayoutOf<ST>::R;
     for (const Tile2 &tl : tiles) {
-        if (tile_interior<R, K>(c, tl)) k_step_tile<ST, K, I, false>(c, S, cur, tl);
-        else k_step_tile<ST, K, I, true>(c, S, cur, tl);
-    }
-}
-
-// One marching three-step launch (tile shape kMarchShape) over every strip,
-// each strip an emulated workgroup with NaN-filled LDS of the kernel's
-// sizes and per-thread registers for the inputs loaded a chunk ahead.
-// Between barriers the threads of a workgroup run in no fixed order; update
-// 1 of a chunk shares a barrier interval with update 3 of the chunk before,
-// and the emulation runs it first, so that an update 1 that overwrote what
-// update 3 still reads would change the result.
-template <int ST>
-void march_all(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, int cur,
-               const std::vector<Tile2> &tiles) {
-    using Lay = typename LayoutOf<ST>::L;
-    using R = typename LayoutOf<ST>::R;
-    using RH = typename LayoutOf<ST>::RH;
-    using Tm = MarchTile<ST>;
-    constexpr int TW = Tm::TW, RR = Tm::RR, NT = Tm::NT;
-    using Sh = MarchShape<Lay, TW, RR>;
-    static_assert(NT >= Sh::NFIRST, "one thread per node of the first update");
-    for (const Tile2 &tl : tiles) {
+        // LDS of the workgroup: exactly the kernel's sizes, NaN bit patterns
         std::vector<unsigned char> lds(Sh::LDS_BYTES, 0xff);
-        std::vector<R> lds_sr(Sh::NSR);
+        std::vector<R> lds_sr(Sh::NSLOT);
         std::memset(lds_sr.data(), 0xff, lds_sr.size() * sizeof(R));
-        std::vector<MarchIn<R, RH>> in(NT);
-        std::memset((void *)in.data(), 0xff, in.size() * sizeof(MarchIn<R, RH>));
-        const void *src = S.pop[cur].data();
-        void *dst = S.pop[1 - cur].data();
-        const R *sr_src = S.sr[cur].data();
-        R *sr_dst = S.sr[1 - cur].data();
-        double *acc = S.acc.data();
-        const int end = tl.y0 + tl.h;
-        const int n1 = Sh::width(1) * RR;
-        auto load = [&](int Y) {
-            for (int t = 0; t < n1; ++t) march_load<Lay, R, RH, TW, RR>(c, tl, Y, src, sr_src, t, in[t]);
-        };
-        auto first = [&](int Y) {  // update 1, then the loads of the next chunk
-            for (int t = 0; t < n1; ++t) {
-                march_update<Lay, R, RH, TW, RR, 1>(c, tl, Y, dst, sr_dst, acc, lds.data(), lds_sr.data(), t, in[t]);
-                if (Y + RR < end) march_load<Lay, R, RH, TW, RR>(c, tl, Y + RR, src, sr_src, t, in[t]);
-            }
-        };
-        int Y = tl.y0 - 2 * (Sh::K - 1);
-        load(Y);
-        first(Y);
-        for (; Y < end; Y += RR) {
-            for (int t = 0; t < Sh::width(2) * RR; ++t) {
-                MarchIn<R, RH> n2;
-                march_update<Lay, R, RH, TW, RR, 2>(c, tl, Y, dst, sr_dst, acc, lds.data(), lds_sr.data(), t, n2);
-            }
-            if (Y + RR < end) first(Y + RR);
-            for (int t = 0; t < TW * RR; ++t) {
-                MarchIn<R, RH> n3;
-                march_update<Lay, R, RH, TW, RR, 3>(c, tl, Y, dst, sr_dst, acc, lds.data(), lds_sr.data(), t, n3);
-            }
+        for (int s = 0; s < NT; ++s)
+            if (s < Sh::LW * (tl.h + 2 * Sh::RING))
+                stepk_first<Lay, R, RH, TW, TH, K>(c, tl, S.pop[cur].data(), S.sr[cur].data(), S.acc.data(),
+                                                   lds.data(), lds_sr.data(), s);
+        for (int j = K - 2; j >= 1; --j) {
+            std::vector<MidNode<R, RH>> nodes(NT);
+            std::vector<char> act(NT, 0);
+            for (int t = 0; t < NT; ++t)
+                act[t] = t < (TW + 2 * j) * (tl.h + 2 * j) &&
+                         stepk_mid_load<Lay, R, RH, TW, TH, K>(c, tl, j, lds.data(), lds_sr.data(), t, nodes[t]);
+            for (int t = 0; t < NT; ++t)
+                if (act[t])
+                    stepk_mid_store<Lay, R, RH, TW, TH, K>(c, tl, S.acc.data(), lds.data(), lds_sr.data(), nodes[t]);
         }
-    }
-}
-
-// A wavefront of 64 lanes on the host: per-lane steps run lane by lane, a
-// lane shift reads the neighbouring lane's value (NaN where a GPU lane
-// would keep a value of its own, so that a result depending on it shows).
-template <typename R, typename RH>
-struct WaveHost {
-    WLane<R, RH> L[kWaveLanes];
-    // this iteration's values, NaN bit patterns until written
-    std::vector<WTemp<R, RH>> temps() {
-        std::vector<WTemp<R, RH>> t(kWaveLanes);
-        std::memset((void *)t.data(), 0xff, t.size() * sizeof(WTemp<R, RH>));
-        return t;
-    }
-    template <class F>
-    void each(std::vector<WTemp<R, RH>> &t, F f) {
-        for (int l = 0; l < kWaveLanes; ++l) f(L[l], t[l]);
-    }
-    template <typename V>
-    static V from(const std::vector<V> &v, int l, int d) {
-        const int s = l - d;
-        return s >= 0 && s < kWaveLanes ? v[s] : std::numeric_limits<V>::quiet_NaN();
-    }
-    template <int QT, class A>
-    void shift(std::vector<WTemp<R, RH>> &t, A a) {
-        for (int i = 1; i < 9; ++i) {
-            const int d = ex_of(i);
-            if (d == 0) continue;
-            std::vector<R> f(kWaveLanes), h(kWaveLanes);
-            std::vector<RH> g(kWaveLanes);
-            for (int l = 0; l < kWaveLanes; ++l) {
-                f[l] = a(L[l], t[l]).f[i];
-                g[l] = a(L[l], t[l]).g[i];
-                h[l] = a(L[l], t[l]).h[i];
-            }
-            for (int l = 0; l < kWaveLanes; ++l) {
-                a(L[l], t[l]).f[i] = from(f, l, d);
-                if (i < QT) {
-                    a(L[l], t[l]).g[i] = from(g, l, d);
-                    a(L[l], t[l]).h[i] = from(h, l, d);
-                }
-            }
-        }
-    }
-    template <int QT, int D, class A, class P>
-    void take(std::vector<WTemp<R, RH>> &t, A a, P pred) {
-        for (int i = 0; i < 9; ++i) {
-            std::vector<R> f(kWaveLanes), h(kWaveLanes);
-            std::vector<RH> g(kWaveLanes);
-            for (int l = 0; l < kWaveLanes; ++l) {
-                f[l] = a(L[l], t[l]).f[i];
-                g[l] = a(L[l], t[l]).g[i];
-                h[l] = a(L[l], t[l]).h[i];
-            }
-            for (int l = 0; l < kWaveLanes; ++l) {
-                if (!pred(L[l])) continue;
-                a(L[l], t[l]).f[i] = from(f, l, D);
-                if (i < QT) {
-                    a(L[l], t[l]).g[i] = from(g, l, D);
-                    a(L[l], t[l]).h[i] = from(h, l, D);
-                }
-            }
-        }
-    }
-};
-
-// One wavefront-marching three-step launch (tile shape kWaveShape): every
-// strip swept by an emulated wavefront whose registers and LDS stash start
-// as NaN bit patterns.
-template <int ST>
-void wave_all(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, int cur,
-              const std::vector<Tile2> &tiles) {
-    using Lay = typename LayoutOf<ST>::L;
-    using R = typename LayoutOf<ST>::R;
-    using RH = typename LayoutOf<ST>::RH;
-    for (const Tile2 &tl : tiles) {
-        auto e = std::make_unique<WaveHost<R, RH>>();
-        auto st = std::make_unique<WStash<R, RH>>();
-        std::memset((void *)e.get(), 0xff, sizeof(WaveHost<R, RH>));
-        std::memset((void *)st.get(), 0xff, sizeof(WStash<R, RH>));
-        for (int l = 0; l < kWaveLanes; ++l) e->L[l].lane = l;
-        WaveArgs<R> a;
-        a.c = &c;
-        a.tl = tl;
-        a.src = S.pop[cur].data();
-        a.dst = S.pop[1 - cur].data();
-        a.sr_src = S.sr[cur].data();
-        a.sr_dst = S.sr[1 - cur].data();
-        a.acc = S.acc.data();
-        a.left_wall = !c.periodic && tl.x0 - 2 <= 0;
-        a.right_wall = !c.periodic && tl.x0 - 2 <= c.nx - 1 && c.nx - 1 <= tl.x0 - 2 + kWaveLanes - 1;
-        wave_sweep<Lay, R, RH>(*e, a, st.get());
+        for (int n = 0; n < NT; ++n)
+            if (n < TW * tl.h)
+                stepk_last<Lay, R, RH, TW, TH, K>(c, tl, S.pop[1 - cur].data(), S.sr[1 - cur].data(), S.acc.data(),
+                                                  lds.data(), lds_sr.data(), n);
     }
 }
 
@@ -435,7 +269,6 @@ int run(const Job &j) {
         }
     }
     if (!tw) return 2;
-    if ((j.shape == kMarchShape || j.shape == kWaveShape) && j.march_h > 0) th = j.march_h;  // strip height under test
     std::vector<Tile2> tiles;
     cavity_tiles2(0, nx, ny, tw, th, tiles);
     State<ST> A = S, B = S;
@@ -454,8 +287,6 @@ int run(const Job &j) {
             if (j.K == 3 && j.shape == 0) k_step_all<ST, 3, 0>(c, B, cb, tiles);
             if (j.K == 3 && j.shape == 1) k_step_all<ST, 3, 1>(c, B, cb, tiles);
             if (j.K == 3 && j.shape == 2) k_step_all<ST, 3, 2>(c, B, cb, tiles);
-            if (j.K == 3 && j.shape == kMarchShape) march_all<ST>(c, B, cb, tiles);
-            if (j.K == 3 && j.shape == kWaveShape) wave_all<ST>(c, B, cb, tiles);
         }
         cb ^= 1;
     }
