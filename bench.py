@@ -44,7 +44,7 @@ FP32_FORM = "f32h64"
 # Algorithmic VALU instructions per node update of the timed forms: those of
 # the one-step kernel (no multi-step ring), counted with rocprofv3
 # (SQ_INSTS_VALU x 64 / node updates) on the 8192^2 cavity.
-ALG_VALU_PER_NODE_STEP = {"f32": 463.3, "f32h64": 485.7}
+ALG_VALU_PER_NODE_STEP = {"f32": 436.3, "f32h64": 468.7}
 # The paper's own timings (Table I, present scheme, quad-core 2.33 GHz CPU;
 # precision and thread count not stated): context only.
 PAPER_TABLE_I = [
@@ -424,21 +424,32 @@ def main():
     if args.workload == "c3" and qt == 9 and not args.no_fp16_store:
         # The metric's FP16-store vs FP32 comparison on the 4096^2 precision
         # workload: the split FP16 form against the FP32 forms, default launch.
-        fp16 = {"workload": workload("c4")[3]}
+        # Also with one and two steps per launch: where a launch is bound by
+        # HBM (one step) the 16-bit store pays; with three it is bound by
+        # instruction issue and the codec costs more than the bytes save.
+        fp16 = {"workload": workload("c4")[3], "by_steps_per_launch": {}}
         for pr in ("f16split", "f32h64", "f32"):
             ps, sd, _, _ = workload("c4")
             s2, ws2 = make_solver(lbm, torch, ps, pr, stream)
             s2.set_initial(0, *W.initial_temperatures(ps[0], sd))
             n2 = ps[0]["nx"] * ps[0]["ny"]
-            sp2 = lbm.lbm_get_launch(s2.h)["steps_per_launch"]
-            t = time_steps(lbm, torch, s2, stream, 96, 12) / 96
-            fp16[pr] = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t, "steps_per_launch": sp2,
-                        "bytes_per_node_step": bytes_per_node(pr),
-                        "alg_GBps_per_launch": bytes_per_node(pr) * n2 / (t * sp2 * 1e-3) / 1e9}
+            l2 = lbm.lbm_get_launch(s2.h)
+            for k in (l2["steps_per_launch"], 2, 1):
+                lbm.lbm_set_launch(s2.h, l2["block"], l2["nodes_per_thread"], l2["xcd_remap"], l2["persistent"],
+                                   steps_per_launch=k, tile_shape=0)
+                t = time_steps(lbm, torch, s2, stream, 96, 12) / 96
+                rec = {"MLUPS": n2 / (t * 1e-3) / 1e6, "ms_per_step": t, "steps_per_launch": k,
+                       "bytes_per_node_step": bytes_per_node(pr),
+                       "alg_GBps_per_launch": bytes_per_node(pr) * n2 / (t * k * 1e-3) / 1e9}
+                if k == l2["steps_per_launch"]:
+                    fp16[pr] = rec
+                fp16["by_steps_per_launch"].setdefault(str(k), {})[pr] = rec["MLUPS"]
             s2.close()
             del ws2
             torch.cuda.empty_cache()
         fp16["f16split_over_f32h64"] = fp16["f16split"]["MLUPS"] / fp16["f32h64"]["MLUPS"]
+        for k, v in fp16["by_steps_per_launch"].items():
+            v["f16split_over_f32"] = v["f16split"] / v["f32"]
         out["fp16_store_vs_fp32"] = fp16
 
     if args.forms:

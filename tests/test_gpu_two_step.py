@@ -148,7 +148,7 @@ def test_every_tile_shape_is_bitwise_single_steps(lbm, spl, form, shape):
 def test_tile_shape_reported_and_validated(lbm):
     s = lbm.Solver(W.scaled_cavity(_c1(), 50, 40), "f32h64")
     cfg = lbm.lbm_get_launch(s.h)
-    assert (cfg["steps_per_launch"], cfg["tile_shape"], cfg["tile_w"], cfg["tile_h"]) == (3, 0, 32, 8)
+    assert (cfg["steps_per_launch"], cfg["tile_shape"], cfg["tile_w"], cfg["tile_h"]) == (3, 0, 32, 10)
     lbm.lbm_set_launch(s.h, 512, 1, 1, 0, steps_per_launch=3, tile_shape=1)
     cfg = lbm.lbm_get_launch(s.h)
     assert (cfg["tile_shape"], cfg["tile_w"], cfg["tile_h"]) == (1, 64, 4)
