@@ -289,19 +289,32 @@ struct PlainH64 {
 // stay close to w_i beta, so their remainders are small and 16 bits keep
 // them to ~1e-3 (binary16) or ~8e-3 (bfloat16) relative, while the
 // conserved content (rest population, base) keeps FP32 precision.
-// Planes: 6 FP32 planes [q_f0, beta_f, q_g0, beta_g, q_h0, beta_h], then 24
-// 16-bit planes [field][direction 1..8]; 72 bytes per node.
+// Planes: 6 FP32 planes [q_f0, b_f, q_g0, b_g, q_h0, b_h] with b = w_1 beta
+// (the axis weight 1/9 times the base), then 24 16-bit planes
+// [field][direction 1..8]; 72 bytes per node.
 // The split codec's arithmetic, shared by the global layout and its LDS
 // copy: a population is w_i beta + r / s (r the 16-bit remainder, s the
-// field's power-of-two scale), decoded with one fused multiply-add, and
-// encoded as the remainder q s - (w_i s) beta, one fused multiply-add.
+// field's power-of-two scale).  With w_i beta = c_i b, c_i = 1 on the axes
+// and 1/4 on the diagonals (exact), an axis population decodes with one
+// fused multiply-add and a diagonal one with two operations, and a field's
+// eight remainders q s - (c_i s) b take one fused multiply-add each after
+// two products per field.  Rounding b once and scaling it by powers of two
+// gives the same bits as rounding w_i beta per direction.
 template <typename V>
-LBM_HD V split_dec(int i, V beta, V r, V inv_scale) {
-    return fma_of(r, inv_scale, w_of<V>(i) * beta);
+__host__ __device__ constexpr V split_c(int i) {
+    return i <= 4 ? V(1) : V(0.25);
 }
 template <typename V>
-LBM_HD float split_rem(int i, V q, V beta, V scale) {
-    return (float)fma_of(q, scale, -(w_of<V>(i) * scale) * beta);
+LBM_HD V split_base(V beta) {
+    return w_of<V>(1) * beta;
+}
+template <typename V>
+LBM_HD V split_dec(int i, V b, V r, V inv_scale) {
+    return fma_of(r, inv_scale, split_c<V>(i) * b);
+}
+template <typename V>
+LBM_HD float split_rem(int i, V q, V b, V scale) {
+    return (float)fma_of(q, scale, -(split_c<V>(i) * scale) * b);
 }
 
 template <class ER>
@@ -312,22 +325,22 @@ struct SplitT {
     LBM_HD static V load(const void *base, int64_t stride, int f, int i, K k, const CavityConst<R> &c) {
         const float *P = (const float *)base;
         if (i == 0) return (V)ld_stream(at(P + (int64_t)(2 * f) * stride, k));
-        const V beta = (V)ld_stream(at(P + (int64_t)(2 * f + 1) * stride, k));
+        const V b = (V)ld_stream(at(P + (int64_t)(2 * f + 1) * stride, k));
         const uint16_t *Qp = (const uint16_t *)(P + 6 * stride);
         const V r = (V)ER::dec(ld_stream(at(Qp + (int64_t)(8 * f + i - 1) * stride, k)));
-        return split_dec<V>(i, beta, r, (V)c.inv_scale[f]);
+        return split_dec<V>(i, b, r, (V)c.inv_scale[f]);
     }
     template <typename V, typename R, typename K>
     LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, K k,
                              const CavityConst<R> &c) {
         float *P = (float *)base;
-        const float e0 = (float)q[0], eb = (float)beta;
+        const float e0 = (float)q[0], eb = (float)split_base<V>(beta);
         st_stream(at_store(P, 2 * f, stride, k, e0), e0);
         st_stream(at_store(P, 2 * f + 1, stride, k, eb), eb);
         uint16_t *Qp = (uint16_t *)(P + 6 * stride);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const uint16_t e = ER::enc(split_rem<V>(i, q[i], beta, (V)c.scale[f]));
+            const uint16_t e = ER::enc(split_rem<V>(i, q[i], (V)eb, (V)c.scale[f]));
             st_stream(at_store(Qp, 8 * f + i - 1, stride, k, e), e);
         }
     }
@@ -1189,11 +1202,12 @@ struct LdsCodec<SplitT<ER>> {
                                  const CavityConst<R> &c) {
         float *P = (float *)lds;
         uint16_t *Qp = (uint16_t *)(P + 6 * nslot);
+        const float b = (float)split_base<V>(beta);
         P[(2 * f) * nslot + slot] = (float)q[0];
-        P[(2 * f + 1) * nslot + slot] = (float)beta;
+        P[(2 * f + 1) * nslot + slot] = b;
 #pragma unroll
         for (int i = 1; i < 9; ++i)
-            Qp[(8 * f + i - 1) * nslot + slot] = ER::enc(split_rem<V>(i, q[i], beta, (V)c.scale[f]));
+            Qp[(8 * f + i - 1) * nslot + slot] = ER::enc(split_rem<V>(i, q[i], (V)b, (V)c.scale[f]));
     }
     template <typename R, typename RH>
     LBM_HD static void put_node(void *lds, int nslot, int slot, const CavityConst<R> &c, const R qf[9],
@@ -1206,10 +1220,10 @@ struct LdsCodec<SplitT<ER>> {
     LBM_HD static V get(const void *lds, int nslot, int f, int i, int slot, const CavityConst<R> &c) {
         const float *P = (const float *)lds;
         if (i == 0) return (V)P[(2 * f) * nslot + slot];
-        const V beta = (V)P[(2 * f + 1) * nslot + slot];
+        const V b = (V)P[(2 * f + 1) * nslot + slot];
         const uint16_t *Qp = (const uint16_t *)(P + 6 * nslot);
         const V r = (V)ER::dec(Qp[(8 * f + i - 1) * nslot + slot]);
-        return split_dec<V>(i, beta, r, (V)c.inv_scale[f]);
+        return split_dec<V>(i, b, r, (V)c.inv_scale[f]);
     }
 };
 

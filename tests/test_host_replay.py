@@ -44,8 +44,9 @@ def _binary():
         os.makedirs(BUILD, exist_ok=True)
         flags = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
                  "-fsanitize=address,undefined", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + CSRC]
-        subprocess.check_call([CXX] + flags + ["-o", exe + ".tmp", SRC])
-        os.replace(exe + ".tmp", exe)
+        tmp = f"{exe}.tmp{os.getpid()}"  # parallel test workers each build their own, then rename
+        subprocess.check_call([CXX] + flags + ["-o", tmp, SRC])
+        os.replace(tmp, exe)
     return exe
 
 
