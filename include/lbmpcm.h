@@ -64,9 +64,10 @@ typedef enum {
  *   LBM_BF16_OFFSET    the offsets in bfloat16 (54)
  *   LBM_F16_SPLIT      per field the rest population and one base value
  *                      (flow: density offset; enthalpy: c_f,ref (T_f - T_ref);
- *                      metal: c_m,ref (T_m - T_ref)) in FP32, and the eight
- *                      moving populations as binary16 remainders from the rest
- *                      equilibrium of that base (72 bytes per node)
+ *                      metal: c_m,ref (T_m - T_ref)), stored times the axis
+ *                      weight 1/9, in FP32, and the eight moving populations
+ *                      as binary16 remainders from the rest equilibrium of
+ *                      that base (72 bytes per node)
  *   LBM_BF16_SPLIT     as LBM_F16_SPLIT with bfloat16 remainders (72)
  *   LBM_F32_H64        as LBM_F32, except the rest population of the enthalpy
  *                      field, which carries H itself, in FP64; that population,
@@ -323,7 +324,8 @@ lbm_status lbm_autotune(lbm_handle *h, int32_t steps_per_trial, const char *cach
 
 /* Write / read the complete state (populations, previous-step sources,
  * wall tallies, step count) to a file; resuming is bit-exact.  lbm_load
- * requires a handle created with the same cavities and precision. */
+ * requires a handle created with the same cavities and precision, and a
+ * file of this library's format (LBM_EIO otherwise). */
 lbm_status lbm_save(lbm_handle *h, const char *path);
 lbm_status lbm_load(lbm_handle *h, const char *path);
 

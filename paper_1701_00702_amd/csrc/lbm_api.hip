@@ -1049,7 +1049,8 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
 // Checkpoints
 // ---------------------------------------------------------------------------
 namespace {
-const char kMagic[8] = {'L', 'B', 'M', 'P', 'C', 'M', '0', '1'};
+// 02: the split 16-bit forms store their base times the axis weight
+const char kMagic[8] = {'L', 'B', 'M', 'P', 'C', 'M', '0', '2'};
 
 struct CkptHeader {
     char magic[8];
