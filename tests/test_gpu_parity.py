@@ -180,23 +180,31 @@ def test_launch_shapes_bitwise_and_deterministic(lbm):
             assert d["flux_E"] == ref[1]["flux_E"]
 
 
-def test_save_resume_bitwise(lbm):
+@pytest.mark.parametrize("prec", ["f64", "f16split", "bf16split"])
+def test_save_resume_bitwise(lbm, prec):
     p = W.scaled_cavity(W.case_c1()[0], 40, 36)
     T_pcm, T_mf = W.initial_temperatures(p, 2)
-    a = lbm.Solver(p, "f64")
+    a = lbm.Solver(p, prec)
     a.set_initial(0, T_pcm, T_mf)
     a.step(120)
-    b = lbm.Solver(p, "f64")
+    b = lbm.Solver(p, prec)
     b.set_initial(0, T_pcm, T_mf)
     b.step(55)
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "ck.bin")
         lbm.lbm_save(b.h, path)
-        c = lbm.Solver(p, "f64")
+        c = lbm.Solver(p, prec)
         lbm.lbm_load(c.h, path)
         assert lbm.lbm_step_count(c.h) == 55
         c.step(65)
-    assert np.array_equal(a.state().view(np.uint64), c.state().view(np.uint64))
+        # a file of another format is refused and leaves the handle alone
+        bad = os.path.join(d, "bad.bin")
+        with open(path, "rb") as f, open(bad, "wb") as g:
+            g.write(b"LBMPCM01" + f.read()[8:])
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_load(c.h, bad)
+        assert e.value.status == lbm.LBM_EIO
+    assert np.array_equal(a.state().view(np.uint8), c.state().view(np.uint8))
     assert a.diagnostics()["flux_E"] == c.diagnostics()["flux_E"]
     for s in (a, b, c):
         s.close()
