@@ -2,7 +2,9 @@
 few rows (every step-kernel tile then crosses band boundaries, and the
 multi-step tiles' rings reach into the next band) must give the same
 populations, sources, wall tallies and diagnostics, bit for bit, as the
-same cavity stored in one band, with one, two and three steps per launch."""
+same cavity stored in one band, with one, two and three steps per launch;
+and the longest rows accepted, whose bands are the largest blocks the
+kernels' 32-bit offsets reach."""
 import numpy as np
 import pytest
 
@@ -69,3 +71,30 @@ def test_bands_give_the_same_bits(lbm, case, qt, prec, spl):
         for k in ("flux_E", "flux_M", "E_int", "M_int", "liquid_fraction", "Nu_hot", "nonfinite"):
             assert da[k] == db[k], k
         assert db["nonfinite"] == 0
+
+
+def test_longest_rows(lbm):
+    # Rows of the greatest accepted length (262 144 nodes: a tile addresses
+    # two band blocks by 32-bit offsets) over 70 rows, so the blocks are about
+    # 2 GB and the multi-step tiles cross them: three steps per launch bit for
+    # bit against single steps, and the FP64 oracle after 9 steps.
+    import oracle
+    from test_gpu_parity import field_errors
+    p = dict(W.scaled_cavity(_c1(), 262144, 70), L_char=127.0)
+    T = W.initial_temperatures(p, 4)
+    out = []
+    for spl in (1, 3):
+        s = lbm.Solver(p, "f32h64")
+        cfg = lbm.lbm_get_launch(s.h)
+        lbm.lbm_set_launch(s.h, cfg["block"], cfg["nodes_per_thread"], cfg["xcd_remap"], 0, steps_per_launch=spl)
+        s.set_initial(0, *T)
+        s.step(9)
+        out.append((s.state().copy(), s.fields()))
+        s.close()
+    assert np.array_equal(out[0][0].view(np.uint8), out[1][0].view(np.uint8))
+    o = oracle.Oracle(p)
+    o.set_initial(*T)
+    o.step(9)
+    e = field_errors(out[1][1], o.fields(), p)
+    del o
+    assert max(e["T_pcm"], e["T_mf"], e["f_l"], e["rho"]) < 1e-5, e
