@@ -76,7 +76,7 @@ def test_bands_give_the_same_bits(lbm, case, qt, prec, spl):
 def test_longest_rows(lbm):
     # Rows of the greatest accepted length (262 144 nodes: a tile addresses
     # two band blocks by 32-bit offsets) over 70 rows, so the blocks are about
-    # 2 GB and the multi-step tiles cross them: three steps per launch bit for
+    # 1 GB and the multi-step tiles cross them: three steps per launch bit for
     # bit against single steps, and the FP64 oracle after 9 steps.
     import oracle
     from test_gpu_parity import field_errors
