@@ -220,7 +220,13 @@ lbm_status lbm_create(const lbm_params *p, lbm_precision prec, lbm_handle **out)
 lbm_status lbm_create_batch(const lbm_params *p, int32_t n_cavities, lbm_precision prec,
                             lbm_handle **out);
 
-/* Device bytes lbm_create_ext needs for the same cavities and precision. */
+/* Device bytes lbm_create_ext needs for the same cavities and precision:
+ * the two state buffers (the bytes per node of lbm_precision), the two
+ * interstitial-source planes (4 bytes per node, 8 with LBM_F64), the tile
+ * tables and wall tallies, and a staging area of at most 2^22 nodes (or one
+ * row of the widest cavity) times six doubles that lbm_set_initial and
+ * lbm_fields pass whole rows through; no per-node scratch beyond that, so
+ * the state buffers can fill nearly all of the GPU's memory. */
 lbm_status lbm_workspace_bytes(const lbm_params *p, int32_t n_cavities, lbm_precision prec,
                                uint64_t *bytes);
 
@@ -270,6 +276,13 @@ int64_t lbm_step_count(const lbm_handle *h);
 lbm_status lbm_fields(lbm_handle *h, int32_t cavity, double *ux, double *uy, double *T_pcm,
                       double *T_mf, double *f_l, double *rho);
 
+/* The same fields for rows [y0, y0 + rows) of the cavity only: each
+ * non-NULL pointer receives double[rows][nx], row y0 first.  For reading
+ * parts of cavities too large for a host copy of every field.  LBM_EINVAL
+ * unless 0 <= y0 and 1 <= rows <= ny - y0.  Synchronises the stream. */
+lbm_status lbm_fields_rows(lbm_handle *h, int32_t cavity, int32_t y0, int32_t rows, double *ux,
+                           double *uy, double *T_pcm, double *T_mf, double *f_l, double *rho);
+
 /* FP64 diagnostics of one cavity (deterministic reductions).  The paper
  * defines none of these quantities; the definitions are this library's:
  * liquid fraction = mean f_l (Eq. 39) over interior nodes; melt front = the
@@ -280,8 +293,9 @@ lbm_status lbm_fields(lbm_handle *h, int32_t cavity, double *ux, double *uy, dou
  * k_e = phi k_f + (1 - phi) k_m (Eq. 8); energy phi rho_l H + (1 - phi)
  * rho_m c_pm T_m (Eqs. 37, 48) and density summed over interior nodes, with
  * the link fluxes across each wall tallied every step.  Uses the handle's
- * workspace (field planes, partial sums) as scratch.  Synchronises the
- * stream.  Returns LBM_ENONFINITE, with *out filled, when the state holds
+ * workspace (per-workgroup partial sums, the temperatures of the three
+ * columns next to each vertical wall, the middle row's liquid fraction) as
+ * scratch.  Synchronises the stream.  Returns LBM_ENONFINITE, with *out filled, when the state holds
  * NaN/Inf. */
 lbm_status lbm_diagnostics(lbm_handle *h, int32_t cavity, lbm_diag *out);
 
@@ -295,10 +309,8 @@ lbm_status lbm_diagnostics(lbm_handle *h, int32_t cavity, lbm_diag *out);
  * 32768 are rejected with LBM_EINVAL.  Every call writes each scratch
  * element it reads, so nothing carries over between calls; calls that
  * overlap on one GPU (several host threads, or streams running at once)
- * share that array and race.  The per-node values and the Nusselt numbers
- * and melt front are those of lbm_diagnostics bit for bit; the sums over
- * nodes (energy, density, liquid fraction, fluxes) run in another order and
- * agree to rounding.  Synchronises the stream. */
+ * share that array and race.  Runs the kernels of lbm_diagnostics, so the
+ * results are the same bit for bit.  Synchronises the stream. */
 lbm_status lbm_diagnostics_noalloc(lbm_handle *h, int32_t cavity, lbm_diag *out);
 
 /* Derived lattice constants of one cavity. */

@@ -103,14 +103,23 @@ struct Plan {
     int64_t pop_bytes = 0;     // one state buffer
     // nodes: packed index range of the flat per-node arrays (stride each)
     int64_t nodes = 0, stride = 0, slots = 0, max_nodes = 0;
+    int max_nx = 0, max_ny = 0;
+    // nodes of the staging area that lbm_fields and lbm_set_initial pass
+    // whole rows of a cavity through (at least one row of the widest cavity)
+    int64_t stage_nodes = 0;
     int max_tiles = 0;
     // tiles of the K-step kernels, K = 2, 3: room for the largest count over
     // the tile shapes (0: not available for this storage)
     int64_t tilesk[4] = {0, 0, 0, 0};
     size_t off_tilesk[4] = {0, 0, 0, 0};
-    size_t off_pop[2], off_sr[2], off_acc, off_accs, off_cav, off_tiles, off_fields, off_part,
-        off_out, total;
+    size_t off_pop[2], off_sr[2], off_acc, off_accs, off_cav, off_tiles, off_fields, off_part, off_tf,
+        off_tm, off_fl, off_out, total;
 };
+
+// Nodes staged at once: field planes and initial temperatures move between
+// host and device in runs of whole rows of at most this many nodes, so the
+// staging area stays a small part of the memory however large a cavity is.
+constexpr int64_t kStageNodes = (int64_t)1 << 22;
 
 lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
     if (!p) return fail(LBM_EINVAL, "params is NULL");
@@ -137,6 +146,8 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
         pl.nodes += (nn + 63) & ~(int64_t)63;
         pl.slots += 2 * ((int64_t)p[c].nx + p[c].ny);
         pl.max_nodes = std::max(pl.max_nodes, nn);
+        pl.max_nx = std::max(pl.max_nx, p[c].nx);
+        pl.max_ny = std::max(pl.max_ny, p[c].ny);
         // interior rows and the wall ring, in tiles of at least 64 nodes
         const int64_t pitch = (p[c].nx + 63) & ~63;
         tiles += (pitch * (p[c].ny - 2) + 63) / 64 + 1 + 2 * (((int64_t)p[c].nx + 63) / 64);
@@ -185,11 +196,17 @@ lbm_status make_plan(const lbm_params *p, int n, lbm_precision prec, Plan &pl) {
         pl.off_tilesk[k] = off;
         off = align256(off + (size_t)pl.tilesk[k] * sizeof(Tile2));
     }
+    pl.stage_nodes = std::max<int64_t>(std::min(pl.max_nodes, kStageNodes), pl.max_nx);
     pl.off_fields = off;
-    off = align256(off + (size_t)6 * pl.max_nodes * sizeof(double));
+    off = align256(off + (size_t)6 * pl.stage_nodes * sizeof(double));
     pl.off_part = off;
-    off = align256(off + (size_t)macro_blocks((int)std::min<int64_t>(pl.max_nodes, INT32_MAX), 1) * NPART * sizeof(double) +
-                   (size_t)NPART * sizeof(double) * 64);
+    off = align256(off + (size_t)LBM_DIAG_MAX_BLOCKS * NPART * sizeof(double));
+    pl.off_tf = off;
+    off = align256(off + (size_t)pl.max_ny * 6 * sizeof(double));
+    pl.off_tm = off;
+    off = align256(off + (size_t)pl.max_ny * 6 * sizeof(double));
+    pl.off_fl = off;
+    off = align256(off + (size_t)pl.max_nx * sizeof(double));
     pl.off_out = off;
     off = align256(off + 64 * sizeof(double));
     pl.total = off;
@@ -236,8 +253,12 @@ struct lbm_handle {
     Tile *dtiles() { return (Tile *)(ws + pl.off_tiles); }
     Tile2 *dtilesk(int k) { return (Tile2 *)(ws + pl.off_tilesk[k]); }
     double *fields() { return (double *)(ws + pl.off_fields); }
-    double *partials() { return (double *)(ws + pl.off_part); }
     double *dout() { return (double *)(ws + pl.off_out); }
+    // rows of cavity c that fit the staging area at once
+    int stage_rows(int c) const {
+        const lbm_params &p = params[c];
+        return (int)std::min<int64_t>(p.ny, std::max<int64_t>(1, pl.stage_nodes / p.nx));
+    }
 };
 
 namespace {
@@ -447,36 +468,37 @@ DiagLaunch diag_args(lbm_handle *h, int c, const double *partials, int nblocks, 
     return D;
 }
 
-// Run the diagnostics kernels for cavity c; results land in h->dout() and
-// the six field planes in h->fields().
-lbm_status run_macro(lbm_handle *h, int c, bool with_diag) {
+// The diagnostics kernels of cavity c, their scratch at the given device
+// addresses: per-workgroup partial sums, the temperatures of the columns
+// next to the vertical walls, the middle row's liquid fraction, and the
+// NDIAG results in out.
+lbm_status launch_diagnostics(lbm_handle *h, int c, char *part, char *tf, char *tm, char *fl, char *out) {
     const lbm_params &p = h->params[c];
-    MacroLaunch M;
+    DiagNodeLaunch M;
     M.storage = h->st;
     M.raw = h->step == 0 ? 1 : 0;
     M.cav_index = c;
     M.src = h->pop(h->cur);
     M.cav = h->cav();
-    M.fields = h->fields();
-    M.partials = h->partials();
-    M.nblocks = macro_blocks(p.nx, p.ny);
-    HIP_TRY(launch_macro(M, p.nx, p.ny, h->stream));
-    if (with_diag) {
-        const int64_t nn = (int64_t)p.nx * p.ny;
-        DiagLaunch D = diag_args(h, c, h->partials(), M.nblocks, h->dout());
-        D.tf = h->fields() + 2 * nn;
-        D.tm = h->fields() + 3 * nn;
-        D.fl_mid = h->fields() + 4 * nn + (int64_t)(p.ny / 2) * p.nx;
-        D.rs = p.nx;
-        const int cx[6] = {0, 1, 2, p.nx - 3, p.nx - 2, p.nx - 1};
-        for (int k = 0; k < 6; ++k) D.cx[k] = cx[k];
-        HIP_TRY(launch_diag(D, p.nx, p.ny, h->stream));
-    }
+    M.partials = (double *)part;
+    M.nblocks = diag_node_blocks(p.nx, p.ny);
+    M.tf = (double *)tf;
+    M.tm = (double *)tm;
+    M.fl_mid = (double *)fl;
+    HIP_TRY(launch_diag_nodes(M, p.nx, p.ny, h->stream));
+    DiagLaunch D = diag_args(h, c, M.partials, M.nblocks, (double *)out);
+    D.tf = M.tf;
+    D.tm = M.tm;
+    D.fl_mid = M.fl_mid;
+    HIP_TRY(launch_diag(D, p.nx, p.ny, h->stream));
     return LBM_OK;
 }
 
+// Diagnostics of cavity c with the workspace as scratch, copied to out.
 lbm_status read_diag(lbm_handle *h, int c, double out[NDIAG]) {
-    lbm_status s = run_macro(h, c, true);
+    char *w = h->ws;
+    lbm_status s = launch_diagnostics(h, c, w + h->pl.off_part, w + h->pl.off_tf, w + h->pl.off_tm,
+                                      w + h->pl.off_fl, w + h->pl.off_out);
     if (s != LBM_OK) return s;
     HIP_TRY(hipMemcpyAsync(out, h->dout(), NDIAG * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -485,19 +507,29 @@ lbm_status read_diag(lbm_handle *h, int c, double out[NDIAG]) {
 
 lbm_status init_cavity(lbm_handle *h, int c, const double *T_pcm, const double *T_mf) {
     const lbm_params &p = h->params[c];
-    const int64_t nn = (int64_t)p.nx * p.ny;
+    const int chunk = h->stage_rows(c);
     double *dT = h->fields();  // staging for the temperature arrays
-    if (T_pcm) HIP_TRY(hipMemcpyAsync(dT, T_pcm, nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    if (T_mf) HIP_TRY(hipMemcpyAsync(dT + nn, T_mf, nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    InitLaunch I;
-    I.storage = h->st;
-    I.cav_index = c;
-    I.cav = h->cav();
-    I.dst = h->pop(h->cur);
-    I.sr = h->sr(h->cur);
-    I.T_pcm = T_pcm ? dT : nullptr;
-    I.T_mf = T_mf ? dT + nn : nullptr;
-    HIP_TRY(launch_init(I, p.nx, p.ny, h->stream));
+    // runs of whole rows through the staging area; stream order keeps a
+    // run's copies behind the previous run's kernel
+    for (int y0 = 0; y0 < p.ny; y0 += chunk) {
+        const int rows = std::min(chunk, p.ny - y0);
+        const int64_t nn = (int64_t)p.nx * rows, o = (int64_t)p.nx * y0;
+        if (T_pcm)
+            HIP_TRY(hipMemcpyAsync(dT, T_pcm + o, nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        if (T_mf)
+            HIP_TRY(hipMemcpyAsync(dT + nn, T_mf + o, nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        InitLaunch I;
+        I.storage = h->st;
+        I.cav_index = c;
+        I.cav = h->cav();
+        I.dst = h->pop(h->cur);
+        I.sr = h->sr(h->cur);
+        I.y0 = y0;
+        I.rows = rows;
+        I.T_pcm = T_pcm ? dT : nullptr;
+        I.T_mf = T_mf ? dT + nn : nullptr;
+        HIP_TRY(launch_init(I, p.nx, p.ny, h->stream));
+    }
     const int64_t a0 = h->pl.acc0[c], ns = 2 * ((int64_t)p.nx + p.ny);
     HIP_TRY(hipMemsetAsync(h->acc() + 2 * a0, 0, ns * 2 * sizeof(double), h->stream));
     double d[NDIAG];
@@ -743,20 +775,42 @@ extern "C" lbm_status lbm_synchronize(lbm_handle *h) {
 
 extern "C" int64_t lbm_step_count(const lbm_handle *h) { return h ? h->step : -1; }
 
+extern "C" lbm_status lbm_fields_rows(lbm_handle *h, int32_t c, int32_t y0, int32_t rows, double *ux,
+                                      double *uy, double *T_pcm, double *T_mf, double *f_l, double *rho) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
+    const lbm_params &p = h->params[c];
+    if (y0 < 0 || rows < 1 || rows > p.ny - y0)
+        return fail(LBM_EINVAL, "rows [%d, %d + %d) outside the cavity's %d rows", y0, y0, rows, p.ny);
+    const int chunk = h->stage_rows(c);
+    double *outs[6] = {ux, uy, T_pcm, T_mf, f_l, rho};
+    for (int r0 = 0; r0 < rows; r0 += chunk) {
+        const int nr = std::min(chunk, rows - r0);
+        MacroLaunch M;
+        M.storage = h->st;
+        M.raw = h->step == 0 ? 1 : 0;
+        M.cav_index = c;
+        M.src = h->pop(h->cur);
+        M.cav = h->cav();
+        M.y0 = y0 + r0;
+        M.rows = nr;
+        M.fields = h->fields();
+        HIP_TRY(launch_macro(M, p.nx, p.ny, h->stream));
+        const int64_t nn = (int64_t)p.nx * nr;
+        for (int k = 0; k < 6; ++k)
+            if (outs[k])
+                HIP_TRY(hipMemcpyAsync(outs[k] + (int64_t)p.nx * r0, h->fields() + k * nn, nn * sizeof(double),
+                                       hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
 extern "C" lbm_status lbm_fields(lbm_handle *h, int32_t c, double *ux, double *uy, double *T_pcm,
                                  double *T_mf, double *f_l, double *rho) {
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     if (c < 0 || c >= h->n) return fail(LBM_EINVAL, "cavity %d out of range", c);
-    lbm_status s = run_macro(h, c, false);
-    if (s != LBM_OK) return s;
-    const int64_t nn = (int64_t)h->params[c].nx * h->params[c].ny;
-    double *outs[6] = {ux, uy, T_pcm, T_mf, f_l, rho};
-    for (int k = 0; k < 6; ++k)
-        if (outs[k])
-            HIP_TRY(hipMemcpyAsync(outs[k], h->fields() + k * nn, nn * sizeof(double), hipMemcpyDeviceToHost,
-                                   h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return LBM_OK;
+    return lbm_fields_rows(h, c, 0, h->params[c].ny, ux, uy, T_pcm, T_mf, f_l, rho);
 }
 
 namespace {
@@ -812,25 +866,8 @@ extern "C" lbm_status lbm_diagnostics_noalloc(lbm_handle *h, int32_t c, lbm_diag
     lbm_status s = noalloc_scratch(h->device, &scr);
     if (s != LBM_OK) return s;
     char *base = (char *)scr;
-    DiagNodeLaunch M;
-    M.storage = h->st;
-    M.raw = h->step == 0 ? 1 : 0;
-    M.cav_index = c;
-    M.src = h->pop(h->cur);
-    M.cav = h->cav();
-    M.partials = (double *)(base + kScrPart);
-    M.nblocks = diag_node_blocks(p.nx, p.ny);
-    M.tf = (double *)(base + kScrTf);
-    M.tm = (double *)(base + kScrTm);
-    M.fl_mid = (double *)(base + kScrFl);
-    HIP_TRY(launch_diag_nodes(M, p.nx, p.ny, h->stream));
-    DiagLaunch D = diag_args(h, c, M.partials, M.nblocks, (double *)(base + kScrOut));
-    D.tf = M.tf;
-    D.tm = M.tm;
-    D.fl_mid = M.fl_mid;
-    D.rs = 6;
-    for (int k = 0; k < 6; ++k) D.cx[k] = k;
-    HIP_TRY(launch_diag(D, p.nx, p.ny, h->stream));
+    s = launch_diagnostics(h, c, base + kScrPart, base + kScrTf, base + kScrTm, base + kScrFl, base + kScrOut);
+    if (s != LBM_OK) return s;
     double d[NDIAG];
     HIP_TRY(hipMemcpyAsync(d, base + kScrOut, NDIAG * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));

@@ -138,15 +138,15 @@ struct Step2Launch {
     int ntiles;
 };
 
+// Macroscopic fields of rows [y0, y0 + rows) of one cavity.
 struct MacroLaunch {
     int storage;
     int raw;  // 1: populations are post-streaming already (step 0)
     int cav_index;
     const void *src;
     const void *cav;     // CavityConst<R>[]
-    double *fields;      // 6 planes of nx*ny doubles: ux, uy, T_f, T_m, f_l, rho
-    double *partials;    // [nblocks][NPART]
-    int nblocks;
+    int y0, rows;
+    double *fields;      // 6 planes of rows*nx doubles: ux, uy, T_f, T_m, f_l, rho
 };
 
 // Per-block partial sums of the diagnostics kernel.
@@ -171,12 +171,9 @@ struct DiagLaunch {
     double L, ke, kf, km, dT;  // kf = phi k_f, km = (1-phi) k_m, ke = kf + km
     // T_f and T_m of the three columns next to each vertical wall, and f_l of
     // the middle row (y = ny / 2): the value at column k (k = 0..5 for
-    // x = 0, 1, 2, nx - 3, nx - 2, nx - 1) of row y is tf[y * rs + cx[k]];
-    // fl_mid[x] for x in [0, nx).  Full field planes (rs = nx, cx = x) or
-    // the compact copies of the allocation-free diagnostics (rs = 6, cx = k).
+    // x = 0, 1, 2, nx - 3, nx - 2, nx - 1) of row y is tf[y * 6 + k];
+    // fl_mid[x] for x in [0, nx).
     const double *tf, *tm, *fl_mid;
-    int64_t rs;
-    int cx[6];
 };
 
 // Diagnostics without the field planes: a fixed grid of at most
@@ -196,14 +193,16 @@ struct DiagNodeLaunch {
     double *fl_mid;    // [nx]
 };
 
+// Initial state of rows [y0, y0 + rows) of one cavity.
 struct InitLaunch {
     int storage;
     int cav_index;
     const void *cav;
     void *dst;
     void *sr;
-    const double *T_pcm;  // device, may be null
-    const double *T_mf;   // device, may be null
+    int y0, rows;
+    const double *T_pcm;  // device [rows][nx], may be null
+    const double *T_mf;   // device [rows][nx], may be null
 };
 
 hipError_t launch_step(const StepLaunch &L, hipStream_t s);
@@ -219,7 +218,6 @@ hipError_t launch_diag_nodes(const DiagNodeLaunch &L, int nx, int ny, hipStream_
 int diag_node_blocks(int nx, int ny);  // workgroups of launch_diag_nodes
 hipError_t launch_init(const InitLaunch &L, int nx, int ny, hipStream_t s);
 hipError_t launch_poke(int elem, void *ptr, double value, hipStream_t s);
-int macro_blocks(int nx, int ny);
 int bytes_per_node(int storage);  // stored bytes of one node's populations
 
 }  // namespace lbm

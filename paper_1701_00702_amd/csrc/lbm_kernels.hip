@@ -372,11 +372,13 @@ hipError_t launch_stepk(const Step2Launch &L, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Macroscopic fields and per-block diagnostics of one cavity.
+// Macroscopic fields of a range of rows of one cavity, and the reductions of
+// the diagnostics.
 // ---------------------------------------------------------------------------
 constexpr int MB = 256;  // threads per block of the diagnostics kernels
 
-int macro_blocks(int nx, int ny) { return (int)(((int64_t)nx * ny + MB - 1) / MB); }
+// Workgroups covering rows nodes of a row range, one node per thread.
+static int row_blocks(int nx, int rows) { return (int)(((int64_t)nx * rows + MB - 1) / MB); }
 
 // Block reduction of N doubles per thread (maxima for P_DT and P_U, sums
 // otherwise), in a fixed order, so the diagnostics are deterministic: a
@@ -412,43 +414,33 @@ __device__ __forceinline__ void block_reduce(double v[N], double (*sh)[MB / 64])
 template <class Lay, typename R, typename RH>
 __global__ __launch_bounds__(MB) void macro_kernel(const void *__restrict__ src,
                                                    const CavityConst<R> *__restrict__ cav, int ci,
-                                                   int raw, double *__restrict__ fields,
-                                                   double *__restrict__ partials) {
+                                                   int raw, int y0, int rows, double *__restrict__ fields) {
     const CavityConst<R> &c = cav[ci];
-    const int nx = c.nx, ny = c.ny;
-    const int64_t nn = (int64_t)nx * ny;
+    const int nx = c.nx;
+    const int64_t nn = (int64_t)nx * rows;
     const int64_t kk = (int64_t)blockIdx.x * MB + threadIdx.x;
-    double v[NPART];
+    if (kk >= nn) return;
+    double out[6], v[NPART];
 #pragma unroll
     for (int k = 0; k < NPART; ++k) v[k] = 0.0;
-    if (kk < nn) {
-        const int x = (int)(kk % nx), y = (int)(kk / nx);
-        double out[6];
-        macro_node<Lay, R, RH>(c, src, raw != 0, x, y, out, v);
+    macro_node<Lay, R, RH>(c, src, raw != 0, (int)(kk % nx), y0 + (int)(kk / nx), out, v);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) fields[q * nn + kk] = out[q];
-    }
-    __shared__ double sh[NPART][MB / 64];
-    block_reduce<NPART>(v, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NPART; ++k) partials[(int64_t)blockIdx.x * NPART + k] = v[k];
-    }
+    for (int q = 0; q < 6; ++q) fields[q * nn + kk] = out[q];
 }
 
 template <int ST>
-static hipError_t launch_macro_s(const MacroLaunch &L, hipStream_t s) {
+static hipError_t launch_macro_s(const MacroLaunch &L, int nx, hipStream_t s) {
     using Lay = typename LayoutOf<ST>::L;
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
-    hipLaunchKernelGGL((macro_kernel<Lay, R, RH>), dim3(L.nblocks), dim3(MB), 0, s, L.src,
-                       (const CavityConst<R> *)L.cav, L.cav_index, L.raw, L.fields, L.partials);
+    hipLaunchKernelGGL((macro_kernel<Lay, R, RH>), dim3(row_blocks(nx, L.rows)), dim3(MB), 0, s, L.src,
+                       (const CavityConst<R> *)L.cav, L.cav_index, L.raw, L.y0, L.rows, L.fields);
     return hipGetLastError();
 }
 
 hipError_t launch_macro(const MacroLaunch &L, int nx, int ny, hipStream_t s) {
-    if (L.nblocks != macro_blocks(nx, ny)) return hipErrorInvalidValue;
-    LBM_DISPATCH(L.storage, launch_macro_s, L, s)
+    if (L.y0 < 0 || L.rows < 1 || L.rows > ny - L.y0) return hipErrorInvalidValue;
+    LBM_DISPATCH(L.storage, launch_macro_s, L, nx, s)
 }
 
 // Final pass: fixed-order sums of the block partials, Nusselt numbers from
@@ -469,15 +461,14 @@ __global__ __launch_bounds__(MB) void diag_kernel(DiagLaunch L) {
         }
     }
     if (!L.periodic) {
-        const int *cx = L.cx;
         for (int y = 1 + t; y <= ny - 2; y += MB) {
-            const double *Tf = L.tf + (int64_t)y * L.rs;
-            const double *Tm = L.tm + (int64_t)y * L.rs;
-            const double dTf = (-3.0 * Tf[cx[0]] + 4.0 * Tf[cx[1]] - Tf[cx[2]]) * 0.5;
-            const double dTm = (-3.0 * Tm[cx[0]] + 4.0 * Tm[cx[1]] - Tm[cx[2]]) * 0.5;
+            const double *Tf = L.tf + (int64_t)y * 6;
+            const double *Tm = L.tm + (int64_t)y * 6;
+            const double dTf = (-3.0 * Tf[0] + 4.0 * Tf[1] - Tf[2]) * 0.5;
+            const double dTm = (-3.0 * Tm[0] + 4.0 * Tm[1] - Tm[2]) * 0.5;
             v[NPART + 0] += dTf;  // PCM-only gradient
-            const double cTf = (3.0 * Tf[cx[5]] - 4.0 * Tf[cx[4]] + Tf[cx[3]]) * 0.5;
-            const double cTm = (3.0 * Tm[cx[5]] - 4.0 * Tm[cx[4]] + Tm[cx[3]]) * 0.5;
+            const double cTf = (3.0 * Tf[5] - 4.0 * Tf[4] + Tf[3]) * 0.5;
+            const double cTm = (3.0 * Tm[5] - 4.0 * Tm[4] + Tm[3]) * 0.5;
             v[NPART + 1] += L.kf * dTf + L.km * dTm;
             v[NPART + 2] += L.kf * cTf + L.km * cTm;
         }
@@ -542,14 +533,15 @@ hipError_t launch_diag(const DiagLaunch &L, int nx, int ny, hipStream_t s) {
     return hipGetLastError();
 }
 
-// The per-node part of the diagnostics without the field planes: a fixed
-// grid strides over the cavity's nodes; each thread folds its nodes'
-// contributions (the same per-node values as macro_kernel) in node order,
-// the block reduction then runs as in macro_kernel.  The temperatures of
-// the three columns next to each vertical wall and the middle row's liquid
-// fraction go to compact arrays (tf/tm: [ny][6], column k for x = 0, 1, 2,
-// nx - 3, nx - 2, nx - 1; fl_mid: [nx]).  Every element of the partials and
-// of the compact arrays is written, so nothing needs clearing beforehand.
+// The per-node part of the diagnostics, without field planes: a fixed grid
+// strides over the cavity's nodes; each thread folds its nodes'
+// contributions (macro_node's per-node values) in node order, then a
+// fixed-order block reduction gives one partial per workgroup.  The
+// temperatures of the three columns next to each vertical wall and the
+// middle row's liquid fraction go to compact arrays (tf/tm: [ny][6], column
+// k for x = 0, 1, 2, nx - 3, nx - 2, nx - 1; fl_mid: [nx]).  Every element
+// of the partials and of the compact arrays is written, so nothing needs
+// clearing beforehand.
 int diag_node_blocks(int nx, int ny) {
     const int64_t b = ((int64_t)nx * ny + MB - 1) / MB;
     return (int)(b < LBM_DIAG_MAX_BLOCKS ? b : LBM_DIAG_MAX_BLOCKS);
@@ -611,32 +603,33 @@ hipError_t launch_diag_nodes(const DiagNodeLaunch &L, int nx, int ny, hipStream_
 // ---------------------------------------------------------------------------
 template <class Lay, typename R, typename RH>
 __global__ __launch_bounds__(MB) void init_kernel(const CavityConst<R> *__restrict__ cav, int ci,
-                                                  void *__restrict__ dst,
-                                                  R *__restrict__ sr, const double *__restrict__ T_pcm,
+                                                  void *__restrict__ dst, R *__restrict__ sr, int y0, int rows,
+                                                  const double *__restrict__ T_pcm,
                                                   const double *__restrict__ T_mf) {
     const CavityConst<R> &c = cav[ci];
-    const int nx = c.nx, ny = c.ny;
-    const int64_t nn = (int64_t)nx * ny;
+    const int nx = c.nx;
+    const int64_t nn = (int64_t)nx * rows;
     const int64_t kk = (int64_t)blockIdx.x * MB + threadIdx.x;
     if (kk >= nn) return;
     const double Tf = T_pcm ? T_pcm[kk] : c.T_init;
     const double Tm = T_mf ? T_mf[kk] : c.T_init;
-    init_node<Lay, R, RH>(c, dst, sr, (int)(kk % nx), (int)(kk / nx), Tf, Tm);
+    init_node<Lay, R, RH>(c, dst, sr, (int)(kk % nx), y0 + (int)(kk / nx), Tf, Tm);
 }
 
 template <int ST>
-static hipError_t launch_init_s(const InitLaunch &L, int nx, int ny, hipStream_t s) {
+static hipError_t launch_init_s(const InitLaunch &L, int nx, hipStream_t s) {
     using Lay = typename LayoutOf<ST>::L;
     using R = typename LayoutOf<ST>::R;
     using RH = typename LayoutOf<ST>::RH;
-    hipLaunchKernelGGL((init_kernel<Lay, R, RH>), dim3(macro_blocks(nx, ny)), dim3(MB), 0, s,
-                       (const CavityConst<R> *)L.cav, L.cav_index, L.dst, (R *)L.sr,
+    hipLaunchKernelGGL((init_kernel<Lay, R, RH>), dim3(row_blocks(nx, L.rows)), dim3(MB), 0, s,
+                       (const CavityConst<R> *)L.cav, L.cav_index, L.dst, (R *)L.sr, L.y0, L.rows,
                        L.T_pcm, L.T_mf);
     return hipGetLastError();
 }
 
 hipError_t launch_init(const InitLaunch &L, int nx, int ny, hipStream_t s) {
-    LBM_DISPATCH(L.storage, launch_init_s, L, nx, ny, s)
+    if (L.y0 < 0 || L.rows < 1 || L.rows > ny - L.y0) return hipErrorInvalidValue;
+    LBM_DISPATCH(L.storage, launch_init_s, L, nx, s)
 }
 
 // Overwrite one stored element (elem: 8 double, 4 float, 2 binary16,

@@ -110,6 +110,7 @@ def _load():
         "lbm_synchronize": ([H], st),
         "lbm_step_count": ([H], ctypes.c_int64),
         "lbm_fields": ([H, ctypes.c_int32, dp, dp, dp, dp, dp, dp], st),
+        "lbm_fields_rows": ([H, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp, dp, dp, dp, dp], st),
         "lbm_diagnostics": ([H, ctypes.c_int32, ctypes.POINTER(lbm_diag)], st),
         "lbm_diagnostics_noalloc": ([H, ctypes.c_int32, ctypes.POINTER(lbm_diag)], st),
         "lbm_get_lattice": ([H, ctypes.c_int32, ctypes.POINTER(lbm_lattice)], st),
@@ -135,7 +136,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("lbm_create", "lbm_create_batch", "lbm_workspace_bytes", "lbm_create_ext",
             "lbm_set_stream", "lbm_set_initial", "lbm_step", "lbm_step_per_cavity",
-            "lbm_synchronize", "lbm_step_count", "lbm_fields", "lbm_diagnostics", "lbm_diagnostics_noalloc",
+            "lbm_synchronize", "lbm_step_count", "lbm_fields", "lbm_fields_rows", "lbm_diagnostics",
+            "lbm_diagnostics_noalloc",
             "lbm_get_lattice", "lbm_lattice_of", "lbm_get_launch", "lbm_set_launch", "lbm_autotune", "lbm_save",
             "lbm_load", "lbm_copy_state", "lbm_debug_poke", "lbm_destroy", "lbm_last_error")
 
@@ -235,6 +237,13 @@ def lbm_fields(h: int, cavity: int, shape) -> dict:
     out = {k: np.empty((ny, nx)) for k in ("ux", "uy", "T_pcm", "T_mf", "f_l", "rho")}
     _check(_lib.lbm_fields(h, cavity, _dptr(out["ux"]), _dptr(out["uy"]), _dptr(out["T_pcm"]),
                            _dptr(out["T_mf"]), _dptr(out["f_l"]), _dptr(out["rho"])))
+    return out
+
+
+def lbm_fields_rows(h: int, cavity: int, nx: int, y0: int, rows: int) -> dict:
+    out = {k: np.empty((max(rows, 0), nx)) for k in ("ux", "uy", "T_pcm", "T_mf", "f_l", "rho")}
+    _check(_lib.lbm_fields_rows(h, cavity, y0, rows, _dptr(out["ux"]), _dptr(out["uy"]), _dptr(out["T_pcm"]),
+                                _dptr(out["T_mf"]), _dptr(out["f_l"]), _dptr(out["rho"])))
     return out
 
 
@@ -369,6 +378,9 @@ class Solver:
 
     def fields(self, c=0):
         return lbm_fields(self.h, c, self.shape(c))
+
+    def fields_rows(self, y0, rows, c=0):
+        return lbm_fields_rows(self.h, c, self.shape(c)[1], y0, rows)
 
     def diagnostics(self, c=0, allow_nonfinite=False):
         return lbm_diagnostics(self.h, c, allow_nonfinite)
