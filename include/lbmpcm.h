@@ -335,9 +335,15 @@ lbm_status lbm_autotune(lbm_handle *h, int32_t steps_per_trial, const char *cach
                         lbm_launch_config *chosen);
 
 /* Write / read the complete state (populations, previous-step sources,
- * wall tallies, step count) to a file; resuming is bit-exact.  lbm_load
- * requires a handle created with the same cavities and precision, and a
- * file of this library's format (LBM_EIO otherwise). */
+ * wall tallies, step count) to a file; resuming is bit-exact.  Both move the
+ * state through one host buffer of 64 MiB, so no host copy of the whole
+ * state is made.  lbm_load requires a handle created with the same cavities
+ * and precision (LBM_EINVAL otherwise) and a file of this library's format
+ * and of the exact length such a checkpoint has (LBM_EIO otherwise, found
+ * before the state is touched).  It reads the state into the buffers the
+ * next step would write and makes them current only when every byte has
+ * arrived, so a failed load leaves the handle's state as it was.  Both
+ * synchronise the stream. */
 lbm_status lbm_save(lbm_handle *h, const char *path);
 lbm_status lbm_load(lbm_handle *h, const char *path);
 

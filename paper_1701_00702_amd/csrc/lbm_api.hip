@@ -11,8 +11,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <new>
 #include <string>
 #include <vector>
+
+#include <sys/types.h>
 
 #include "../../include/lbmpcm.h"
 #include "lbm_internal.h"
@@ -1096,14 +1100,48 @@ struct CkptHeader {
 };
 }  // namespace
 
+namespace {
+// Checkpoints move device memory through one host buffer of at most this
+// many bytes, so saving or loading the largest states needs no host copy of
+// the state.
+constexpr size_t kCkptChunk = (size_t)64 << 20;
+
+// Device bytes [dev, dev + n) to f, through the host buffer tmp.
+bool write_device(FILE *f, const char *dev, size_t n, char *tmp, hipError_t &err) {
+    for (size_t o = 0; o < n; o += kCkptChunk) {
+        const size_t m = std::min(kCkptChunk, n - o);
+        err = hipMemcpy(tmp, dev + o, m, hipMemcpyDeviceToHost);
+        if (err != hipSuccess) return false;
+        if (fwrite(tmp, 1, m, f) != m) return false;
+    }
+    return true;
+}
+
+// n bytes of f to device memory at dev, through the host buffer tmp.
+bool read_device(FILE *f, char *dev, size_t n, char *tmp, hipError_t &err) {
+    for (size_t o = 0; o < n; o += kCkptChunk) {
+        const size_t m = std::min(kCkptChunk, n - o);
+        if (fread(tmp, 1, m, f) != m) return false;
+        err = hipMemcpy(dev + o, tmp, m, hipMemcpyHostToDevice);
+        if (err != hipSuccess) return false;
+    }
+    return true;
+}
+
+// Bytes of a checkpoint of handle h: header, parameters, initial energy and
+// mass, then the state buffer, the source plane and the wall tallies.
+int64_t ckpt_bytes(const lbm_handle *h) {
+    return (int64_t)sizeof(CkptHeader) + (int64_t)h->n * (sizeof(lbm_params) + 2 * sizeof(double)) +
+           h->pl.pop_bytes + h->pl.stride * (int64_t)real_size(h->st) + h->pl.slots * 2 * (int64_t)sizeof(double);
+}
+}  // namespace
+
 extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
     if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
     HIP_TRY(hipStreamSynchronize(h->stream));
-    const size_t rs = real_size(h->st);
-    std::vector<char> buf((size_t)h->pl.pop_bytes);
-    HIP_TRY(hipMemcpy(buf.data(), h->pop(h->cur), buf.size(), hipMemcpyDeviceToHost));
-    std::vector<char> sr((size_t)h->pl.stride * rs);
-    HIP_TRY(hipMemcpy(sr.data(), h->sr(h->cur), sr.size(), hipMemcpyDeviceToHost));
+    const size_t sr_bytes = (size_t)h->pl.stride * real_size(h->st);
+    std::unique_ptr<char[]> tmp(new (std::nothrow) char[kCkptChunk]);
+    if (!tmp) return fail(LBM_ENOMEM, "no host memory for the checkpoint buffer");
     std::vector<double> acc((size_t)h->pl.slots * 2);
     HIP_TRY(hipMemcpy(acc.data(), h->acc(), acc.size() * sizeof(double), hipMemcpyDeviceToHost));
     FILE *f = fopen(path, "wb");
@@ -1117,14 +1155,16 @@ extern "C" lbm_status lbm_save(lbm_handle *h, const char *path) {
     hd.step = h->step;
     hd.nodes = h->pl.nodes;
     hd.slots = h->pl.slots;
+    hipError_t err = hipSuccess;
     bool ok = fwrite(&hd, sizeof(hd), 1, f) == 1;
     ok = ok && fwrite(h->params.data(), sizeof(lbm_params), h->n, f) == (size_t)h->n;
     ok = ok && fwrite(h->E0.data(), sizeof(double), h->n, f) == (size_t)h->n;
     ok = ok && fwrite(h->M0.data(), sizeof(double), h->n, f) == (size_t)h->n;
-    ok = ok && fwrite(buf.data(), 1, buf.size(), f) == buf.size();
-    ok = ok && fwrite(sr.data(), 1, sr.size(), f) == sr.size();
+    ok = ok && write_device(f, (const char *)h->pop(h->cur), (size_t)h->pl.pop_bytes, tmp.get(), err);
+    ok = ok && write_device(f, (const char *)h->sr(h->cur), sr_bytes, tmp.get(), err);
     ok = ok && fwrite(acc.data(), sizeof(double), acc.size(), f) == acc.size();
     ok = (fclose(f) == 0) && ok;
+    if (err != hipSuccess) return fail(LBM_EDEVICE, "copy of the state for %s: %s", path, hipGetErrorString(err));
     if (!ok) return fail(LBM_EIO, "short write to %s", path);
     return LBM_OK;
 }
@@ -1144,25 +1184,51 @@ extern "C" lbm_status lbm_load(lbm_handle *h, const char *path) {
     }
     std::vector<lbm_params> ps(h->n);
     std::vector<double> E0(h->n), M0(h->n);
-    const size_t rs = real_size(h->st);
-    std::vector<char> buf((size_t)h->pl.pop_bytes), sr((size_t)h->pl.stride * rs);
-    std::vector<double> acc((size_t)h->pl.slots * 2);
     bool ok = fread(ps.data(), sizeof(lbm_params), h->n, f) == (size_t)h->n;
     ok = ok && fread(E0.data(), sizeof(double), h->n, f) == (size_t)h->n;
     ok = ok && fread(M0.data(), sizeof(double), h->n, f) == (size_t)h->n;
-    ok = ok && fread(buf.data(), 1, buf.size(), f) == buf.size();
-    ok = ok && fread(sr.data(), 1, sr.size(), f) == sr.size();
+    if (!ok) {
+        fclose(f);
+        return fail(LBM_EIO, "short read from %s", path);
+    }
+    for (int c = 0; c < h->n; ++c)
+        if (std::memcmp(&ps[c], &h->params[c], sizeof(lbm_params)) != 0) {
+            fclose(f);
+            return fail(LBM_EINVAL, "checkpoint %s: parameters of cavity %d differ", path, c);
+        }
+    // a file of the wrong length is refused before any device memory changes
+    const off_t here = ftello(f);
+    if (here < 0 || fseeko(f, 0, SEEK_END) != 0 || ftello(f) != (off_t)ckpt_bytes(h) ||
+        fseeko(f, here, SEEK_SET) != 0) {
+        fclose(f);
+        return fail(LBM_EIO, "%s is not %lld bytes long, as a checkpoint of these cavities is", path,
+                    (long long)ckpt_bytes(h));
+    }
+    std::unique_ptr<char[]> tmp(new (std::nothrow) char[kCkptChunk]);
+    if (!tmp) {
+        fclose(f);
+        return fail(LBM_ENOMEM, "no host memory for the checkpoint buffer");
+    }
+    // the state goes into the buffer pair the next step would write, and
+    // becomes current only once all of it has arrived: a failed load leaves
+    // the handle's state as it was
+    const hipError_t es = hipStreamSynchronize(h->stream);
+    if (es != hipSuccess) {
+        fclose(f);
+        return fail(LBM_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(es));
+    }
+    const int nb = 1 - h->cur;
+    const size_t sr_bytes = (size_t)h->pl.stride * real_size(h->st);
+    std::vector<double> acc((size_t)h->pl.slots * 2);
+    hipError_t err = hipSuccess;
+    ok = read_device(f, (char *)h->pop(nb), (size_t)h->pl.pop_bytes, tmp.get(), err);
+    ok = ok && read_device(f, (char *)h->sr(nb), sr_bytes, tmp.get(), err);
     ok = ok && fread(acc.data(), sizeof(double), acc.size(), f) == acc.size();
     fclose(f);
+    if (err != hipSuccess) return fail(LBM_EDEVICE, "copy of the state from %s: %s", path, hipGetErrorString(err));
     if (!ok) return fail(LBM_EIO, "short read from %s", path);
-    for (int c = 0; c < h->n; ++c)
-        if (std::memcmp(&ps[c], &h->params[c], sizeof(lbm_params)) != 0)
-            return fail(LBM_EINVAL, "checkpoint %s: parameters of cavity %d differ", path, c);
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    h->cur = 0;
-    HIP_TRY(hipMemcpy(h->pop(0), buf.data(), buf.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(h->sr(0), sr.data(), sr.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(h->acc(), acc.data(), acc.size() * sizeof(double), hipMemcpyHostToDevice));
+    h->cur = nb;
     h->step = hd.step;
     h->E0 = E0;
     h->M0 = M0;

@@ -180,9 +180,10 @@ def test_launch_shapes_bitwise_and_deterministic(lbm):
             assert d["flux_E"] == ref[1]["flux_E"]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f16split", "bf16split"])
-def test_save_resume_bitwise(lbm, prec):
-    p = W.scaled_cavity(W.case_c1()[0], 40, 36)
+@pytest.mark.parametrize("prec,n", [("f64", 40), ("f16split", 40), ("bf16split", 40), ("f32h64", 1024)])
+def test_save_resume_bitwise(lbm, prec, n):
+    # (the 1024^2 state, 117 MB, moves through the 64 MiB buffer in two parts)
+    p = W.scaled_cavity(W.case_c1()[0], n, n - 4)
     T_pcm, T_mf = W.initial_temperatures(p, 2)
     a = lbm.Solver(p, prec)
     a.set_initial(0, T_pcm, T_mf)
@@ -197,13 +198,18 @@ def test_save_resume_bitwise(lbm, prec):
         lbm.lbm_load(c.h, path)
         assert lbm.lbm_step_count(c.h) == 55
         c.step(65)
-        # a file of another format is refused and leaves the handle alone
-        bad = os.path.join(d, "bad.bin")
-        with open(path, "rb") as f, open(bad, "wb") as g:
-            g.write(b"LBMPCM01" + f.read()[8:])
-        with pytest.raises(lbm.LbmError) as e:
-            lbm.lbm_load(c.h, bad)
-        assert e.value.status == lbm.LBM_EIO
+        # a file of another format, a truncated one and one with bytes to
+        # spare are refused and leave the handle alone
+        with open(path, "rb") as f:
+            blob = f.read()
+        for k, data in enumerate((b"LBMPCM01" + blob[8:], blob[:-1], blob[:len(blob) // 2], blob + b"\0")):
+            bad = os.path.join(d, f"bad{k}.bin")
+            with open(bad, "wb") as g:
+                g.write(data)
+            with pytest.raises(lbm.LbmError) as e:
+                lbm.lbm_load(c.h, bad)
+            assert e.value.status == lbm.LBM_EIO
+        assert lbm.lbm_step_count(c.h) == 120
     assert np.array_equal(a.state().view(np.uint8), c.state().view(np.uint8))
     assert a.diagnostics()["flux_E"] == c.diagnostics()["flux_E"]
     for s in (a, b, c):
