@@ -135,6 +135,25 @@ def test_workspace_plan_sizes():
     assert lbm.state_bytes_per_node("f32h64", 5) == 80 and lbm.state_bytes_per_node("f64", 5) == 152
 
 
+def test_workspace_is_the_state_and_little_else():
+    """No per-node scratch beside the state: at 32768^2 the workspace is the
+    two state buffers and the two source planes plus under 1% (tile tables,
+    wall tallies, a staging area of 2^22 nodes x six doubles), so a 32768^2
+    FP32_H64 cavity fits one 288 GiB GPU."""
+    from paper_1701_00702_amd import lbm
+    n = 32768
+    p = W.scaled_cavity(W.case_c1()[0], n, n)
+    for prec, sr in (("f32h64", 4), ("f32", 4), ("f16split", 4), ("f16", 4), ("f64", 8)):
+        core = (2 * lbm.state_bytes_per_node(prec) + 2 * sr) * n * n
+        b = lbm.lbm_workspace_bytes(p, prec)
+        assert core <= b <= 1.01 * core, (prec, b, core)
+    assert lbm.lbm_workspace_bytes(p, "f32h64") < 0.9 * 288 * 2**30
+    # a small cavity stages all its rows at once: six doubles per node
+    q = W.case_c1()[0]
+    nq = q["nx"] * q["ny"]
+    assert lbm.lbm_workspace_bytes(q, "f32") >= (2 * 108 + 8 + 48) * nq
+
+
 def test_band_rows_validation_and_sizes():
     """Storage bands: 0 (automatic), at least max(32, ceil(2048 / nx) + 4)
     rows, or the whole cavity; a cut layout never needs less memory."""
