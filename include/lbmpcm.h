@@ -145,6 +145,21 @@ typedef struct lbm_params {
                                   max(32, ceil(2048 / nx) + 4), at most ny
                                   (larger values take ny).  Results do not
                                   depend on it.                               */
+    int32_t pcm_even_rates;    /* D2Q9 MRT thermal fields only.  0: the
+                                  enthalpy field's stress moments (p_xx,
+                                  p_xy; moments 7 and 8 of Eq. 13) relax at
+                                  the free rate zeta_v = 1.2 of Sec. III C;
+                                  1: at the rate of e and eps (Eq. 53, or
+                                  the given zeta_e), so every even
+                                  non-conserved moment of that field relaxes
+                                  at one rate and every odd one at
+                                  zeta_alpha.  With 1 the solid stays at the
+                                  melting temperature to rounding, the
+                                  property Sec. V C states for the scheme;
+                                  with 1.2 it undershoots by up to about 2%
+                                  of the temperature difference.  Other
+                                  lattices or BGK collisions: LBM_EINVAL
+                                  unless 0.                                   */
 } lbm_params;
 
 /* Derived lattice constants of one cavity (read-only view). */

@@ -26,7 +26,7 @@ PARAM_FIELDS = (
     "F_phi", "dp_over_L", "k_f", "cf_ref", "cm_ref", "J",
     "T_hot", "T_cold", "T_init", "T_solidus", "T_liquidus",
     "thermal_lattice", "thermal_collision", "varpi", "zeta_e", "wall_type", "wall_T", "L_char",
-    "solid_treatment", "band_rows",
+    "solid_treatment", "band_rows", "pcm_even_rates",
 )
 
 _DEFAULTS = dict(
@@ -51,6 +51,8 @@ _DEFAULTS = dict(
     L_char=0.0,             # <= 0: nx - 1 (periodic channel: ny - 1)
     solid_treatment=0,      # 0: volumetric scheme (Eq. 20); 1: bounce-back (Sec. V B)
     band_rows=0,            # storage only (GPU library): rows per state band, 0 automatic
+    pcm_even_rates=0,       # 0: enthalpy stress moments at zeta_v = 1.2 (Sec. III C);
+                            # 1: at the rate of e and eps (D2Q9 MRT only)
 )
 
 

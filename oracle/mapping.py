@@ -151,6 +151,11 @@ def lattice_params(p: dict) -> dict:
     if collision not in (0, 1):
         raise ValueError("thermal_collision must be 0 (MRT) or 1 (BGK)")
     zeta_e_given = float(p.get("zeta_e", 0.0))
+    even_rates = int(p.get("pcm_even_rates", 0))
+    if even_rates not in (0, 1):
+        raise ValueError("pcm_even_rates must be 0 or 1")
+    if even_rates and (collision == 1 or qt == 5):
+        raise ValueError("pcm_even_rates applies to D2Q9 MRT thermal fields only")
     solid_treatment = int(p.get("solid_treatment", 0))
     if solid_treatment not in (0, 1):
         raise ValueError("solid_treatment must be 0 (volumetric, Eq. 20) or 1 (bounce-back, Sec. V B)")
@@ -181,7 +186,11 @@ def lattice_params(p: dict) -> dict:
     else:
         ze = zeta_e_given if zeta_e_given > 0 else 2.0 - zeta_a
         if qt == 9:
-            zeta = [1.0, ze, ze, zeta_a, zeta_a, zeta_a, zeta_a, 1.2, 1.2]
+            # zeta_v = 1.2 (Sec. III C) for the stress moments, or on request
+            # the rate of e and eps, which puts every even non-conserved
+            # moment at one rate and every odd one at zeta_alpha
+            zv = ze if even_rates else 1.2
+            zeta = [1.0, ze, ze, zeta_a, zeta_a, zeta_a, zeta_a, zv, zv]
             eta = [1.0, 1.1, 1.1, eta_a, eta_a, eta_a, eta_a, 1.2, 1.2]
         else:
             zeta = [1.0, zeta_a, zeta_a, ze, ze, 1.0, 1.0, 1.0, 1.0]

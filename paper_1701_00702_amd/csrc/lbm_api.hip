@@ -1091,7 +1091,8 @@ extern "C" lbm_status lbm_autotune(lbm_handle *h, int32_t steps, const char *cac
 // ---------------------------------------------------------------------------
 namespace {
 // 02: the split 16-bit forms store their base times the axis weight
-const char kMagic[8] = {'L', 'B', 'M', 'P', 'C', 'M', '0', '2'};
+// 03: the parameters gain pcm_even_rates
+const char kMagic[8] = {'L', 'B', 'M', 'P', 'C', 'M', '0', '3'};
 
 struct CkptHeader {
     char magic[8];

@@ -99,6 +99,10 @@ inline lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l
     }
     if (p.thermal_collision == 1 && p.zeta_e > 0)
         return fail(LBM_EINVAL, "zeta_e cannot be set for BGK thermal collisions");
+    if (p.pcm_even_rates != 0 && p.pcm_even_rates != 1)
+        return fail(LBM_EINVAL, "pcm_even_rates must be 0 or 1");
+    if (p.pcm_even_rates == 1 && (p.thermal_collision == 1 || p.thermal_lattice == 5))
+        return fail(LBM_EINVAL, "pcm_even_rates applies to D2Q9 MRT thermal fields only");
     if (p.solid_treatment != 0 && p.solid_treatment != 1)
         return fail(LBM_EINVAL, "solid_treatment must be 0 (volumetric, Eq. 20) or 1 (bounce-back, Sec. V B)");
     l.solid = p.solid_treatment;
@@ -178,7 +182,8 @@ inline lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l
     // reference diffusivities with the thermal lattice's sound speed (Eq. A19
     // and after Eq. 51; App. B); free rates and zeta_e = zeta_eps =
     // 2 - zeta_alpha (Sec. III C, Eq. 53), or the given zeta_e (Sec. V D)
-    // for the pair zeta_e = zeta_eps.
+    // for the pair zeta_e = zeta_eps; on request the enthalpy field's stress
+    // moments take that rate too instead of zeta_v = 1.2 (pcm_even_rates).
     // D2Q5 rates in the moment order of Eq. (B1), entries 5..8 unused (1).
     // BGK (Sec. V A): every thermal rate 1/tau.
     const double s_v = 1.0 / (0.5 + 3.0 * l.nu_e);
@@ -195,7 +200,8 @@ inline lbm_status map_params(const lbm_params &p, lbm_precision prec, Lattice &l
             et[k] = k < l.qt ? ea : 1.0;
         }
     } else if (l.qt == 9) {
-        const double z9[9] = {1.0, ze, ze, za, za, za, za, 1.2, 1.2};
+        const double zv = p.pcm_even_rates == 1 ? ze : 1.2;
+        const double z9[9] = {1.0, ze, ze, za, za, za, za, zv, zv};
         const double e9[9] = {1.0, 1.1, 1.1, ea, ea, ea, ea, 1.2, 1.2};
         for (int k = 0; k < 9; ++k) {
             zt[k] = z9[k];

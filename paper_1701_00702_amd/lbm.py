@@ -55,7 +55,7 @@ class lbm_params(ctypes.Structure):
         ("varpi", ctypes.c_double), ("zeta_e", ctypes.c_double),
         ("wall_type", ctypes.c_int32 * 4), ("wall_T", ctypes.c_double * 4),
         ("L_char", ctypes.c_double), ("solid_treatment", ctypes.c_int32),
-        ("band_rows", ctypes.c_int32),
+        ("band_rows", ctypes.c_int32), ("pcm_even_rates", ctypes.c_int32),
     ]
 
 
@@ -161,8 +161,8 @@ def _params_array(params):
                 for k, v in enumerate(vals):
                     dst[k] = v
             else:
-                # the storage-only band_rows may be absent (automatic)
-                setattr(arr[i], name, p.get(name, 0) if name == "band_rows" else p[name])
+                # band_rows (storage only) and pcm_even_rates may be absent (0)
+                setattr(arr[i], name, p.get(name, 0) if name in ("band_rows", "pcm_even_rates") else p[name])
     return arr
 
 

@@ -99,6 +99,7 @@ bool read_job(Job &j) {
         else if (k == "L_char") ok = rd(p.L_char);
         else if (k == "solid_treatment") ok = ri(p.solid_treatment);
         else if (k == "band_rows") ok = ri(p.band_rows);
+        else if (k == "pcm_even_rates") ok = ri(p.pcm_even_rates);
         else if (k == "K") ok = scanf("%d", &j.K) == 1;
         else if (k == "shape") ok = scanf("%d", &j.shape) == 1;
         else if (k == "launches") ok = scanf("%d", &j.launches) == 1;

@@ -58,7 +58,8 @@ def test_host_mapping_matches_paper_and_oracle():
                                   dict(thermal_collision=1), dict(thermal_lattice=5, thermal_collision=1),
                                   dict(zeta_e=1.2), dict(thermal_lattice=5, zeta_e=0.6),
                                   dict(wall_type=(1, 2, 1, 0), wall_T=(-1.0, 0.0, 0.5, 0.0)),
-                                  dict(L_char=40.0), dict(solid_treatment=1)])
+                                  dict(L_char=40.0), dict(solid_treatment=1), dict(pcm_even_rates=1),
+                                  dict(pcm_even_rates=1, zeta_e=1.5)])
 def test_host_mapping_of_variants_matches_oracle(over):
     from paper_1701_00702_amd import lbm
     p = dict(W.case_c1()[0], **over)
@@ -89,7 +90,8 @@ def test_host_validation_rejects_bad_sets():
            dict(base, thermal_lattice=5, varpi=1.5), dict(base, thermal_collision=1, zeta_e=1.0),
            dict(base, wall_type=(3, 0, 0, 0)),
            dict(base, bc_x=1, wall_type=(1, 0, 0, 0)), dict(base, solid_treatment=2),
-           dict(base, nx=262145, ny=4)]
+           dict(base, nx=262145, ny=4), dict(base, pcm_even_rates=2),
+           dict(base, pcm_even_rates=1, thermal_lattice=5), dict(base, pcm_even_rates=1, thermal_collision=1)]
     for q in bad:
         with pytest.raises(lbm.LbmError) as e:
             lbm.lbm_lattice_of(q, "f32")

@@ -202,7 +202,7 @@ def test_save_resume_bitwise(lbm, prec, n):
         # spare are refused and leave the handle alone
         with open(path, "rb") as f:
             blob = f.read()
-        for k, data in enumerate((b"LBMPCM01" + blob[8:], blob[:-1], blob[:len(blob) // 2], blob + b"\0")):
+        for k, data in enumerate((b"LBMPCM02" + blob[8:], blob[:-1], blob[:len(blob) // 2], blob + b"\0")):
             bad = os.path.join(d, f"bad{k}.bin")
             with open(bad, "wb") as g:
                 g.write(data)

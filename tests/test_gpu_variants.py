@@ -4,8 +4,9 @@ through the C ABI against the FP64 CPU oracle, same seeded inputs):
 * D2Q5 thermal fields (Appendix B) in FP64, FP32 and FP32 with the FP64
   rest enthalpy population; ragged tiles, launch shapes, batches and
   checkpoints bit-identical;
-* BGK thermal collisions (Sec. V A) on both lattices, and the Sec. V D
-  zeta_e sweep;
+* BGK thermal collisions (Sec. V A) on both lattices, the Sec. V D
+  zeta_e sweep, and the enthalpy field's stress moments at the rate of e
+  and eps, with which the solid stays at the melting temperature (Sec. V C);
 * the conduction-induced solidification of Sec. IV A at the paper's
   200 x 200 grid and full length (Fo = 0.02), and mixed wall types;
 * the 8192^2 cavity on D2Q5 in the benchmark's launch shape, sampled
@@ -45,8 +46,9 @@ def _c1(**over):
 
 @pytest.mark.parametrize("over", [dict(thermal_lattice=5), dict(thermal_lattice=5, varpi=0.5),
                                   dict(thermal_collision=1), dict(thermal_lattice=5, thermal_collision=1),
-                                  dict(zeta_e=1.8), dict(thermal_lattice=5, zeta_e=0.6)],
-                         ids=["d2q5", "d2q5_varpi0.5", "d2q9_bgk", "d2q5_bgk", "d2q9_zeta1.8", "d2q5_zeta0.6"])
+                                  dict(zeta_e=1.8), dict(thermal_lattice=5, zeta_e=0.6), dict(pcm_even_rates=1)],
+                         ids=["d2q5", "d2q5_varpi0.5", "d2q9_bgk", "d2q5_bgk", "d2q9_zeta1.8", "d2q5_zeta0.6",
+                              "d2q9_even_rates"])
 def test_fp64_variant_parity_c1(lbm, over):
     p, seed = _c1(**over)
     g, gd, r, rd = run_pair(lbm, p, 2000, seed)
@@ -253,3 +255,31 @@ def test_bounce_back_channel_parity(lbm):
     e = field_errors(g, r, p)
     assert max(e.values()) < 1e-10, e
     assert np.all(g["ux"][:k + 1] == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32h64"])
+def test_solid_stays_at_the_melting_temperature(lbm, precision):
+    # Sec. V C: T_melt = T_init = T_cold, no interstitial exchange, the 41^2
+    # cavity of the Sec. IV B run to Fo = 0.002 in the default launch.  With
+    # the stress moments of the enthalpy field at the rate of e and eps
+    # (pcm_even_rates) the solid stays at the melting temperature (FP64: to
+    # rounding; FP32 populations: within their rounding); with the printed
+    # zeta_v = 1.2 it undershoots, as the oracle shows for both sets.
+    from oracle.mapping import lattice_params, steps_for_fourier
+    q = W.case_p1()[0]
+    p = dict(W.scaled_cavity(q, 41), Nu_i=0.0, T_solidus=0.0, T_liquidus=0.002)
+    steps = int(round(steps_for_fourier(lattice_params(p), 0.002)))
+    T0 = np.full((p["ny"], p["nx"]), p["T_init"])
+    low = {}
+    for even in (1, 0):
+        s = lbm.Solver(dict(p, pcm_even_rates=even), precision)
+        s.set_initial(0, T0, T0)
+        s.step(steps)
+        f = s.fields()
+        s.close()
+        assert f["f_l"].max() > 0.5 and (f["f_l"] < 1e-9).sum() > 0.2 * f["f_l"].size
+        low[even] = f["T_pcm"].min()
+    print(precision, steps, low)
+    bar = 1e-12 if precision == "f64" else 1e-6
+    assert low[1] >= p["T_solidus"] - bar, low
+    assert low[0] < p["T_solidus"] - 5e-4, low

@@ -64,7 +64,7 @@ def _job(p: dict, **kw) -> str:
         if isinstance(v, (list, tuple)):
             lines.append(f"{k} " + " ".join(repr(float(x)) if k == "wall_T" else str(int(x)) for x in v))
         elif k in ("nx", "ny", "bc_x", "gravity_axis", "thermal_lattice", "thermal_collision",
-                   "solid_treatment", "band_rows"):
+                   "solid_treatment", "band_rows", "pcm_even_rates"):
             lines.append(f"{k} {int(v)}")
         else:
             lines.append(f"{k} {float(v)!r}")

@@ -313,6 +313,10 @@ def test_solid_stays_at_the_melting_temperature():
     for p in (stefan, cavity):
         T_fs = p["T_solidus"]
         assert _min_solid_T(p, _two_rate) >= T_fs - 1e-12
+        # the library's option for this rate set (pcm_even_rates) maps to it
+        even = lattice_params(dict(p, pcm_even_rates=1))
+        assert even["zeta"] == _two_rate(lattice_params(p))["zeta"]
+        assert _min_solid_T(dict(p, pcm_even_rates=1)) >= T_fs - 1e-12
         assert _min_solid_T(dict(p, thermal_lattice=5)) >= T_fs - 1e-12
         assert _min_solid_T(p) < T_fs - 5e-4          # the printed zeta_v = 1.2
 
