@@ -80,6 +80,33 @@ def test_staged_rows(lbm):
         assert max(e.values()) < 1e-4, ((x0, y0), e)
 
 
+def test_staged_rows_in_a_batch(lbm):
+    # a batch whose largest cavity (2100 x 2100) sizes the staging area:
+    # the wide cavity goes in and out in two runs, the others (one wider
+    # than the first is tall, one narrow) in one; every cavity's fields,
+    # whole and by row ranges, are those of the same cavity run alone
+    ps = [W.scaled_cavity(_c1(), 2100, 2100), W.scaled_cavity(_c1(), 3000, 40), W.scaled_cavity(_c1(), 37, 900)]
+    Ts = [W.initial_temperatures(q, 50 + c) for c, q in enumerate(ps)]
+    b = lbm.Solver(ps, "f32h64")
+    for c, T in enumerate(Ts):
+        b.set_initial(c, *T)
+    b.step(4)
+    for c, (q, T) in enumerate(zip(ps, Ts)):
+        a = lbm.Solver(q, "f32h64")
+        a.set_initial(0, *T)
+        a.step(4)
+        ga, gb = a.fields(), b.fields(c)
+        a.close()
+        for k in ga:
+            assert np.array_equal(ga[k], gb[k]), (c, k)
+        ny = q["ny"]
+        for (y0, rows) in ((0, ny), (ny // 3, ny // 2), (ny - 1, 1)):
+            r = b.fields_rows(y0, rows, c)
+            for k in ga:
+                assert np.array_equal(r[k], ga[k][y0:y0 + rows]), (c, y0, rows, k)
+    b.close()
+
+
 def test_largest_timed_form_cavity(lbm):
     # 32768^2 nodes (1.07e9) in FP32_H64: 250 GB with both state buffers,
     # the largest power-of-two square of that form one GPU's memory holds.
