@@ -194,13 +194,17 @@ template <class Lay, typename R, typename RH, int TW, int TH, int NT, int K>
 __device__ __forceinline__ void stepk_advance(const void *__restrict__ src, void *__restrict__ dst,
                                               const R *__restrict__ sr_src, R *__restrict__ sr_dst,
                                               double *__restrict__ acc, const CavityConst<R> *__restrict__ cav,
-                                              const Tile2 &tl, void *lds_q, R *lds_sr) {
+                                              const Tile2 &tl, void *lds_q, R *lds_sr, float *lds_b) {
     using Sh = StepKShape<Lay, TW, TH, K>;
     const CavityConst<R> &c = cav[tl.cav];
     // NT >= NFIRST: each thread advances at most one node per update
     const int s = (int)threadIdx.x;
+    if constexpr (Sh::STAGE_BASE) {
+        stepk_stage_bases<Lay, R, TW, TH, K, NT>(c, tl, src, lds_b, s);
+        __syncthreads();
+    }
     if (s < Sh::LW * (tl.h + 2 * Sh::RING))
-        stepk_first<Lay, R, RH, TW, TH, K>(c, tl, src, sr_src, acc, lds_q, lds_sr, s);
+        stepk_first<Lay, R, RH, TW, TH, K>(c, tl, src, sr_src, acc, lds_q, lds_sr, lds_b, s);
     __syncthreads();
 #pragma unroll
     for (int j = K - 2; j >= 1; --j) {
@@ -220,7 +224,7 @@ __device__ __forceinline__ void stepk_advance(const void *__restrict__ src, void
 template <class Lay, typename R, int TW, int TH, int NT, int K>
 constexpr int stepk_waves_per_eu() {
     using Sh = StepKShape<Lay, TW, TH, K>;
-    constexpr int lds = (int)(Sh::LDS_BYTES + Sh::NSLOT * sizeof(R));
+    constexpr int lds = (int)(Sh::LDS_BYTES + Sh::NSLOT * sizeof(R) + Sh::BASE_BYTES);
     constexpr int by_lds = (160 * 1024) / lds;
     constexpr int by_waves = 32 / (NT / 64);
     constexpr int wgs = by_lds < by_waves ? by_lds : by_waves;
@@ -249,18 +253,20 @@ __global__ __launch_bounds__(NT, WPE) void stepk_kernel(const void *__restrict__
                                                    const CavityConst<R> *__restrict__ cav,
                                                    const Tile2 *__restrict__ tiles, int ntiles, int xcd_remap) {
     using Sh = StepKShape<Lay, TW, TH, K>;
-    static_assert(Sh::LDS_BYTES + Sh::NSLOT * sizeof(R) <= 65536, "tile exceeds 64 KiB of LDS");
+    static_assert(Sh::LDS_BYTES + Sh::NSLOT * sizeof(R) + Sh::BASE_BYTES <= 65536, "tile exceeds 64 KiB of LDS");
     static_assert(NT >= Sh::NFIRST && NT % 64 == 0, "one thread per node of the first update");
     __shared__ __align__(16) unsigned char lds_q[Sh::LDS_BYTES];
     __shared__ R lds_sr[Sh::NSLOT];
+    __shared__ float lds_b[Sh::STAGE_BASE ? 3 * Sh::NBASE : 1];
     const int b = remap_block(blockIdx.x, gridDim.x, xcd_remap);
     if (!LOOP) {
         if (b < ntiles)
-            stepk_advance<Lay, R, RH, TW, TH, NT, K>(src, dst, sr_src, sr_dst, acc, cav, tiles[b], lds_q, lds_sr);
+            stepk_advance<Lay, R, RH, TW, TH, NT, K>(src, dst, sr_src, sr_dst, acc, cav, tiles[b], lds_q, lds_sr,
+                                                     lds_b);
         return;
     }
     for (int t = b; t < ntiles; t += gridDim.x) {
-        stepk_advance<Lay, R, RH, TW, TH, NT, K>(src, dst, sr_src, sr_dst, acc, cav, tiles[t], lds_q, lds_sr);
+        stepk_advance<Lay, R, RH, TW, TH, NT, K>(src, dst, sr_src, sr_dst, acc, cav, tiles[t], lds_q, lds_sr, lds_b);
         __syncthreads();  // the next tile reuses the LDS
     }
 }

@@ -321,14 +321,23 @@ template <class ER>
 struct SplitT {
     static constexpr int QT = 9;
     static constexpr int bytes_per_node = 6 * 4 + 24 * 2;
+    // the stored base b of field f at node k
+    template <typename K>
+    LBM_HD static float load_base(const void *base, int64_t stride, int f, K k) {
+        return ld_stream(at((const float *)base + (int64_t)(2 * f + 1) * stride, k));
+    }
+    // moving population i (>= 1) of field f at node k, given that node's base
+    template <typename V, typename R, typename K>
+    LBM_HD static V load_moving(const void *base, int64_t stride, int f, int i, K k, V b, const CavityConst<R> &c) {
+        const uint16_t *Qp = (const uint16_t *)((const float *)base + 6 * stride);
+        const V r = (V)ER::dec(ld_stream(at(Qp + (int64_t)(8 * f + i - 1) * stride, k)));
+        return split_dec<V>(i, b, r, (V)c.inv_scale[f]);
+    }
     template <typename V, typename R, typename K>
     LBM_HD static V load(const void *base, int64_t stride, int f, int i, K k, const CavityConst<R> &c) {
         const float *P = (const float *)base;
         if (i == 0) return (V)ld_stream(at(P + (int64_t)(2 * f) * stride, k));
-        const V b = (V)ld_stream(at(P + (int64_t)(2 * f + 1) * stride, k));
-        const uint16_t *Qp = (const uint16_t *)(P + 6 * stride);
-        const V r = (V)ER::dec(ld_stream(at(Qp + (int64_t)(8 * f + i - 1) * stride, k)));
-        return split_dec<V>(i, b, r, (V)c.inv_scale[f]);
+        return load_moving<V>(base, stride, f, i, k, (V)load_base(base, stride, f, k), c);
     }
     template <typename V, typename R, typename K>
     LBM_HD static void store(void *base, int64_t stride, int f, const V q[9], V beta, K k,
@@ -1262,6 +1271,15 @@ struct PushLds<Plain<E64, false, 9>, 2> {
     static constexpr bool value = LBM_PUSH_F64_K2;
 };
 
+template <class Lay>
+struct IsSplitLayout {
+    static constexpr bool value = false;
+};
+template <class ER>
+struct IsSplitLayout<SplitT<ER>> {
+    static constexpr bool value = true;
+};
+
 template <class Lay, int TW, int TH, int K>
 struct StepKShape {
     static constexpr int QT = Lay::QT;
@@ -1274,6 +1292,15 @@ struct StepKShape {
     static constexpr int NSLOT = WW * WH;                // LDS plane stride
     using Codec = LdsCodec<Lay>;
     static constexpr size_t LDS_BYTES = Codec::bytes(NSLOT);
+    // Split layouts: every pull of the first update needs the base of the
+    // node it pulls from, so the workgroup first copies the bases of the
+    // pulled region (the first update's region and one more ring) into LDS
+    // and the pulls read them there instead of loading one base per pull.
+    static constexpr bool STAGE_BASE = IsSplitLayout<Lay>::value;
+    static constexpr int BW = TW + 2 * K, BH = TH + 2 * K;  // pulled region
+    static constexpr int BP = BW;  // row pitch of the staged bases
+    static constexpr int NBASE = STAGE_BASE ? BP * BH : 0;   // base plane stride
+    static constexpr size_t BASE_BYTES = (size_t)3 * NBASE * sizeof(float);
     static_assert(TH + 2 * K <= LBM_MIN_BAND_ROWS, "a tile's rows must span at most two bands");
 };
 
@@ -1316,12 +1343,74 @@ LBM_HD void lds_push(const CavityConst<R> &c, const Tile2 &tl, int x, int y, voi
     if (wx >= 0 && wx < Sh::WW && wy >= 0 && wy < Sh::WH) lds_sr[wy * Sh::WW + wx] = (R)srf;
 }
 
+// Split layouts, before the first update: thread t (of NT) copies the
+// bases of its nodes of the pulled region (unwrapped columns tl.x0 - K ..
+// tl.x0 + w + K - 1, rows tl.y0 - K .. tl.y0 + h + K - 1, at row pitch BP;
+// nodes outside the cavity are skipped, nothing reads them) into three LDS
+// planes of NBASE.
+template <class Lay, typename R, int TW, int TH, int K, int NT>
+LBM_HD void stepk_stage_bases(const CavityConst<R> &c, const Tile2 &tl, const void *src, float *lds_b, int t) {
+    using Sh = StepKShape<Lay, TW, TH, K>;
+    static_assert(Sh::STAGE_BASE, "split layouts only");
+    const int yb = tile_first_row<R, K>(c, tl);
+    const BandOrigin org = band_origin(c, yb);
+    const void *blk = band_block(c, src, yb / c.band_rows);
+    const int64_t stride = c.band_nodes;
+    for (int q = t; q < Sh::BP * (tl.h + 2 * K); q += NT) {
+        const int bx = q % Sh::BP;
+        if (bx >= tl.w + 2 * K) continue;
+        const int x = tl.x0 - K + bx, y = tl.y0 - K + q / Sh::BP;  // unwrapped
+        if (y < 0 || y >= c.ny) continue;
+        int xx = x;
+        if (c.periodic) xx = x < 0 ? x + c.nx : (x >= c.nx ? x - c.nx : x);
+        else if (x < 0 || x >= c.nx) continue;
+        LBM_HOST_CHECK(xx >= 0 && xx < c.nx && q < Sh::NBASE);
+        LBM_HOST_CHECK(y >= yb && y < yb + TH + 2 * K && y < org.y_next + c.band_rows);
+        const NodeRef k = org(xx, y);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) lds_b[f * Sh::NBASE + q] = Lay::load_base(blk, stride, f, k);
+    }
+}
+
+// Split layouts, first update: the pulls of the node at unwrapped column x
+// (wrapped xx) or of its wall partner, with the pulled nodes' bases from
+// the staged LDS copy; the same values as gather_at.
+template <class Lay, typename R, typename RH, int TW, int TH, int K>
+LBM_HD void gather_staged(const CavityConst<R> &c, const Tile2 &tl, const void *blk, const NodeGeom &g, int x,
+                          int xx, const BandOrigin &org, const float *lds_b, R qf[9], RH qg[9], R qh[9]) {
+    using Sh = StepKShape<Lay, TW, TH, K>;
+    const int64_t stride = c.band_nodes;
+    const int px = x + (g.sx - xx);  // partner column, unwrapped
+    const NodeRef rows[3] = {org.row(g.sy - 1), org.row(g.sy), org.row(g.sy + 1)};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int sx = g.sx - ex_of(i);
+        if (c.periodic) sx = sx < 0 ? sx + c.nx : (sx >= c.nx ? sx - c.nx : sx);
+        const NodeRef k = BandOrigin::at_row(rows[1 - ey_of(i)], sx);
+        if (i == 0) {
+            qf[0] = Lay::template load<R>(blk, stride, 0, 0, k, c);
+            qg[0] = Lay::template load<RH>(blk, stride, 1, 0, k, c);
+            qh[0] = Lay::template load<R>(blk, stride, 2, 0, k, c);
+            continue;
+        }
+        const int bi = (g.sy - ey_of(i) - (tl.y0 - K)) * Sh::BP + (px - ex_of(i) - (tl.x0 - K));
+        LBM_HOST_CHECK(px - ex_of(i) - (tl.x0 - K) >= 0 && px - ex_of(i) - (tl.x0 - K) < tl.w + 2 * K);
+        LBM_HOST_CHECK(g.sy - ey_of(i) - (tl.y0 - K) >= 0 && g.sy - ey_of(i) - (tl.y0 - K) < tl.h + 2 * K);
+        LBM_HOST_CHECK(bi >= 0 && bi < Sh::NBASE);
+        qf[i] = Lay::template load_moving<R>(blk, stride, 0, i, k, (R)lds_b[bi], c);
+        qg[i] = Lay::template load_moving<RH>(blk, stride, 1, i, k, (RH)lds_b[Sh::NBASE + bi], c);
+        qh[i] = Lay::template load_moving<R>(blk, stride, 2, i, k, (R)lds_b[2 * Sh::NBASE + bi], c);
+    }
+}
+
 // First update: slot s of R_(K-1) (row-major with the fixed pitch LW, so the
 // decode divides by a constant; columns beyond w + 2 RING idle).  Reads the
-// global state, writes the slot's post-collision populations and Sr_f to LDS.
+// global state (split layouts: with the bases staged in lds_b), writes the
+// slot's post-collision populations and Sr_f to LDS.
 template <class Lay, typename R, typename RH, int TW, int TH, int K>
 LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *src,
-                        const R *__restrict__ sr_src, double *__restrict__ acc, void *lds_q, R *lds_sr, int s) {
+                        const R *__restrict__ sr_src, double *__restrict__ acc, void *lds_q, R *lds_sr,
+                        const float *lds_b, int s) {
     using Sh = StepKShape<Lay, TW, TH, K>;
     constexpr int LW = Sh::LW, RG = Sh::RING;
     LBM_HOST_CHECK(s >= 0 && s < LW * (tl.h + 2 * RG) && s < Sh::NFIRST);
@@ -1341,7 +1430,12 @@ LBM_HD void stepk_first(const CavityConst<R> &c, const Tile2 &tl, const void *sr
     LBM_HOST_CHECK(g.sy + 1 < org.y_next + c.band_rows);
     R qf[9], qh[9];
     RH qg[9];
-    gather_at<Lay, R, RH, true>(c, band_block(c, src, yb / c.band_rows), g, xx, y, org, qf, qg, qh);
+    if constexpr (Sh::STAGE_BASE)
+        gather_staged<Lay, R, RH, TW, TH, K>(c, tl, band_block(c, src, yb / c.band_rows), g, x, xx, org, lds_b, qf,
+                                              qg, qh);
+    else
+        gather_at<Lay, R, RH, true>(c, band_block(c, src, yb / c.band_rows), g, xx, y, org, qf, qg, qh);
+    (void)lds_b;
     Thermo<RH> th;
     Macro<R> m;
     const R sr_prev = sr_src[flat_index(c, xx, y)];

@@ -182,10 +182,15 @@ void k_step_all(const CavityConst<typename LayoutOf<ST>::R> &c, State<ST> &S, in
         std::vector<unsigned char> lds(Sh::LDS_BYTES, 0xff);
         std::vector<R> lds_sr(Sh::NSLOT);
         std::memset(lds_sr.data(), 0xff, lds_sr.size() * sizeof(R));
+        std::vector<float> lds_b(Sh::STAGE_BASE ? 3 * Sh::NBASE : 1);
+        std::memset(lds_b.data(), 0xff, lds_b.size() * sizeof(float));
+        if constexpr (Sh::STAGE_BASE)
+            for (int t = 0; t < NT; ++t)
+                stepk_stage_bases<Lay, R, TW, TH, K, NT>(c, tl, S.pop[cur].data(), lds_b.data(), t);
         for (int s = 0; s < NT; ++s)
             if (s < Sh::LW * (tl.h + 2 * Sh::RING))
                 stepk_first<Lay, R, RH, TW, TH, K>(c, tl, S.pop[cur].data(), S.sr[cur].data(), S.acc.data(),
-                                                   lds.data(), lds_sr.data(), s);
+                                                   lds.data(), lds_sr.data(), lds_b.data(), s);
         for (int j = K - 2; j >= 1; --j) {
             std::vector<MidNode<R, RH>> nodes(NT);
             std::vector<char> act(NT, 0);
