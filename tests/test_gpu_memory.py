@@ -1,8 +1,8 @@
 """GPU checks of the memory plan: the staging area that lbm_set_initial and
 lbm_fields pass whole rows through (runs of at most 2^22 nodes, so no
-per-node copy of the fields sits beside the state), reading row ranges, and
-the largest square power-of-two cavity of the timed storage form that one
-GPU holds."""
+per-node copy of the fields sits beside the state), reading row ranges, the
+largest square power-of-two cavity of the timed storage form that one GPU
+holds, and the largest cavity the library accepts (just under 2^31 nodes)."""
 import numpy as np
 import pytest
 
@@ -27,14 +27,17 @@ def _c1():
 
 def _window_errors(p, T_pcm, T_mf, steps, windows, rows_of, w=48):
     """Oracle windows (with their light-cone masks) next to the GPU fields
-    that rows_of(y0, w) returns for rows [y0, y0 + w)."""
+    that rows_of(y0, w) returns for rows [y0, y0 + w); None for a
+    temperature array means T_init everywhere."""
     import oracle
     from test_gpu_parity import field_errors
     out = []
     for (x0, y0) in windows:
         o = oracle.Oracle(p, window=(x0, y0, w, w))
-        tm = np.full((w, w), float(p["T_init"])) if T_mf is None else T_mf[y0:y0 + w, x0:x0 + w]
-        o.set_initial(T_pcm[y0:y0 + w, x0:x0 + w], tm)
+        uniform = np.full((w, w), float(p["T_init"]))
+        tf = uniform if T_pcm is None else T_pcm[y0:y0 + w, x0:x0 + w]
+        tm = uniform if T_mf is None else T_mf[y0:y0 + w, x0:x0 + w]
+        o.set_initial(tf, tm)
         o.step(steps)
         r = o.fields()
         assert r["valid"].sum() > 100, (x0, y0)
@@ -153,3 +156,41 @@ def test_largest_timed_form_cavity(lbm):
     for (x0, y0), e in zip(windows, errs):
         assert max(e["T_pcm"], e["T_mf"], e["f_l"], e["rho"]) < 1e-5, ((x0, y0), e)
         assert max(e["ux"], e["uy"]) < 1e-4, ((x0, y0), e)
+
+
+def test_largest_accepted_cavity(lbm):
+    # 46336 x 46344 nodes, just under the 2^31 nodes one cavity may hold, in
+    # the FP16 offset form (117 B per node: a 251 GB workspace): node
+    # indices, tile tables and reductions at the top of their range.  The
+    # default launch for 9 steps from the uniform initial state; oracle
+    # windows at the walls and corners within that form's characterised
+    # error (its offsets round at 5e-4 relative each step); the
+    # allocation-free diagnostics refuse sides above their scratch.
+    import torch
+    nx, ny = 46336, 46344
+    assert ((nx + 63) // 64 * 64) * ny < 2**31 - 4096 and nx * ny > 2**31 - 2**17
+    p = dict(W.scaled_cavity(_c1(), nx, ny), L_char=127.0)
+    need = lbm.lbm_workspace_bytes(p, "f16")
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    print(f"workspace {need / 1e9:.1f} GB, device free {free / 1e9:.1f} of {total / 1e9:.1f} GB", flush=True)
+    if total < need * 1.05:
+        pytest.skip(f"the cavity needs a GPU with more than {need * 1.05 / 1e9:.0f} GB")
+    s = lbm.Solver(p, "f16")
+    assert lbm.lbm_get_launch(s.h)["steps_per_launch"] == 3
+    steps = 9
+    s.step(steps)
+    d = s.diagnostics()
+    assert d["nonfinite"] == 0 and d["liquid_fraction"] > 0
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_diagnostics_noalloc(s.h, 0)
+    assert e.value.status == lbm.LBM_EINVAL
+    w = 48
+    windows = [(0, 0), (0, ny // 2), (nx - w, ny - w), (nx // 2, 0), (nx - w, ny // 2), (0, ny - w)]
+    errs = _window_errors(p, None, None, steps, windows, lambda y0, w: s.fields_rows(y0, w))
+    s.close()
+    worst = {k: max(e[k] for e in errs) for k in errs[0]}
+    print(worst)
+    # measured: T_pcm 9.7e-5, T_mf 1.2e-4, f_l 6.1e-4, rho 1.4e-8, u 9.3e-5
+    assert worst["T_pcm"] < 2.5e-4 and worst["T_mf"] < 2.5e-4 and worst["f_l"] < 1.5e-3, worst
+    assert worst["rho"] < 1e-6 and worst["ux"] < 2.5e-4 and worst["uy"] < 2.5e-4, worst
