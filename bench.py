@@ -212,6 +212,43 @@ def cpu_baseline(params, seed, budget_s=15.0, side=1536):
             "host_cpu": model}
 
 
+def errors_vs_f64(f, d, rf, rd, dT) -> dict:
+    """Errors of fields f and diagnostics d against the FP64 ones (rf, rd):
+    liquid fraction, melt front (units of L) absolute, hot-wall Nu relative,
+    interior T in units of dT, f_l absolute, u over the largest FP64 speed."""
+    inner = (slice(1, -1), slice(1, -1))
+    umax = max(np.abs(rf["ux"]).max(), np.abs(rf["uy"]).max(), 1e-300)
+    return {
+        "liquid_fraction": abs(d["liquid_fraction"] - rd["liquid_fraction"]),
+        "x_front_mid": abs(d["x_front_mid"] - rd["x_front_mid"]),
+        "Nu_hot_rel": abs(d["Nu_hot"] - rd["Nu_hot"]) / max(abs(rd["Nu_hot"]), 1e-300),
+        "T_pcm": float(np.abs(f["T_pcm"] - rf["T_pcm"])[inner].max() / dT),
+        "T_mf": float(np.abs(f["T_mf"] - rf["T_mf"])[inner].max() / dT),
+        "f_l": float(np.abs(f["f_l"] - rf["f_l"])[inner].max()),
+        "u": float(max(np.abs(f["ux"] - rf["ux"]).max(), np.abs(f["uy"] - rf["uy"]).max()) / umax),
+    }
+
+
+def short_errors(lbm, p, seed, steps, forms) -> dict:
+    """The storage forms against FP64 on the same GPU after a short run (the
+    default launch of each form)."""
+    import lbm_workloads as W
+    T_pcm, T_mf = W.initial_temperatures(p, seed)
+    dT = p["T_hot"] - p["T_cold"]
+    ref, out = None, {}
+    for prec in ["f64"] + list(forms):
+        s = lbm.Solver(p, prec)
+        s.set_initial(0, T_pcm, T_mf)
+        s.step(steps)
+        f, d = s.fields(), s.diagnostics(allow_nonfinite=True)
+        s.close()
+        if ref is None:
+            ref = (f, d)
+        else:
+            out[prec] = errors_vs_f64(f, d, ref[0], ref[1], dT)
+    return out
+
+
 def accuracy(name: str) -> dict:
     """Full-length runs of the 1024^2 (FP32 forms, 200 000 steps) or the
     4096^2 (16-bit forms, 100 000 steps) cavity next to the FP64 path on the
@@ -248,18 +285,7 @@ def accuracy(name: str) -> dict:
         if ref is None:
             ref = (f, d)
         else:
-            rf, rd = ref
-            inner = (slice(1, -1), slice(1, -1))
-            umax = max(np.abs(rf["ux"]).max(), np.abs(rf["uy"]).max(), 1e-300)
-            row["error_vs_f64"] = {
-                "liquid_fraction": abs(d["liquid_fraction"] - rd["liquid_fraction"]),
-                "x_front_mid": abs(d["x_front_mid"] - rd["x_front_mid"]),
-                "Nu_hot_rel": abs(d["Nu_hot"] - rd["Nu_hot"]) / max(abs(rd["Nu_hot"]), 1e-300),
-                "T_pcm": float(np.abs(f["T_pcm"] - rf["T_pcm"])[inner].max() / dT),
-                "T_mf": float(np.abs(f["T_mf"] - rf["T_mf"])[inner].max() / dT),
-                "f_l": float(np.abs(f["f_l"] - rf["f_l"])[inner].max()),
-                "u": float(max(np.abs(f["ux"] - rf["ux"]).max(), np.abs(f["uy"] - rf["uy"]).max()) / umax),
-            }
+            row["error_vs_f64"] = errors_vs_f64(f, d, ref[0], ref[1], dT)
         out[prec] = row
         del f
     return {"accuracy": name, "nx": p["nx"], "ny": p["ny"], "steps": steps, "seed": seed,
@@ -451,6 +477,11 @@ def main():
         fp16["f16split_over_f32h64"] = fp16["f16split"]["MLUPS"] / fp16["f32h64"]["MLUPS"]
         for k, v in fp16["by_steps_per_launch"].items():
             v["f16split_over_f32"] = v["f16split"] / v["f32"]
+        # error against FP64: the same physics on 256^2 for 3000 steps (the
+        # full-length 4096^2 errors take minutes: bench.py --accuracy c4)
+        pe = W.scaled_cavity(workload("c4")[0][0], 256)
+        fp16["error_vs_f64"] = {"workload": "the 4096^2 physics on 256x256, 3000 steps, FP64 on the same GPU",
+                                "forms": short_errors(lbm, pe, workload("c4")[1], 3000, ("f16split", "f32h64", "f32"))}
         out["fp16_store_vs_fp32"] = fp16
 
     if args.forms:
