@@ -169,3 +169,40 @@ def test_band_rows_validation_and_sizes():
         with pytest.raises(lbm.LbmError) as e:
             lbm.lbm_workspace_bytes(dict(p, band_rows=bad), "f32")
         assert e.value.status == lbm.LBM_EINVAL
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of lbm_params, lbm_lattice, lbm_diag and
+    lbm_launch_config have the header's sizes and field offsets (a C99
+    program built against the header prints them; no library call)."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_1701_00702_amd import lbm
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"lbm_params": lbm.lbm_params, "lbm_lattice": lbm.lbm_lattice, "lbm_diag": lbm.lbm_diag,
+               "lbm_launch_config": lbm.lbm_launch_config}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lbmpcm.h"', "int main(void) {"]
+    for s, py in structs.items():
+        lines.append(f'    printf("{s} size %zu\\n", sizeof({s}));')
+        for name, _ in py._fields_:
+            lines.append(f'    printf("{s} {name} %zu\\n", offsetof({s}, {name}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        parts = line.split()
+        s, py = parts[0], structs[parts[0]]
+        if parts[1] == "size":
+            assert ctypes.sizeof(py) == int(parts[2]), line
+        else:
+            assert getattr(py, parts[1]).offset == int(parts[2]), line
+        seen += 1
+    assert seen == len(structs) + sum(len(py._fields_) for py in structs.values())

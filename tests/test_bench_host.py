@@ -55,3 +55,21 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_errors_against_fp64():
+    import numpy as np
+    ny, nx = 6, 7
+    rf = {k: np.zeros((ny, nx)) for k in ("T_pcm", "T_mf", "f_l", "ux", "uy", "rho")}
+    rf["ux"][2, 3] = 2.0
+    f = {k: v.copy() for k, v in rf.items()}
+    f["T_pcm"][0, 0] = 5.0          # a wall node: not counted
+    f["T_pcm"][3, 3] = 0.25
+    f["f_l"][1, 1] = 0.5
+    f["uy"][4, 4] = 0.1
+    rd = {"liquid_fraction": 0.2, "x_front_mid": 0.3, "Nu_hot": 4.0}
+    d = {"liquid_fraction": 0.25, "x_front_mid": 0.35, "Nu_hot": 5.0}
+    e = bench.errors_vs_f64(f, d, rf, rd, 0.5)
+    assert e["T_pcm"] == pytest.approx(0.5) and e["T_mf"] == 0.0 and e["f_l"] == pytest.approx(0.5)
+    assert e["u"] == pytest.approx(0.05) and e["Nu_hot_rel"] == pytest.approx(0.25)
+    assert e["liquid_fraction"] == pytest.approx(0.05) and e["x_front_mid"] == pytest.approx(0.05)
