@@ -206,3 +206,16 @@ def test_binding_structs_match_the_header_layout(tmp_path):
             assert getattr(py, parts[1]).offset == int(parts[2]), line
         seen += 1
     assert seen == len(structs) + sum(len(py._fields_) for py in structs.values())
+
+
+def test_lent_workspace_is_checked_before_any_device_call():
+    """lbm_create_ext refuses a NULL, short or misaligned workspace with
+    LBM_EINVAL before it touches the device (the pointers below are never
+    dereferenced)."""
+    from paper_1701_00702_amd import lbm
+    p = W.case_c1()[0]
+    need = lbm.lbm_workspace_bytes(p, "f32")
+    for ptr, size in ((0, need), (1 << 40, need - 1), ((1 << 40) + 128, need)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_create_ext([p], "f32", ptr, size, 0)
+        assert e.value.status == lbm.LBM_EINVAL, (ptr, size)
