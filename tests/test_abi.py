@@ -219,3 +219,42 @@ def test_lent_workspace_is_checked_before_any_device_call():
         with pytest.raises(lbm.LbmError) as e:
             lbm.lbm_create_ext([p], "f32", ptr, size, 0)
         assert e.value.status == lbm.LBM_EINVAL, (ptr, size)
+
+
+def test_every_entry_point_refuses_a_null_handle():
+    """Each call on a NULL handle returns LBM_EINVAL with a message and no
+    device call; lbm_destroy(NULL) is a no-op and lbm_step_count(NULL) is -1."""
+    import ctypes
+    from paper_1701_00702_amd import lbm
+    L = lbm._lib
+    d, lat, cfg = lbm.lbm_diag(), lbm.lbm_lattice(), lbm.lbm_launch_config()
+    buf = (ctypes.c_double * 4)()
+    dp = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+    calls = {
+        "lbm_set_stream": lambda: L.lbm_set_stream(None, None),
+        "lbm_set_initial": lambda: L.lbm_set_initial(None, 0, None, None),
+        "lbm_step": lambda: L.lbm_step(None, 1),
+        "lbm_step_per_cavity": lambda: L.lbm_step_per_cavity(None, 1),
+        "lbm_synchronize": lambda: L.lbm_synchronize(None),
+        "lbm_fields": lambda: L.lbm_fields(None, 0, dp, dp, dp, dp, dp, dp),
+        "lbm_fields_rows": lambda: L.lbm_fields_rows(None, 0, 0, 1, dp, dp, dp, dp, dp, dp),
+        "lbm_diagnostics": lambda: L.lbm_diagnostics(None, 0, ctypes.byref(d)),
+        "lbm_diagnostics_noalloc": lambda: L.lbm_diagnostics_noalloc(None, 0, ctypes.byref(d)),
+        "lbm_get_lattice": lambda: L.lbm_get_lattice(None, 0, ctypes.byref(lat)),
+        "lbm_get_launch": lambda: L.lbm_get_launch(None, ctypes.byref(cfg)),
+        "lbm_set_launch": lambda: L.lbm_set_launch(None, ctypes.byref(cfg)),
+        "lbm_autotune": lambda: L.lbm_autotune(None, 2, None, ctypes.byref(cfg)),
+        "lbm_save": lambda: L.lbm_save(None, b"/nonexistent/x"),
+        "lbm_load": lambda: L.lbm_load(None, b"/nonexistent/x"),
+        "lbm_copy_state": lambda: L.lbm_copy_state(None, 0, ctypes.cast(buf, ctypes.c_void_p), 32),
+        "lbm_debug_poke": lambda: L.lbm_debug_poke(None, 0, 1, 1, 0, 1, 0.0),
+    }
+    for name, call in calls.items():
+        assert call() == lbm.LBM_EINVAL, name
+        assert lbm.lbm_last_error(), name
+    assert L.lbm_destroy(None) == lbm.LBM_OK
+    assert L.lbm_step_count(None) == -1
+    missing = [n for n in lbm.EXPORTED if n not in calls and n not in (
+        "lbm_create", "lbm_create_batch", "lbm_workspace_bytes", "lbm_create_ext", "lbm_lattice_of",
+        "lbm_destroy", "lbm_step_count", "lbm_last_error")]
+    assert not missing, missing
